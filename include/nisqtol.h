@@ -1,0 +1,218 @@
+/*
+ * nisqtol.h -- C ABI of libnisqtol: Monte Carlo state-vector simulation of a
+ * quantum circuit under the Pauli error model on an AMD Instinct MI355X
+ * (gfx950), following ArsoNISQ (Brandhofer, Devitt, Polian; arXiv 2301.07264).
+ *
+ * The paper's framework takes a circuit, a success criterion and either a
+ * Pauli error rate (-> success probability) or a target success probability
+ * (-> tolerable error rate) (Sec. IV).  Its Monte Carlo branch simulates the
+ * circuit N times; after every one-qubit gate an X, Z or Y error happens with
+ * probabilities p_X, p_Z, p_Y, and after a two-qubit gate the same happens
+ * independently on each of its qubits (Sec. IV-B.2).  An error is an error
+ * gate appended after the gate (Sec. IV-B); Eq. 2 gives the single-qubit
+ * actions.  Success probability is the mean of the criterion over the
+ * simulated states (Sec. IV-C); the tolerable rate is where it meets the
+ * target (Sec. IV-D, Fig. 3).
+ *
+ * Conventions
+ *   - Amplitude k of an n-qubit state belongs to basis state |k>; qubit 0 is
+ *     the least-significant bit of k.  Amplitudes are interleaved complex:
+ *     NT_C64 = 2 x float per amplitude, NT_C128 = 2 x double.
+ *   - Error sites: one per qubit a gate touches, numbered in gate order and,
+ *     within a gate, in the order its qubits are listed (the k + 2m error
+ *     locations of Sec. IV-B.1).  "Error rate" p is per site; the uniform
+ *     model is p_X = p_Y = p_Z = p/3 (Sec. IV-D, Sec. V).
+ *   - Random draws: Philox4x64-10 (Salmon et al., SC'11), key = (seed,
+ *     circuit id), counter = (site, trajectory, 0, 0).  A site fires iff
+ *     word0 < floor((p_x+p_y+p_z) * 2^64) (always when the sum is >= 1); its
+ *     Pauli is X if word1 < floor(p_x/sum * 2^64), else Y if
+ *     word1 < floor((p_x+p_y)/sum * 2^64), else Z (a fraction >= 1 means
+ *     "always").  Rates are not part of the counter, so the fired sets of one
+ *     trajectory are nested across rates.
+ *   - Fidelity criterion: F = |<R|psi>|^2 / (<R|R><psi|psi>) against the
+ *     error-free final state R of the same precision; a trajectory succeeds
+ *     iff F >= tau (Sec. II criteria; Sec. IV-C).
+ *   - Results are a pure function of (circuit, error model, precision, seed,
+ *     trajectory range, tau): batching, tiling and the pass plan never change
+ *     which errors a trajectory sees.
+ *
+ * Errors: every call returns an nt_status; no C++ exception crosses the ABI.
+ * nt_last_error() returns a thread-local message for the last failure.
+ * Threading: one host thread at a time per context.  Host outputs are
+ * complete when a call returns; device outputs are ordered on the context's
+ * stream.
+ */
+#ifndef NISQTOL_H
+#define NISQTOL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum nt_status {
+  NT_OK = 0,
+  NT_ERR_INVALID_ARG = 1,      /* bad argument; nothing was changed */
+  NT_ERR_UNSUPPORTED = 2,      /* valid request this build cannot serve */
+  NT_ERR_OUT_OF_MEMORY = 3,    /* size check failed before any allocation, or an allocation failed */
+  NT_ERR_DEVICE = 4,           /* HIP runtime error; message carries hipGetErrorString */
+  NT_ERR_BUFFER_TOO_SMALL = 5, /* required size returned through the size argument */
+  NT_ERR_NOT_BRACKETED = 6     /* tolerable-rate search: target not inside [p_lo, p_hi] */
+} nt_status;
+
+/* Amplitude precision (nt_set_precision). */
+enum { NT_C64 = 1, NT_C128 = 2 };
+
+/* Gate kinds.  R_P(theta) = exp(-i theta P/2); U(a,b,c) = Rz(a) Ry(b) Rz(c)
+ * as one gate with one error site; CNOT lists (control, target); CP(phi)
+ * multiplies the |11> component by e^{i phi}; RZZ(g) = exp(-i g Z(x)Z/2);
+ * U1Q/U2Q take a caller matrix, row-major complex (re, im interleaved), the
+ * 4x4 one on local index b_q0 + 2*b_q1. */
+enum nt_gate_kind {
+  NT_H = 0, NT_X = 1, NT_Y = 2, NT_Z = 3, NT_S = 4, NT_T = 5,
+  NT_RX = 6, NT_RY = 7, NT_RZ = 8, NT_U = 9, NT_U1Q = 10,
+  NT_CNOT = 11, NT_CZ = 12, NT_CP = 13, NT_SWAP = 14, NT_RZZ = 15, NT_U2Q = 16,
+  NT_NUM_GATE_KINDS = 17
+};
+
+typedef struct nt_gate {
+  uint16_t kind;          /* enum nt_gate_kind */
+  uint8_t nq;             /* 1 or 2; must match the kind */
+  uint8_t pad;
+  int32_t q[2];           /* qubits; q[1] unused for one-qubit kinds */
+  double param[3];        /* angles (radians) as the kind requires */
+  const double *matrix;   /* U1Q: 8 doubles, U2Q: 32 doubles; else NULL */
+} nt_gate;
+
+typedef struct nt_ctx nt_ctx;
+typedef struct nt_circuit nt_circuit;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Opens HIP device `device`.  hip_stream: a hipStream_t to launch on (for
+ * example torch.cuda.current_stream().cuda_stream), or NULL to let the
+ * library create and own a default-priority stream.  Fails with
+ * NT_ERR_DEVICE when no device is present. */
+nt_status nt_create(nt_ctx **out, int device, void *hip_stream);
+
+/* Frees every library-owned device buffer and the owned stream. */
+void nt_destroy(nt_ctx *ctx);
+
+/* Error model (Sec. IV-B.2): after every gate, on each touched qubit, X with
+ * p_x, Y with p_y, Z with p_z.  Needs each >= 0 and p_x+p_y+p_z <= 1.
+ * Default: all zero. */
+nt_status nt_set_error_model(nt_ctx *ctx, double p_x, double p_y, double p_z);
+
+/* NT_C64 (float amplitudes; FP64 overlaps, norms and counts) or NT_C128.
+ * Default NT_C128. */
+nt_status nt_set_precision(nt_ctx *ctx, int prec);
+
+/* Upper bound on trajectories simulated concurrently (each holds one state
+ * vector in device memory).  0 = automatic (memory-bounded).  Does not change
+ * results. */
+nt_status nt_set_max_batch(nt_ctx *ctx, uint64_t max_batch);
+
+/* ---- circuits (host objects; ctx may be NULL) ---------------------------- */
+
+/* Copies gates[0..n_gates) after validating qubits (0 <= q < n, distinct for
+ * two-qubit kinds), kinds, arity and matrices.  1 <= n_qubits <= 32. */
+nt_status nt_circuit_load(nt_ctx *ctx, int n_qubits, const nt_gate *gates, int64_t n_gates,
+                          nt_circuit **out);
+
+/* Text format: "qubits <n>" then one gate per line, "NAME q0 [q1] [angles]",
+ * U1Q/U2Q followed by the row-major (re im) matrix entries; '#' comments. */
+nt_status nt_circuit_load_text(nt_ctx *ctx, const char *path, nt_circuit **out);
+
+void nt_circuit_free(nt_circuit *c);
+
+/* n qubits, G gates, S error sites (k + 2m, Sec. IV-B.1). */
+nt_status nt_circuit_info(const nt_circuit *c, int *n, int64_t *G, int64_t *S);
+
+/* Second Philox key word (default 0), so that many circuits under one seed
+ * draw independent errors. */
+nt_status nt_circuit_set_id(nt_circuit *c, uint64_t circuit_id);
+
+/* Host-only view of the gate-pass plan used for precision `prec`: number of
+ * HBM passes over a state vector per trajectory, LDS segments, and the
+ * local-tile width in qubits. */
+nt_status nt_plan_info(const nt_circuit *c, int prec, int *n_passes, int *n_segments,
+                       int *tile_qubits);
+
+/* Host-only export of that plan, for checking it: for each op in application
+ * order its gate index, pass and segment (arrays of n_gates); the local-qubit
+ * mask of each pass (n_passes) and the register-qubit mask of each segment
+ * (n_segments).  Any pointer may be NULL; sizes must match nt_plan_info. */
+nt_status nt_plan_export(const nt_circuit *c, int prec, int32_t *op_gate, int32_t *op_pass,
+                         int32_t *op_segment, uint64_t *pass_local_mask, uint64_t *segment_reg_mask);
+
+/* ---- Monte Carlo runs ------------------------------------------------------ */
+
+/* Runs trajectories [traj_begin, traj_begin + n_traj) under the current
+ * error model and precision and scores each against the error-free state
+ * (Sec. IV-B.2, IV-C).  fid_out: n_traj doubles, host or device memory, may
+ * be NULL.  count_out: number of trajectories with F >= tau (may be NULL).
+ * p_out: count / n_traj (may be NULL). */
+nt_status nt_run(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_begin,
+                 uint64_t n_traj, double tau, double *fid_out, uint64_t *count_out,
+                 double *p_out);
+
+/* Success probability at each uniform rate rates[r] (p/3 per Pauli) with the
+ * same trajectories [0, n_traj) at every rate.  p_out: R doubles (host).
+ * The context's error model is left unchanged. */
+nt_status nt_sweep(nt_ctx *ctx, const nt_circuit *c, const double *rates, int R, uint64_t seed,
+                   uint64_t n_traj, double tau, double *p_out);
+
+/* Tolerable uniform rate (Sec. IV-D, Monte Carlo branch, Fig. 3): bisection
+ * in log10(p) over [p_lo, p_hi] with the same trajectories [0, n_traj) at
+ * every probe.  Returns the first probe whose success probability is within
+ * tol of P_target, else the midpoint once p_hi/p_lo <= 1.001.
+ * NT_ERR_NOT_BRACKETED if P(p_lo) < P_target or P(p_hi) > P_target.
+ * *n_probes counts every Monte Carlo evaluation, including the two ends. */
+nt_status nt_tolerable_rate(nt_ctx *ctx, const nt_circuit *c, double P_target, double tol,
+                            double p_lo, double p_hi, uint64_t seed, uint64_t n_traj,
+                            double tau, double *p_star, int *n_probes);
+
+/* ---- parity and debug exports ---------------------------------------------- */
+
+/* Fired error sites of trajectories [traj_begin, traj_begin + n_traj) under
+ * the current error model, drawn on the device: CSR with offsets[n_traj+1]
+ * (host), sites (site index) and paulis (1 = X, 2 = Y, 3 = Z), in site order.
+ * cap = capacity of sites/paulis; NT_ERR_BUFFER_TOO_SMALL with the required
+ * total in *n_out when it is too small (offsets are still filled). */
+nt_status nt_sample_sites(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_begin,
+                          uint64_t n_traj, uint64_t *offsets, int32_t *sites, uint8_t *paulis,
+                          int64_t cap, int64_t *n_out);
+
+/* Final amplitudes of trajectory `traj` (current error model and precision).
+ * amps_out: host or device, len = 2^n amplitudes in the current precision. */
+nt_status nt_final_state(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj,
+                         void *amps_out, int64_t len);
+
+/* Error-free final state (the reference of the fidelity criterion). */
+nt_status nt_reference_state(nt_ctx *ctx, const nt_circuit *c, void *amps_out, int64_t len);
+
+/* ---- timing (HIP events on the context stream) ------------------------------ */
+
+/* When enabled, every gate-pass kernel launch is bracketed by HIP events on
+ * the context stream.  nt_timing_read returns, since the last reset, the
+ * number of pass launches, their summed duration (ms) and their summed
+ * algorithmic HBM bytes (each pass reads and writes every state once; the
+ * first pass only writes; the scoring pass reads the state and the
+ * reference).  Reading synchronizes the stream. */
+nt_status nt_timing_enable(nt_ctx *ctx, int enable);
+nt_status nt_timing_reset(nt_ctx *ctx);
+nt_status nt_timing_read(nt_ctx *ctx, int64_t *n_launches, double *ms_total, double *bytes_total,
+                         double *updates_total);
+
+/* Thread-local text of the last failure ("" if none). */
+const char *nt_last_error(void);
+
+/* Library version string. */
+const char *nt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NISQTOL_H */

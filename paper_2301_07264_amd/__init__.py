@@ -1,0 +1,312 @@
+"""Python binding of libnisqtol (MI355X / gfx950).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+library, which must have been built (``paper_2301_07264_amd.build.build()``).
+Importing this package does not load the library; the first call does, and
+fails loudly when it is missing.  There is no CPU fallback.
+
+The functions keep the C names (``nt_create``, ``nt_run``, ...) and signatures
+of include/nisqtol.h, with numpy arrays in place of pointers and exceptions in
+place of status codes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libnisqtol.so")
+
+NT_OK = 0
+NT_ERR_INVALID_ARG = 1
+NT_ERR_UNSUPPORTED = 2
+NT_ERR_OUT_OF_MEMORY = 3
+NT_ERR_DEVICE = 4
+NT_ERR_BUFFER_TOO_SMALL = 5
+NT_ERR_NOT_BRACKETED = 6
+STATUS_NAMES = {0: "NT_OK", 1: "NT_ERR_INVALID_ARG", 2: "NT_ERR_UNSUPPORTED", 3: "NT_ERR_OUT_OF_MEMORY",
+                4: "NT_ERR_DEVICE", 5: "NT_ERR_BUFFER_TOO_SMALL", 6: "NT_ERR_NOT_BRACKETED"}
+
+NT_C64 = 1
+NT_C128 = 2
+
+GATE_KIND = {
+    "H": 0, "X": 1, "Y": 2, "Z": 3, "S": 4, "T": 5, "RX": 6, "RY": 7, "RZ": 8, "U": 9,
+    "U1Q": 10, "CNOT": 11, "CZ": 12, "CP": 13, "SWAP": 14, "RZZ": 15, "U2Q": 16,
+}
+
+# Symbols declared in include/nisqtol.h.
+EXPORTED = [
+    "nt_create", "nt_destroy", "nt_set_error_model", "nt_set_precision", "nt_set_max_batch",
+    "nt_circuit_load", "nt_circuit_load_text", "nt_circuit_free", "nt_circuit_info",
+    "nt_circuit_set_id", "nt_plan_info", "nt_plan_export", "nt_run", "nt_sweep", "nt_tolerable_rate",
+    "nt_sample_sites", "nt_final_state", "nt_reference_state", "nt_timing_enable",
+    "nt_timing_reset", "nt_timing_read", "nt_last_error", "nt_version",
+]
+
+
+class nt_gate(C.Structure):
+    _fields_ = [("kind", C.c_uint16), ("nq", C.c_uint8), ("pad", C.c_uint8),
+                ("q", C.c_int32 * 2), ("param", C.c_double * 3), ("matrix", C.POINTER(C.c_double))]
+
+
+class NtError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libnisqtol.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libnisqtol.so not built ({LIB_PATH}); run paper_2301_07264_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    P, i32, i64, u64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_double
+    PP = C.POINTER(C.c_void_p)
+    sig = {
+        "nt_create": ([PP, i32, P], i32),
+        "nt_destroy": ([P], None),
+        "nt_set_error_model": ([P, dbl, dbl, dbl], i32),
+        "nt_set_precision": ([P, i32], i32),
+        "nt_set_max_batch": ([P, u64], i32),
+        "nt_circuit_load": ([P, i32, P, i64, PP], i32),
+        "nt_circuit_load_text": ([P, C.c_char_p, PP], i32),
+        "nt_circuit_free": ([P], None),
+        "nt_circuit_info": ([P, P, P, P], i32),
+        "nt_circuit_set_id": ([P, u64], i32),
+        "nt_plan_info": ([P, i32, P, P, P], i32),
+        "nt_plan_export": ([P, i32, P, P, P, P, P], i32),
+        "nt_run": ([P, P, u64, u64, u64, dbl, P, P, P], i32),
+        "nt_sweep": ([P, P, P, i32, u64, u64, dbl, P], i32),
+        "nt_tolerable_rate": ([P, P, dbl, dbl, dbl, dbl, u64, u64, dbl, P, P], i32),
+        "nt_sample_sites": ([P, P, u64, u64, u64, P, P, P, i64, P], i32),
+        "nt_final_state": ([P, P, u64, u64, P, i64], i32),
+        "nt_reference_state": ([P, P, P, i64], i32),
+        "nt_timing_enable": ([P, i32], i32),
+        "nt_timing_reset": ([P], i32),
+        "nt_timing_read": ([P, P, P, P, P], i32),
+        "nt_last_error": ([], C.c_char_p),
+        "nt_version": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != NT_OK:
+        msg = lib().nt_last_error().decode(errors="replace")
+        raise NtError(status, msg)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def nt_last_error() -> str:
+    return lib().nt_last_error().decode(errors="replace")
+
+
+def nt_version() -> str:
+    return lib().nt_version().decode()
+
+
+# ---- context -----------------------------------------------------------------
+
+def nt_create(device: int = 0, hip_stream: Optional[int] = None) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().nt_create(C.byref(h), device, C.c_void_p(hip_stream) if hip_stream else None))
+    return h
+
+
+def nt_destroy(ctx) -> None:
+    lib().nt_destroy(ctx)
+
+
+def nt_set_error_model(ctx, p_x: float, p_y: float, p_z: float) -> None:
+    _check(lib().nt_set_error_model(ctx, p_x, p_y, p_z))
+
+
+def nt_set_precision(ctx, prec: int) -> None:
+    _check(lib().nt_set_precision(ctx, prec))
+
+
+def nt_set_max_batch(ctx, max_batch: int) -> None:
+    _check(lib().nt_set_max_batch(ctx, max_batch))
+
+
+# ---- circuits ------------------------------------------------------------------
+
+class _GateArray:
+    """Keeps the nt_gate array and the matrices it points to alive."""
+
+    def __init__(self, circuit):
+        G = len(circuit.gates)
+        self.arr = (nt_gate * max(G, 1))()
+        self.mats = []
+        for i, g in enumerate(circuit.gates):
+            e = self.arr[i]
+            e.kind = GATE_KIND[g.name]
+            e.nq = len(g.qubits)
+            e.q[0] = g.qubits[0]
+            e.q[1] = g.qubits[1] if len(g.qubits) > 1 else -1
+            for j, v in enumerate(g.params):
+                e.param[j] = float(v)
+            if g.matrix is not None:
+                m = np.asarray(g.matrix, np.complex128).ravel()
+                buf = np.empty(2 * m.size, np.float64)
+                buf[0::2] = m.real
+                buf[1::2] = m.imag
+                self.mats.append(buf)
+                e.matrix = buf.ctypes.data_as(C.POINTER(C.c_double))
+        self.G = G
+
+
+def nt_circuit_load(ctx, circuit) -> C.c_void_p:
+    """Load a ``workloads.Circuit`` (gate list) into the library."""
+    ga = _GateArray(circuit)
+    h = C.c_void_p()
+    _check(lib().nt_circuit_load(ctx, circuit.n, C.cast(ga.arr, C.c_void_p), ga.G, C.byref(h)))
+    return h
+
+
+def nt_circuit_load_text(ctx, path: str) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().nt_circuit_load_text(ctx, path.encode(), C.byref(h)))
+    return h
+
+
+def nt_circuit_free(circ) -> None:
+    lib().nt_circuit_free(circ)
+
+
+def nt_circuit_info(circ) -> Tuple[int, int, int]:
+    n, G, S = C.c_int(), C.c_int64(), C.c_int64()
+    _check(lib().nt_circuit_info(circ, C.byref(n), C.byref(G), C.byref(S)))
+    return n.value, G.value, S.value
+
+
+def nt_circuit_set_id(circ, cid: int) -> None:
+    _check(lib().nt_circuit_set_id(circ, cid))
+
+
+def nt_plan_info(circ, prec: int) -> Tuple[int, int, int]:
+    a, b, c = C.c_int(), C.c_int(), C.c_int()
+    _check(lib().nt_plan_info(circ, prec, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def nt_plan_export(circ, prec: int):
+    """Dict with op_gate, op_pass, op_segment, pass_local_mask, segment_reg_mask."""
+    npass, nseg, _ = nt_plan_info(circ, prec)
+    _, G, _ = nt_circuit_info(circ)
+    og = np.zeros(max(G, 1), np.int32)
+    op = np.zeros(max(G, 1), np.int32)
+    osg = np.zeros(max(G, 1), np.int32)
+    pm = np.zeros(max(npass, 1), np.uint64)
+    sm = np.zeros(max(nseg, 1), np.uint64)
+    _check(lib().nt_plan_export(circ, prec, _ptr(og), _ptr(op), _ptr(osg), _ptr(pm), _ptr(sm)))
+    return {"op_gate": og[:G], "op_pass": op[:G], "op_segment": osg[:G],
+            "pass_local_mask": pm[:npass], "segment_reg_mask": sm[:nseg]}
+
+
+# ---- runs ----------------------------------------------------------------------
+
+def nt_run(ctx, circ, seed: int, traj_begin: int, n_traj: int, tau: float,
+           fid_out: Optional[np.ndarray] = None, fid_out_ptr: Optional[int] = None):
+    """Returns (count, p).  fid_out: host float64 array of n_traj, or
+    fid_out_ptr: a device pointer (e.g. torch tensor data_ptr())."""
+    cnt = C.c_uint64()
+    p = C.c_double()
+    if fid_out is not None:
+        assert fid_out.dtype == np.float64 and fid_out.size >= n_traj and fid_out.flags.c_contiguous
+        fp = _ptr(fid_out)
+    elif fid_out_ptr is not None:
+        fp = C.c_void_p(fid_out_ptr)
+    else:
+        fp = None
+    _check(lib().nt_run(ctx, circ, seed, traj_begin, n_traj, tau, fp, C.byref(cnt), C.byref(p)))
+    return cnt.value, p.value
+
+
+def nt_sweep(ctx, circ, rates: Sequence[float], seed: int, n_traj: int, tau: float) -> np.ndarray:
+    r = np.ascontiguousarray(rates, np.float64)
+    out = np.zeros(len(r), np.float64)
+    _check(lib().nt_sweep(ctx, circ, _ptr(r), len(r), seed, n_traj, tau, _ptr(out)))
+    return out
+
+
+def nt_tolerable_rate(ctx, circ, P_target: float, tol: float, p_lo: float, p_hi: float, seed: int,
+                      n_traj: int, tau: float) -> Tuple[float, int]:
+    ps = C.c_double()
+    npb = C.c_int()
+    _check(lib().nt_tolerable_rate(ctx, circ, P_target, tol, p_lo, p_hi, seed, n_traj, tau,
+                                   C.byref(ps), C.byref(npb)))
+    return ps.value, npb.value
+
+
+def nt_sample_sites(ctx, circ, seed: int, traj_begin: int, n_traj: int, cap: Optional[int] = None):
+    """Returns (offsets[n_traj+1], sites, paulis) drawn on the device."""
+    offsets = np.zeros(n_traj + 1, np.uint64)
+    n_out = C.c_int64()
+    if cap is None:
+        _, _, S = nt_circuit_info(circ)
+        cap = max(16, n_traj * 4 + 64)
+    sites = np.zeros(max(cap, 1), np.int32)
+    paulis = np.zeros(max(cap, 1), np.uint8)
+    st = lib().nt_sample_sites(ctx, circ, seed, traj_begin, n_traj, _ptr(offsets), _ptr(sites),
+                               _ptr(paulis), cap, C.byref(n_out))
+    if st == NT_ERR_BUFFER_TOO_SMALL:
+        need = n_out.value
+        sites = np.zeros(max(need, 1), np.int32)
+        paulis = np.zeros(max(need, 1), np.uint8)
+        st = lib().nt_sample_sites(ctx, circ, seed, traj_begin, n_traj, _ptr(offsets), _ptr(sites),
+                                   _ptr(paulis), need, C.byref(n_out))
+    _check(st)
+    return offsets, sites[:n_out.value].copy(), paulis[:n_out.value].copy()
+
+
+def _state_buffer(circ, prec):
+    n, _, _ = nt_circuit_info(circ)
+    dt = np.complex64 if prec == NT_C64 else np.complex128
+    return np.zeros(1 << n, dt)
+
+
+def nt_final_state(ctx, circ, seed: int, traj: int, prec: int) -> np.ndarray:
+    out = _state_buffer(circ, prec)
+    _check(lib().nt_final_state(ctx, circ, seed, traj, _ptr(out), out.size))
+    return out
+
+
+def nt_reference_state(ctx, circ, prec: int) -> np.ndarray:
+    out = _state_buffer(circ, prec)
+    _check(lib().nt_reference_state(ctx, circ, _ptr(out), out.size))
+    return out
+
+
+def nt_timing_enable(ctx, enable: bool) -> None:
+    _check(lib().nt_timing_enable(ctx, 1 if enable else 0))
+
+
+def nt_timing_reset(ctx) -> None:
+    _check(lib().nt_timing_reset(ctx))
+
+
+def nt_timing_read(ctx):
+    """(launches, ms_total, algorithmic_bytes_total, updates_total)."""
+    n = C.c_int64()
+    ms, by, up = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().nt_timing_read(ctx, C.byref(n), C.byref(ms), C.byref(by), C.byref(up)))
+    return n.value, ms.value, by.value, up.value

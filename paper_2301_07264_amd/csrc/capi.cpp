@@ -1,0 +1,321 @@
+// C ABI of libnisqtol (declared in include/nisqtol.h).  Every entry point
+// validates its arguments, converts internal errors into nt_status codes and
+// records a thread-local message; no exception crosses the boundary.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "engine.hpp"
+
+struct nt_ctx {
+  nt::Ctx *impl;
+};
+struct nt_circuit {
+  nt::Circuit *impl;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+nt_status fail(nt_status s, const std::string &m) {
+  g_last_error = m;
+  return s;
+}
+
+template <typename F>
+nt_status guard(F &&f) {
+  try {
+    f();
+    g_last_error.clear();
+    return NT_OK;
+  } catch (const nt::Error &e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc &) {
+    return fail(NT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (const std::exception &e) {
+    return fail(NT_ERR_DEVICE, e.what());
+  } catch (...) {
+    return fail(NT_ERR_DEVICE, "unknown error");
+  }
+}
+
+bool valid_prob(double p) { return std::isfinite(p) && p >= 0.0 && p <= 1.0; }
+
+}  // namespace
+
+extern "C" {
+
+const char *nt_last_error(void) { return g_last_error.c_str(); }
+
+const char *nt_version(void) { return "nisqtol 0.1 (gfx950)"; }
+
+nt_status nt_create(nt_ctx **out, int device, void *hip_stream) {
+  if (!out) return fail(NT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  return guard([&] {
+    nt::Ctx *c = new nt::Ctx(device, hip_stream);
+    *out = new nt_ctx{c};
+  });
+}
+
+void nt_destroy(nt_ctx *ctx) {
+  if (!ctx) return;
+  try {
+    delete ctx->impl;
+  } catch (...) {
+  }
+  delete ctx;
+}
+
+nt_status nt_set_error_model(nt_ctx *ctx, double px, double py, double pz) {
+  if (!ctx) return fail(NT_ERR_INVALID_ARG, "ctx is NULL");
+  if (!valid_prob(px) || !valid_prob(py) || !valid_prob(pz))
+    return fail(NT_ERR_INVALID_ARG, "each Pauli probability must be finite and in [0, 1]");
+  if (px + py + pz > 1.0) return fail(NT_ERR_INVALID_ARG, "p_x + p_y + p_z must be <= 1");
+  ctx->impl->px = px;
+  ctx->impl->py = py;
+  ctx->impl->pz = pz;
+  g_last_error.clear();
+  return NT_OK;
+}
+
+nt_status nt_set_precision(nt_ctx *ctx, int prec) {
+  if (!ctx) return fail(NT_ERR_INVALID_ARG, "ctx is NULL");
+  if (prec != NT_C64 && prec != NT_C128) return fail(NT_ERR_INVALID_ARG, "precision must be NT_C64 or NT_C128");
+  ctx->impl->prec = prec;
+  g_last_error.clear();
+  return NT_OK;
+}
+
+nt_status nt_set_max_batch(nt_ctx *ctx, uint64_t max_batch) {
+  if (!ctx) return fail(NT_ERR_INVALID_ARG, "ctx is NULL");
+  if (max_batch > (1ull << 31)) return fail(NT_ERR_INVALID_ARG, "max_batch too large");
+  ctx->impl->max_batch = max_batch;
+  g_last_error.clear();
+  return NT_OK;
+}
+
+nt_status nt_circuit_load(nt_ctx *ctx, int n_qubits, const nt_gate *gates, int64_t n_gates, nt_circuit **out) {
+  (void)ctx;
+  if (!out) return fail(NT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  return guard([&] { *out = new nt_circuit{nt::load_circuit(n_qubits, gates, n_gates)}; });
+}
+
+nt_status nt_circuit_load_text(nt_ctx *ctx, const char *path, nt_circuit **out) {
+  (void)ctx;
+  if (!out) return fail(NT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  return guard([&] { *out = new nt_circuit{nt::load_circuit_text(path)}; });
+}
+
+void nt_circuit_free(nt_circuit *c) {
+  if (!c) return;
+  delete c->impl;
+  delete c;
+}
+
+nt_status nt_circuit_info(const nt_circuit *c, int *n, int64_t *G, int64_t *S) {
+  if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
+  if (n) *n = c->impl->n;
+  if (G) *G = (int64_t)c->impl->gates.size();
+  if (S) *S = c->impl->S;
+  g_last_error.clear();
+  return NT_OK;
+}
+
+nt_status nt_circuit_set_id(nt_circuit *c, uint64_t cid) {
+  if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
+  c->impl->cid = cid;
+  g_last_error.clear();
+  return NT_OK;
+}
+
+nt_status nt_plan_info(const nt_circuit *c, int prec, int *n_passes, int *n_segments, int *tile_qubits) {
+  if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
+  if (prec != NT_C64 && prec != NT_C128) return fail(NT_ERR_INVALID_ARG, "precision must be NT_C64 or NT_C128");
+  return guard([&] {
+    int L, R, cfix;
+    nt::plan_for_precision(*c->impl, prec, &L, &R, &cfix);
+    nt::Plan P = nt::make_plan(*c->impl, L, R, cfix);
+    if (n_passes) *n_passes = (int)P.passes.size();
+    if (n_segments) *n_segments = (int)P.segs.size();
+    if (tile_qubits) *tile_qubits = P.L;
+  });
+}
+
+nt_status nt_plan_export(const nt_circuit *c, int prec, int32_t *op_gate, int32_t *op_pass, int32_t *op_segment,
+                         uint64_t *pass_local_mask, uint64_t *segment_reg_mask) {
+  if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
+  if (prec != NT_C64 && prec != NT_C128) return fail(NT_ERR_INVALID_ARG, "precision must be NT_C64 or NT_C128");
+  return guard([&] {
+    int L, R, cfix;
+    nt::plan_for_precision(*c->impl, prec, &L, &R, &cfix);
+    nt::Plan P = nt::make_plan(*c->impl, L, R, cfix);
+    for (size_t p = 0; p < P.passes.size(); ++p) {
+      const nt::Pass &ps = P.passes[p];
+      if (pass_local_mask) pass_local_mask[p] = ps.local_mask;
+      for (int s = ps.seg_begin; s < ps.seg_end; ++s) {
+        const nt::Segment &sg = P.segs[s];
+        uint64_t m = 0;
+        for (int q : sg.reg_q) m |= 1ull << q;
+        if (segment_reg_mask) segment_reg_mask[s] = m;
+        for (int o = sg.op_begin; o < sg.op_end; ++o) {
+          if (op_gate) op_gate[o] = P.ops[o].gate;
+          if (op_pass) op_pass[o] = (int32_t)p;
+          if (op_segment) op_segment[o] = s;
+        }
+      }
+    }
+  });
+}
+
+static nt_status check_run_args(nt_ctx *ctx, const nt_circuit *c, double tau) {
+  if (!ctx) return fail(NT_ERR_INVALID_ARG, "ctx is NULL");
+  if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
+  if (!std::isfinite(tau)) return fail(NT_ERR_INVALID_ARG, "tau must be finite");
+  return NT_OK;
+}
+
+nt_status nt_run(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_begin, uint64_t n_traj,
+                 double tau, double *fid_out, uint64_t *count_out, double *p_out) {
+  nt_status s = check_run_args(ctx, c, tau);
+  if (s) return s;
+  if (n_traj == 0) return fail(NT_ERR_INVALID_ARG, "n_traj must be > 0");
+  return guard([&] {
+    uint64_t cnt = 0;
+    ctx->impl->run(*c->impl, seed, traj_begin, n_traj, tau, fid_out, &cnt);
+    if (count_out) *count_out = cnt;
+    if (p_out) *p_out = (double)cnt / (double)n_traj;
+  });
+}
+
+nt_status nt_sweep(nt_ctx *ctx, const nt_circuit *c, const double *rates, int R, uint64_t seed, uint64_t n_traj,
+                   double tau, double *p_out) {
+  nt_status s = check_run_args(ctx, c, tau);
+  if (s) return s;
+  if (R < 0 || (R > 0 && (!rates || !p_out))) return fail(NT_ERR_INVALID_ARG, "bad rates / p_out");
+  if (n_traj == 0) return fail(NT_ERR_INVALID_ARG, "n_traj must be > 0");
+  for (int r = 0; r < R; ++r)
+    if (!valid_prob(rates[r])) return fail(NT_ERR_INVALID_ARG, "rates must be in [0, 1]");
+  return guard([&] {
+    nt::Ctx &cx = *ctx->impl;
+    const double spx = cx.px, spy = cx.py, spz = cx.pz;
+    try {
+      for (int r = 0; r < R; ++r) {
+        const double p3 = rates[r] / 3.0;
+        cx.px = cx.py = cx.pz = p3;
+        uint64_t cnt = 0;
+        cx.run(*c->impl, seed, 0, n_traj, tau, nullptr, &cnt);
+        p_out[r] = (double)cnt / (double)n_traj;
+      }
+    } catch (...) {
+      cx.px = spx; cx.py = spy; cx.pz = spz;
+      throw;
+    }
+    cx.px = spx; cx.py = spy; cx.pz = spz;
+  });
+}
+
+nt_status nt_tolerable_rate(nt_ctx *ctx, const nt_circuit *c, double P_target, double tol, double p_lo,
+                            double p_hi, uint64_t seed, uint64_t n_traj, double tau, double *p_star,
+                            int *n_probes) {
+  nt_status s = check_run_args(ctx, c, tau);
+  if (s) return s;
+  if (!p_star) return fail(NT_ERR_INVALID_ARG, "p_star is NULL");
+  if (!(P_target >= 0 && P_target <= 1) || !(tol >= 0)) return fail(NT_ERR_INVALID_ARG, "bad P_target / tol");
+  if (!(p_lo > 0) || !(p_hi <= 1) || !(p_lo < p_hi)) return fail(NT_ERR_INVALID_ARG, "need 0 < p_lo < p_hi <= 1");
+  if (n_traj == 0) return fail(NT_ERR_INVALID_ARG, "n_traj must be > 0");
+  int probes = 0;
+  bool bracketed = true;
+  nt_status st = guard([&] {
+    nt::Ctx &cx = *ctx->impl;
+    const double spx = cx.px, spy = cx.py, spz = cx.pz;
+    auto P_at = [&](double p) {
+      cx.px = cx.py = cx.pz = p / 3.0;
+      uint64_t cnt = 0;
+      cx.run(*c->impl, seed, 0, n_traj, tau, nullptr, &cnt);
+      ++probes;
+      return (double)cnt / (double)n_traj;
+    };
+    try {
+      const double Plo = P_at(p_lo), Phi = P_at(p_hi);
+      if (Plo < P_target || Phi > P_target) {
+        bracketed = false;
+      } else {
+        double lo = std::log10(p_lo), hi = std::log10(p_hi);
+        for (;;) {
+          const double mid = 0.5 * (lo + hi);
+          const double pm = std::pow(10.0, mid);
+          if (std::pow(10.0, hi - lo) <= 1.001) { *p_star = pm; break; }
+          const double P = P_at(pm);
+          if (std::fabs(P - P_target) <= tol) { *p_star = pm; break; }
+          if (P > P_target) lo = mid; else hi = mid;
+        }
+      }
+    } catch (...) {
+      cx.px = spx; cx.py = spy; cx.pz = spz;
+      throw;
+    }
+    cx.px = spx; cx.py = spy; cx.pz = spz;
+  });
+  if (n_probes) *n_probes = probes;
+  if (st) return st;
+  if (!bracketed) return fail(NT_ERR_NOT_BRACKETED, "target success probability not bracketed by [p_lo, p_hi]");
+  return NT_OK;
+}
+
+nt_status nt_sample_sites(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_begin, uint64_t n_traj,
+                          uint64_t *offsets, int32_t *sites, uint8_t *paulis, int64_t cap, int64_t *n_out) {
+  if (!ctx || !c) return fail(NT_ERR_INVALID_ARG, "ctx / circuit is NULL");
+  if (!offsets || !n_out || cap < 0 || (cap > 0 && (!sites || !paulis)))
+    return fail(NT_ERR_INVALID_ARG, "bad output buffers");
+  return guard([&] { ctx->impl->sample_sites(*c->impl, seed, traj_begin, n_traj, offsets, sites, paulis, cap, n_out); });
+}
+
+nt_status nt_final_state(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj, void *amps_out,
+                         int64_t len) {
+  if (!ctx || !c) return fail(NT_ERR_INVALID_ARG, "ctx / circuit is NULL");
+  if (!amps_out) return fail(NT_ERR_INVALID_ARG, "amps_out is NULL");
+  return guard([&] { ctx->impl->final_state(*c->impl, seed, traj, amps_out, len); });
+}
+
+nt_status nt_reference_state(nt_ctx *ctx, const nt_circuit *c, void *amps_out, int64_t len) {
+  if (!ctx || !c) return fail(NT_ERR_INVALID_ARG, "ctx / circuit is NULL");
+  if (!amps_out) return fail(NT_ERR_INVALID_ARG, "amps_out is NULL");
+  return guard([&] { ctx->impl->reference_state(*c->impl, amps_out, len); });
+}
+
+nt_status nt_timing_enable(nt_ctx *ctx, int enable) {
+  if (!ctx) return fail(NT_ERR_INVALID_ARG, "ctx is NULL");
+  return guard([&] {
+    if (!enable) ctx->impl->timing_flush();
+    ctx->impl->timing = enable != 0;
+  });
+}
+
+nt_status nt_timing_reset(nt_ctx *ctx) {
+  if (!ctx) return fail(NT_ERR_INVALID_ARG, "ctx is NULL");
+  return guard([&] {
+    nt::Ctx &cx = *ctx->impl;
+    cx.timing_flush();
+    cx.t_launches = 0;
+    cx.t_ms = cx.t_bytes = cx.t_updates = 0;
+  });
+}
+
+nt_status nt_timing_read(nt_ctx *ctx, int64_t *n_launches, double *ms_total, double *bytes_total,
+                         double *updates_total) {
+  if (!ctx) return fail(NT_ERR_INVALID_ARG, "ctx is NULL");
+  return guard([&] {
+    nt::Ctx &cx = *ctx->impl;
+    cx.timing_flush();
+    if (n_launches) *n_launches = cx.t_launches;
+    if (ms_total) *ms_total = cx.t_ms;
+    if (bytes_total) *bytes_total = cx.t_bytes;
+    if (updates_total) *updates_total = cx.t_updates;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,517 @@
+// Host engine: plan upload, reference state, batched trajectory runs.
+//
+// Per batch of B trajectories (Sec. IV-B.2 Monte Carlo runs):
+//   1. k_sample draws every error site of every trajectory (Philox) and
+//      writes the fired ones in plan order;
+//   2. one k_pass launch per pass of the plan (the first synthesizes |0...0>,
+//      the last fuses the fidelity partials against the resident reference);
+//   3. k_finalize turns partials into F per trajectory and the success count.
+// The error-free reference state (Sec. IV-B.1: the reference state psi_R) is
+// computed once per circuit and precision with the same kernels and kept in
+// device memory.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+namespace nt {
+
+void check_hip(hipError_t e, const char *what) {
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+      throw Error(NT_ERR_OUT_OF_MEMORY, std::string(what) + ": " + hipGetErrorString(e));
+    throw Error(NT_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+bool is_device_pointer(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof attr);
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice;
+}
+
+DevBuf::~DevBuf() { release(); }
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+void DevBuf::ensure(size_t n) {
+  if (n == 0) n = 16;
+  if (n <= bytes) return;
+  release();
+  check_hip(hipMalloc(&p, n), "hipMalloc");
+  bytes = n;
+}
+
+Ctx::Ctx(int dev, void *s) : device(dev) {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0) {
+    (void)hipGetLastError();
+    throw Error(NT_ERR_DEVICE, "no HIP device present");
+  }
+  if (dev < 0 || dev >= count) throw Error(NT_ERR_INVALID_ARG, "device index out of range");
+  check_hip(hipSetDevice(dev), "hipSetDevice");
+  if (s) {
+    stream = static_cast<hipStream_t>(s);
+  } else {
+    check_hip(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking), "hipStreamCreate");
+    own_stream = true;
+  }
+}
+
+Ctx::~Ctx() {
+  (void)hipSetDevice(device);
+  if (stream) (void)hipStreamSynchronize(stream);
+  for (auto &pr : ev_pending) {
+    ev_pool.push_back(pr.first);
+    ev_pool.push_back(pr.second);
+  }
+  for (hipEvent_t ev : ev_pool) (void)hipEventDestroy(ev);
+  plans.clear();
+  states.release(); events.release(); ev_count.release(); partials.release();
+  fid.release(); count.release(); frames.release(); tmp.release();
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+void Ctx::sync() { check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+
+static size_t amp_bytes(int prec) { return prec == NT_C64 ? 8 : 16; }
+
+// Order of a segment's thread-id bits: lanes 0..2^SW-1 take local positions
+// with distinct residues mod SW (conflict-free under the LDS swizzle), the
+// rest follow in ascending order.
+static std::vector<int> thread_bit_order(const std::vector<int> &tpos, int SW) {
+  std::vector<int> first, rest;
+  std::vector<char> used_res(SW, 0), used(tpos.size(), 0);
+  for (size_t i = 0; i < tpos.size() && (int)first.size() < SW; ++i) {
+    int r = tpos[i] % SW;
+    if (!used_res[r]) {
+      used_res[r] = 1;
+      used[i] = 1;
+      first.push_back(tpos[i]);
+    }
+  }
+  if ((int)first.size() < SW) return tpos;   // cannot do better
+  for (size_t i = 0; i < tpos.size(); ++i)
+    if (!used[i]) rest.push_back(tpos[i]);
+  first.insert(first.end(), rest.begin(), rest.end());
+  return first;
+}
+
+template <typename T>
+static void upload_ops(DevPlan &dp, hipStream_t s) {
+  const Plan &P = dp.plan;
+  std::vector<ntk::DevOp<T>> ops(std::max<size_t>(P.ops.size(), 1));
+  std::memset(ops.data(), 0, ops.size() * sizeof(ntk::DevOp<T>));
+  for (const Segment &sg : P.segs) {
+    auto rbit = [&](int q) {
+      for (size_t b = 0; b < sg.reg_q.size(); ++b)
+        if (sg.reg_q[b] == q) return (int)b;
+      return -1;
+    };
+    for (int o = sg.op_begin; o < sg.op_end; ++o) {
+      const HostOp &h = P.ops[o];
+      ntk::DevOp<T> &d = ops[o];
+      d.cls = h.cls;
+      d.qa = h.qa;
+      d.qb = h.qb;
+      int nent = 0;
+      switch (h.cls) {
+        case OPC_G1: d.rsel = rbit(h.qa); nent = 4; break;
+        case OPC_C1: d.rsel = rbit(h.qa); nent = 4; break;
+        case OPC_D1: d.rsel = 0; nent = 2; break;
+        case OPC_D2: d.rsel = 0; nent = 4; break;
+        case OPC_G2: d.rsel = rbit(h.qa) | (rbit(h.qb) << 4); nent = 16; break;
+      }
+      if ((h.cls == OPC_G1 || h.cls == OPC_C1 || h.cls == OPC_G2) && (d.rsel < 0 || (d.rsel >> 4) < 0))
+        throw Error(NT_ERR_UNSUPPORTED, "internal: dense op outside its segment's registers");
+      for (int i = 0; i < nent; ++i) {
+        d.m[2 * i] = (T)h.m[i].real();
+        d.m[2 * i + 1] = (T)h.m[i].imag();
+      }
+    }
+  }
+  dp.ops.ensure(ops.size() * sizeof(ntk::DevOp<T>));
+  check_hip(hipMemcpyAsync(dp.ops.p, ops.data(), ops.size() * sizeof(ntk::DevOp<T>), hipMemcpyHostToDevice, s),
+            "upload ops");
+}
+
+DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
+  auto key = std::make_pair(c.serial, pr);
+  auto it = plans.find(key);
+  if (it != plans.end()) return *it->second;
+  // keep at most a few plans (each may hold a reference state)
+  if (plans.size() >= 4) plans.clear();
+  auto dp = std::make_unique<DevPlan>();
+  dp->prec = pr;
+  int L, R, cfix;
+  plan_for_precision(c, pr, &L, &R, &cfix);
+  dp->plan = make_plan(c, L, R, cfix);
+  const Plan &P = dp->plan;
+  dp->nthreads = 1 << (L - R);
+  const int SW = pr == NT_C64 ? 4 : 3;
+
+  std::vector<ntk::DevSeg> segs(std::max<size_t>(P.segs.size(), 1));
+  std::memset(segs.data(), 0, segs.size() * sizeof(ntk::DevSeg));
+  std::vector<ntk::DevPass> dpass(P.passes.size());
+  std::memset(dpass.data(), 0, dpass.size() * sizeof(ntk::DevPass));
+  for (size_t p = 0; p < P.passes.size(); ++p) {
+    const Pass &ps = P.passes[p];
+    std::vector<int> loc, nl;
+    for (int q = 0; q < c.n; ++q) ((ps.local_mask >> q) & 1 ? loc : nl).push_back(q);
+    if ((int)loc.size() != L) throw Error(NT_ERR_UNSUPPORTED, "internal: tile size mismatch");
+    for (int q = 0; q < cfix; ++q)
+      if (loc[q] != q) throw Error(NT_ERR_UNSUPPORTED, "internal: low qubits not local");
+    for (size_t i = 0; i < loc.size(); ++i) dpass[p].locq[i] = (uint8_t)loc[i];
+    for (size_t i = 0; i < nl.size(); ++i) dpass[p].nlq[i] = (uint8_t)nl[i];
+    for (int s = ps.seg_begin; s < ps.seg_end; ++s) {
+      const Segment &sg = P.segs[s];
+      ntk::DevSeg &d = segs[s];
+      d.op_begin = sg.op_begin;
+      d.op_end = sg.op_end;
+      std::vector<int> is_reg(L, 0);
+      for (int b = 0; b < R; ++b) {
+        int lp = (int)(std::find(loc.begin(), loc.end(), sg.reg_q[b]) - loc.begin());
+        if (lp >= L) throw Error(NT_ERR_UNSUPPORTED, "internal: register qubit not local");
+        d.rpos[b] = (uint8_t)lp;
+        d.rq[b] = (uint8_t)sg.reg_q[b];
+        is_reg[lp] = 1;
+      }
+      std::vector<int> tpos;
+      for (int lp = 0; lp < L; ++lp)
+        if (!is_reg[lp]) tpos.push_back(lp);
+      tpos = thread_bit_order(tpos, SW);
+      for (size_t i = 0; i < tpos.size(); ++i) {
+        d.tpos[i] = (uint8_t)tpos[i];
+        d.tq[i] = (uint8_t)loc[tpos[i]];
+      }
+    }
+  }
+  dp->passes.ensure(dpass.size() * sizeof(ntk::DevPass));
+  check_hip(hipMemcpyAsync(dp->passes.p, dpass.data(), dpass.size() * sizeof(ntk::DevPass), hipMemcpyHostToDevice,
+                           stream), "upload passes");
+  dp->segs.ensure(segs.size() * sizeof(ntk::DevSeg));
+  check_hip(hipMemcpyAsync(dp->segs.p, segs.data(), segs.size() * sizeof(ntk::DevSeg), hipMemcpyHostToDevice, stream),
+            "upload segments");
+  if (pr == NT_C64) upload_ops<float>(*dp, stream);
+  else upload_ops<double>(*dp, stream);
+
+  const size_t S = std::max<size_t>(P.app_site.size(), 1);
+  std::vector<int32_t> ident(S);
+  std::vector<uint32_t> itag(S);
+  for (size_t k = 0; k < S; ++k) {
+    ident[k] = (int32_t)k;
+    itag[k] = (uint32_t)k << 8;
+  }
+  dp->app_order.ensure(S * 4);
+  dp->app_tag.ensure(S * 4);
+  dp->site_order.ensure(S * 4);
+  dp->site_tag.ensure(S * 4);
+  if (!P.app_site.empty()) {
+    check_hip(hipMemcpyAsync(dp->app_order.p, P.app_site.data(), P.app_site.size() * 4, hipMemcpyHostToDevice, stream), "upload");
+    check_hip(hipMemcpyAsync(dp->app_tag.p, P.app_tag.data(), P.app_tag.size() * 4, hipMemcpyHostToDevice, stream), "upload");
+  }
+  check_hip(hipMemcpyAsync(dp->site_order.p, ident.data(), S * 4, hipMemcpyHostToDevice, stream), "upload");
+  check_hip(hipMemcpyAsync(dp->site_tag.p, itag.data(), S * 4, hipMemcpyHostToDevice, stream), "upload");
+  sync();   // host vectors go out of scope
+  DevPlan &ref = *dp;
+  plans.emplace(key, std::move(dp));
+  return ref;
+}
+
+uint64_t Ctx::batch_size(const Circuit &c, const DevPlan &dp, uint64_t n_traj) {
+  const size_t state = ((size_t)1 << c.n) * amp_bytes(dp.prec);
+  uint64_t cap = max_batch ? max_batch : 65536;
+  if (dp.plan.passes.size() > 1) {
+    size_t freeb = 0, total = 0;
+    check_hip(hipMemGetInfo(&freeb, &total), "hipMemGetInfo");
+    size_t held = states.bytes;             // reusable
+    size_t avail = freeb + held;
+    size_t margin = (size_t)1 << 30;
+    if (avail < state + margin / 4)
+      throw Error(NT_ERR_OUT_OF_MEMORY, "not enough device memory for one state vector");
+    size_t budget = std::min(avail > margin ? avail - margin : avail / 2, (size_t)32 << 30);
+    uint64_t by_mem = std::max<uint64_t>(1, budget / state);
+    if (!max_batch) cap = std::min<uint64_t>(cap, by_mem);
+    else if (cap > by_mem) throw Error(NT_ERR_OUT_OF_MEMORY, "max_batch state vectors do not fit in device memory");
+  }
+  return std::max<uint64_t>(1, std::min<uint64_t>(cap, std::max<uint64_t>(n_traj, 1)));
+}
+
+static hipEvent_t take_event(std::vector<hipEvent_t> &pool) {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  check_hip(hipEventCreate(&e), "hipEventCreate");
+  return e;
+}
+
+void Ctx::timing_flush() {
+  if (ev_pending.empty()) return;
+  sync();
+  for (size_t i = 0; i < ev_pending.size(); ++i) {
+    float ms = 0;
+    check_hip(hipEventElapsedTime(&ms, ev_pending[i].first, ev_pending[i].second), "hipEventElapsedTime");
+    t_ms += ms;
+    t_bytes += ev_bytes[i];
+    t_updates += ev_updates[i];
+    ++t_launches;
+    ev_pool.push_back(ev_pending[i].first);
+    ev_pool.push_back(ev_pending[i].second);
+  }
+  ev_pending.clear();
+  ev_bytes.clear();
+  ev_updates.clear();
+}
+
+template <typename T>
+static void run_passes(Ctx &cx, const Circuit &c, DevPlan &dp, ntk::cx<T> *state, int B, int last_flags,
+                       const uint32_t *events, const int32_t *ev_count, int ev_stride, double *partials,
+                       uint32_t *frames) {
+  const Plan &P = dp.plan;
+  const int np = (int)P.passes.size();
+  const size_t dim = (size_t)1 << c.n;
+  for (int p = 0; p < np; ++p) {
+    const Pass &ps = P.passes[p];
+    ntk::PassArgs<T> a;
+    std::memset(&a, 0, sizeof a);
+    a.state = state;
+    a.ref = static_cast<const ntk::cx<T> *>(dp.ref.p);
+    a.ops = static_cast<const ntk::DevOp<T> *>(dp.ops.p);
+    a.segs = static_cast<const ntk::DevSeg *>(dp.segs.p);
+    a.events = events;
+    a.ev_count = ev_count;
+    a.partials = partials;
+    a.frame_out = (p == np - 1) ? frames : nullptr;
+    a.state_stride = dim;
+    a.ev_stride = ev_stride;
+    a.B = B;
+    a.L = P.L;
+    a.ntile_bits = c.n - P.L;
+    a.seg_begin = ps.seg_begin;
+    a.seg_end = ps.seg_end;
+    a.op_begin = ps.op_begin;
+    a.flags = (p == 0 ? ntk::PF_FIRST : 0) | (p == np - 1 ? last_flags : ntk::PF_STORE);
+    a.init_index = 0;
+    a.pass = static_cast<const ntk::DevPass *>(dp.passes.p) + p;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (cx.timing) {
+      e0 = take_event(cx.ev_pool);
+      e1 = take_event(cx.ev_pool);
+      check_hip(hipEventRecord(e0, cx.stream), "hipEventRecord");
+    }
+    check_hip(ntk::launch_pass<T>(a, P.R, dp.nthreads, cx.stream), "k_pass launch");
+    if (cx.timing) {
+      check_hip(hipEventRecord(e1, cx.stream), "hipEventRecord");
+      // algorithmic HBM bytes: every pass reads and writes each state once,
+      // except that the first does not read and a scoring pass reads the
+      // reference instead of writing.
+      double per_state = (double)dim * sizeof(ntk::cx<T>);
+      double reads = (a.flags & ntk::PF_FIRST) ? 0.0 : 1.0;
+      double writes = (a.flags & ntk::PF_SCORE) ? 0.0 : 1.0;
+      double refr = (a.flags & ntk::PF_SCORE) ? 1.0 : 0.0;
+      cx.ev_pending.emplace_back(e0, e1);
+      cx.ev_bytes.push_back(per_state * B * (reads + writes + refr));
+      cx.ev_updates.push_back((double)dim * B * (ps.op_end - ps.op_begin));
+      if (cx.ev_pending.size() >= 2048) cx.timing_flush();
+    }
+  }
+}
+
+void Ctx::ensure_reference(const Circuit &c, DevPlan &dp) {
+  if (dp.ref_ready) return;
+  const size_t dim = (size_t)1 << c.n;
+  const size_t ntiles = (size_t)1 << (c.n - dp.plan.L);
+  size_t freeb = 0, total = 0;
+  check_hip(hipMemGetInfo(&freeb, &total), "hipMemGetInfo");
+  if (dim * amp_bytes(dp.prec) + (64u << 20) > freeb)
+    throw Error(NT_ERR_OUT_OF_MEMORY, "not enough device memory for the reference state");
+  dp.ref.ensure(dim * amp_bytes(dp.prec));
+  dp.nref.ensure(sizeof(double));
+  dp.ref_partials.ensure(ntiles * 3 * sizeof(double));
+  ev_count.ensure(sizeof(int32_t) * 4);
+  events.ensure(16);
+  check_hip(hipMemsetAsync(ev_count.p, 0, sizeof(int32_t), stream), "hipMemsetAsync");
+  bool was = timing;
+  timing = false;
+  if (dp.prec == NT_C64)
+    run_passes<float>(*this, c, dp, dp.ref.as<ntk::cx<float>>(), 1, ntk::PF_STORE | ntk::PF_NORM,
+                      events.as<uint32_t>(), ev_count.as<int32_t>(), 1, dp.ref_partials.as<double>(), nullptr);
+  else
+    run_passes<double>(*this, c, dp, dp.ref.as<ntk::cx<double>>(), 1, ntk::PF_STORE | ntk::PF_NORM,
+                       events.as<uint32_t>(), ev_count.as<int32_t>(), 1, dp.ref_partials.as<double>(), nullptr);
+  timing = was;
+  check_hip(ntk::launch_norm_final(dp.ref_partials.as<double>(), (int)ntiles, dp.nref.as<double>(), stream),
+            "k_norm_final launch");
+  sync();
+  dp.ref_ready = true;
+}
+
+void Ctx::simulate_batch(const Circuit &c, DevPlan &dp, uint64_t seed, uint64_t t0, int B, int mode, double tau,
+                         double *fid_dev, uint64_t *count_dev, const Thresholds &th) {
+  const Plan &P = dp.plan;
+  const size_t dim = (size_t)1 << c.n;
+  const size_t ntiles = (size_t)1 << (c.n - P.L);
+  const int S = (int)std::max<int64_t>(c.S, 1);
+  events.ensure((size_t)B * S * 4);
+  ev_count.ensure((size_t)B * 4);
+  partials.ensure((size_t)B * ntiles * 3 * sizeof(double));
+  frames.ensure((size_t)B * 4 * sizeof(uint32_t));
+  const bool need_states = P.passes.size() > 1 || mode == 1;
+  if (need_states) states.ensure((size_t)B * dim * amp_bytes(dp.prec));
+
+  ntk::SampleArgs sa;
+  std::memset(&sa, 0, sizeof sa);
+  sa.seed = seed;
+  sa.cid = c.cid;
+  sa.t0 = t0;
+  sa.t_fire = th.t_fire;
+  sa.c_x = th.c_x;
+  sa.c_xy = th.c_xy;
+  sa.always = th.always;
+  sa.B = B;
+  sa.S = (int)c.S;
+  sa.ev_stride = S;
+  sa.order = dp.app_order.as<int32_t>();
+  sa.tag = dp.app_tag.as<uint32_t>();
+  sa.events = events.as<uint32_t>();
+  sa.ev_count = ev_count.as<int32_t>();
+  check_hip(ntk::launch_sample(sa, stream), "k_sample launch");
+
+  const int last = mode == 0 ? ntk::PF_SCORE : ntk::PF_STORE;
+  if (dp.prec == NT_C64)
+    run_passes<float>(*this, c, dp, need_states ? states.as<ntk::cx<float>>() : nullptr, B, last,
+                      events.as<uint32_t>(), ev_count.as<int32_t>(), S, partials.as<double>(),
+                      frames.as<uint32_t>());
+  else
+    run_passes<double>(*this, c, dp, need_states ? states.as<ntk::cx<double>>() : nullptr, B, last,
+                       events.as<uint32_t>(), ev_count.as<int32_t>(), S, partials.as<double>(),
+                       frames.as<uint32_t>());
+  if (mode == 0)
+    check_hip(ntk::launch_finalize(partials.as<double>(), (int)ntiles, B, dp.nref.as<double>(), tau, fid_dev,
+                                   count_dev, stream),
+              "k_finalize launch");
+}
+
+void Ctx::run(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
+              uint64_t *count_out) {
+  check_hip(hipSetDevice(device), "hipSetDevice");
+  DevPlan &dp = plan_for(c, prec);
+  ensure_reference(c, dp);
+  const Thresholds th = make_thresholds(px, py, pz);
+  const uint64_t bs = batch_size(c, dp, n);
+  const bool dev_out = is_device_pointer(fid_out);
+  count.ensure(sizeof(uint64_t));
+  check_hip(hipMemsetAsync(count.p, 0, sizeof(uint64_t), stream), "hipMemsetAsync");
+  if (!dev_out) fid.ensure((size_t)bs * sizeof(double));
+  for (uint64_t off = 0; off < n; off += bs) {
+    const int B = (int)std::min<uint64_t>(bs, n - off);
+    double *fd = dev_out ? fid_out + off : fid.as<double>();
+    simulate_batch(c, dp, seed, t0 + off, B, 0, tau, fd, count.as<uint64_t>(), th);
+    if (fid_out && !dev_out)
+      check_hip(hipMemcpyAsync(fid_out + off, fd, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, stream),
+                "copy fidelities");
+  }
+  uint64_t cnt = 0;
+  check_hip(hipMemcpyAsync(&cnt, count.p, sizeof cnt, hipMemcpyDeviceToHost, stream), "copy count");
+  sync();
+  if (count_out) *count_out = cnt;
+}
+
+void Ctx::sample_sites(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, uint64_t *offsets, int32_t *sites,
+                       uint8_t *paulis, int64_t cap, int64_t *n_out) {
+  check_hip(hipSetDevice(device), "hipSetDevice");
+  DevPlan &dp = plan_for(c, prec);
+  const Thresholds th = make_thresholds(px, py, pz);
+  const int S = (int)std::max<int64_t>(c.S, 1);
+  const uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(n, (256u << 20) / ((uint64_t)S * 4)));
+  events.ensure((size_t)chunk * S * 4);
+  ev_count.ensure((size_t)chunk * 4);
+  std::vector<uint32_t> hev((size_t)chunk * S);
+  std::vector<int32_t> hcnt(chunk);
+  int64_t total = 0;
+  offsets[0] = 0;
+  for (uint64_t off = 0; off < n; off += chunk) {
+    const int B = (int)std::min<uint64_t>(chunk, n - off);
+    ntk::SampleArgs sa;
+    std::memset(&sa, 0, sizeof sa);
+    sa.seed = seed; sa.cid = c.cid; sa.t0 = t0 + off;
+    sa.t_fire = th.t_fire; sa.c_x = th.c_x; sa.c_xy = th.c_xy; sa.always = th.always;
+    sa.B = B; sa.S = (int)c.S; sa.ev_stride = S;
+    sa.order = dp.site_order.as<int32_t>();
+    sa.tag = dp.site_tag.as<uint32_t>();
+    sa.events = events.as<uint32_t>();
+    sa.ev_count = ev_count.as<int32_t>();
+    check_hip(ntk::launch_sample(sa, stream), "k_sample launch");
+    check_hip(hipMemcpyAsync(hcnt.data(), ev_count.p, (size_t)B * 4, hipMemcpyDeviceToHost, stream), "copy counts");
+    check_hip(hipMemcpyAsync(hev.data(), events.p, (size_t)B * S * 4, hipMemcpyDeviceToHost, stream), "copy events");
+    sync();
+    for (int b = 0; b < B; ++b) {
+      for (int k = 0; k < hcnt[b]; ++k) {
+        if (total + k < cap) {
+          const uint32_t e = hev[(size_t)b * S + k];
+          sites[total + k] = (int32_t)(e >> 8);
+          paulis[total + k] = (uint8_t)(e & 3u);
+        }
+      }
+      total += hcnt[b];
+      offsets[off + b + 1] = (uint64_t)total;
+    }
+  }
+  *n_out = total;
+  if (total > cap) throw Error(NT_ERR_BUFFER_TOO_SMALL, "site buffers too small; required size in *n_out");
+}
+
+void Ctx::final_state(const Circuit &c, uint64_t seed, uint64_t traj, void *out, int64_t len) {
+  check_hip(hipSetDevice(device), "hipSetDevice");
+  const size_t dim = (size_t)1 << c.n;
+  if (len < (int64_t)dim) throw Error(NT_ERR_BUFFER_TOO_SMALL, "amps_out shorter than 2^n");
+  DevPlan &dp = plan_for(c, prec);
+  ensure_reference(c, dp);
+  const Thresholds th = make_thresholds(px, py, pz);
+  simulate_batch(c, dp, seed, traj, 1, 1, 0.0, nullptr, nullptr, th);
+  const size_t bytes = dim * amp_bytes(prec);
+  const bool dev_out = is_device_pointer(out);
+  void *dst = out;
+  if (!dev_out) {
+    tmp.ensure(bytes);
+    dst = tmp.p;
+  }
+  if (prec == NT_C64)
+    check_hip(ntk::launch_unframe<float>(states.as<ntk::cx<float>>(), static_cast<ntk::cx<float> *>(dst), dim,
+                                         frames.as<uint32_t>(), stream), "k_unframe launch");
+  else
+    check_hip(ntk::launch_unframe<double>(states.as<ntk::cx<double>>(), static_cast<ntk::cx<double> *>(dst), dim,
+                                          frames.as<uint32_t>(), stream), "k_unframe launch");
+  if (!dev_out) check_hip(hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, stream), "copy state");
+  sync();
+}
+
+void Ctx::reference_state(const Circuit &c, void *out, int64_t len) {
+  check_hip(hipSetDevice(device), "hipSetDevice");
+  const size_t dim = (size_t)1 << c.n;
+  if (len < (int64_t)dim) throw Error(NT_ERR_BUFFER_TOO_SMALL, "amps_out shorter than 2^n");
+  DevPlan &dp = plan_for(c, prec);
+  ensure_reference(c, dp);
+  const size_t bytes = dim * amp_bytes(prec);
+  check_hip(hipMemcpyAsync(out, dp.ref.p, bytes, is_device_pointer(out) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           stream), "copy reference");
+  sync();
+}
+
+}  // namespace nt

@@ -1,0 +1,78 @@
+// Host engine of libnisqtol: owns device buffers, uploads plans, sequences
+// kernel launches on the context stream.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "kernels.hpp"
+#include "nt_internal.hpp"
+
+namespace nt {
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf();
+  void ensure(size_t n);       // grows (never shrinks); contents not kept
+  void release();
+  template <typename X> X *as() const { return static_cast<X *>(p); }
+};
+
+// Device copy of a plan for one precision, plus the cached reference state.
+struct DevPlan {
+  int prec = 0;
+  Plan plan;
+  int nthreads = 0;            // threads per work-group = 2^(L - R)
+  DevBuf ops, segs, passes, app_order, app_tag, site_order, site_tag;
+  DevBuf ref, nref, ref_partials;
+  bool ref_ready = false;
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  double px = 0, py = 0, pz = 0;
+  int prec = NT_C128;
+  uint64_t max_batch = 0;
+  std::map<std::pair<uint64_t, int>, std::unique_ptr<DevPlan>> plans;
+  DevBuf states, events, ev_count, partials, fid, count, frames, tmp;
+  // timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+  std::vector<double> ev_bytes, ev_updates;
+  std::vector<hipEvent_t> ev_pool;
+  int64_t t_launches = 0;
+  double t_ms = 0, t_bytes = 0, t_updates = 0;
+
+  Ctx(int dev, void *stream);
+  ~Ctx();
+
+  DevPlan &plan_for(const Circuit &c, int prec);
+  void ensure_reference(const Circuit &c, DevPlan &dp);
+  uint64_t batch_size(const Circuit &c, const DevPlan &dp, uint64_t n_traj);
+
+  // Simulate trajectories [t0, t0 + B) and leave results on the device:
+  //   mode 0: score -> fid_dev[0..B), count_dev += successes
+  //   mode 1: store final states (frames in `frames`)
+  void simulate_batch(const Circuit &c, DevPlan &dp, uint64_t seed, uint64_t t0, int B, int mode,
+                      double tau, double *fid_dev, uint64_t *count_dev, const Thresholds &th);
+
+  void run(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
+           uint64_t *count_out);
+  void sample_sites(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, uint64_t *offsets,
+                    int32_t *sites, uint8_t *paulis, int64_t cap, int64_t *n_out);
+  void final_state(const Circuit &c, uint64_t seed, uint64_t traj, void *out, int64_t len);
+  void reference_state(const Circuit &c, void *out, int64_t len);
+
+  void timing_flush();
+  void sync();
+};
+
+void check_hip(hipError_t e, const char *what);
+bool is_device_pointer(const void *p);
+
+}  // namespace nt

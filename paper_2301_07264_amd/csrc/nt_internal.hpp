@@ -1,0 +1,106 @@
+// Internal declarations of libnisqtol (host side).
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "nisqtol.h"
+
+namespace nt {
+
+using cd = std::complex<double>;
+
+// Status-carrying exception used inside the library; converted to an
+// nt_status at the C ABI.
+struct Error : std::runtime_error {
+  nt_status code;
+  Error(nt_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+// How a gate acts on the amplitude array.  Diagonal ops never need their
+// qubits in a work-group's tile; dense ops need every listed qubit there; a
+// controlled op needs only its target.
+enum OpClass : int32_t {
+  OPC_G1 = 0,  // dense 2x2 on qa
+  OPC_D1 = 1,  // diagonal (d0, d1) on qa
+  OPC_C1 = 2,  // 2x2 on target qa when control qb equals the control value
+  OPC_D2 = 3,  // diagonal (d00, d10, d01, d11) on local index b_qa + 2 b_qb
+  OPC_G2 = 4,  // dense 4x4 on local index b_qa + 2 b_qb
+};
+
+struct HostGate {
+  int kind = 0;
+  int nq = 1;
+  int q[2] = {0, -1};
+  double param[3] = {0, 0, 0};
+  cd m[16];          // full local matrix (2x2 or 4x4 row-major), FP64
+};
+
+// One gate as an op of the simulator: class, qubits and the class's matrix
+// data (FP64; rounded once to FP32 for complex64 amplitudes).
+struct HostOp {
+  int32_t cls = OPC_G1;
+  int32_t qa = 0, qb = -1;
+  int32_t gate = 0;        // index in the circuit
+  cd m[16];                // G1/C1: 4 entries; D1: 2; D2: 4; G2: 16
+  // qubits that must be in the work-group tile / in registers
+  uint32_t need_mask() const;
+};
+
+struct Segment {
+  int op_begin = 0, op_end = 0;       // into Plan::ops (application order)
+  std::vector<int> reg_q;             // register qubits (global ids), size R
+};
+
+struct Pass {
+  uint64_t local_mask = 0;            // qubits held in the tile
+  int seg_begin = 0, seg_end = 0;
+  int op_begin = 0, op_end = 0;
+};
+
+struct Plan {
+  int n = 0;
+  int L = 0;          // tile qubits (<= n)
+  int R = 0;          // register qubits per thread
+  int cfix = 0;       // low qubits always in the tile (coalescing)
+  std::vector<HostOp> ops;              // application order
+  std::vector<Pass> passes;
+  std::vector<Segment> segs;
+  // sites in application order: Philox site index and kernel tag
+  std::vector<int32_t> app_site;
+  std::vector<uint32_t> app_tag;        // (op << 8) | (qubit << 2)
+  std::vector<int> op_of_gate;          // gate -> application position
+};
+
+struct Circuit {
+  int n = 0;
+  std::vector<HostGate> gates;
+  int64_t S = 0;
+  uint64_t cid = 0;
+  uint64_t serial = 0;                  // unique per loaded circuit
+};
+
+// circuit.cpp
+void gate_matrix(int kind, const double *param, const double *umat, cd *m);
+int kind_arity(int kind);
+const char *kind_name(int kind);
+int kind_from_name(const std::string &s);
+Circuit *load_circuit(int n, const nt_gate *gates, int64_t G);
+Circuit *load_circuit_text(const char *path);
+std::vector<HostOp> classify(const Circuit &c);
+
+// plan.cpp
+Plan make_plan(const Circuit &c, int max_tile_qubits, int max_reg, int cfix);
+void plan_for_precision(const Circuit &c, int prec, int *L, int *R, int *cfix);
+
+// sampling thresholds (host, FP64)
+struct Thresholds {
+  uint64_t t_fire = 0, c_x = 0, c_xy = 0;
+  uint32_t always = 0;                  // bit0 fire, bit1 x, bit2 xy
+};
+Thresholds make_thresholds(double px, double py, double pz);
+
+}  // namespace nt

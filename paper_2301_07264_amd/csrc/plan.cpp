@@ -1,0 +1,216 @@
+// Gate-pass planner.
+//
+// The Monte Carlo branch simulates every trajectory gate by gate (Sec. IV-B,
+// IV-B.2); its cost is one sweep over the 2^n amplitudes per gate.  On the GPU
+// a sweep over HBM is the expensive unit, so gates are grouped:
+//
+//   pass     one read + one write of the state in HBM.  A work-group holds a
+//            tile of 2^L amplitudes whose indices differ only in L "local"
+//            qubits (always including the lowest `cfix`, so that each tile is
+//            made of contiguous 128-byte runs).  A pass applies every gate it
+//            can reach whose non-diagonal qubits are local.  Diagonal gates
+//            (Z, S, T, RZ, CZ, CP, RZZ) and the control of a CNOT only read
+//            index bits, so they never need their qubits local.
+//   segment  inside a pass, each thread holds 2^R amplitudes in registers,
+//            whose indices differ in R "register" qubits; gates whose dense
+//            qubits are register qubits are applied without LDS traffic.
+//            Between segments the tile is exchanged through LDS.
+//
+// Gates keep their order on every qubit, so any schedule produced here is
+// the circuit's product of unitaries; errors stay attached to their gate.
+// The plan is the same for every trajectory.
+#include <algorithm>
+#include <numeric>
+
+#include "nt_internal.hpp"
+
+namespace nt {
+
+namespace {
+
+struct Sched {
+  const std::vector<HostOp> *ops;
+  int n;
+  std::vector<std::vector<int>> queue;   // per qubit: op indices in order
+  std::vector<int> head;
+  std::vector<char> done;
+
+  Sched(const std::vector<HostOp> &o, int nq, const std::vector<int> &subset) : ops(&o), n(nq) {
+    queue.assign(n, {});
+    head.assign(n, 0);
+    done.assign(o.size(), 0);
+    for (int i : subset) {
+      const HostOp &op = o[i];
+      queue[op.qa].push_back(i);
+      if (op.qb >= 0) queue[op.qb].push_back(i);
+    }
+  }
+
+  bool finished() const {
+    for (int q = 0; q < n; ++q)
+      if (head[q] < (int)queue[q].size()) return false;
+    return true;
+  }
+
+  // Schedule every ready op whose needed qubits are in `allowed`.  With
+  // out != nullptr the schedule is committed and the ops appended in order;
+  // otherwise heads are restored and only the count is returned.
+  int drain(uint64_t allowed, std::vector<int> *out) {
+    std::vector<int> saved;
+    if (!out) saved = head;
+    int cnt = 0;
+    std::vector<int> stack(n);
+    std::iota(stack.begin(), stack.end(), 0);
+    std::vector<char> instack(n, 1);
+    while (!stack.empty()) {
+      int q = stack.back();
+      stack.pop_back();
+      instack[q] = 0;
+      while (head[q] < (int)queue[q].size()) {
+        int i = queue[q][head[q]];
+        const HostOp &op = (*ops)[i];
+        int other = (op.qa == q) ? op.qb : op.qa;
+        if (other >= 0 && (head[other] >= (int)queue[other].size() || queue[other][head[other]] != i)) break;
+        if ((uint64_t)op.need_mask() & ~allowed) break;
+        head[q]++;
+        if (other >= 0) {
+          head[other]++;
+          if (!instack[other]) { stack.push_back(other); instack[other] = 1; }
+        }
+        ++cnt;
+        if (out) out->push_back(i);
+      }
+    }
+    if (!out) head = saved;
+    return cnt;
+  }
+
+  // Op index at the head of qubit q's queue (or a large value).
+  int head_op(int q) const { return head[q] < (int)queue[q].size() ? queue[q][head[q]] : (1 << 30); }
+};
+
+// Greedy choice of a qubit set of size k within `pool`, starting from
+// `base`: add one qubit at a time, taking the one that lets the most ops be
+// scheduled; ties go to the qubit whose next op comes first.
+uint64_t choose_set(Sched &s, uint64_t base, uint64_t pool, int k) {
+  uint64_t set = base;
+  int have = __builtin_popcountll(base);
+  while (have < k) {
+    int best = -1, best_cnt = -1, best_head = 1 << 30;
+    for (int q = 0; q < s.n; ++q) {
+      if (!((pool >> q) & 1) || ((set >> q) & 1)) continue;
+      int c = s.drain(set | (1ull << q), nullptr);
+      int h = s.head_op(q);
+      if (c > best_cnt || (c == best_cnt && h < best_head)) {
+        best = q; best_cnt = c; best_head = h;
+      }
+    }
+    if (best < 0) break;
+    set |= 1ull << best;
+    ++have;
+  }
+  return set;
+}
+
+}  // namespace
+
+void plan_for_precision(const Circuit &c, int prec, int *L, int *R, int *cfix) {
+  int n = c.n;
+  int lmax = prec == NT_C64 ? 13 : 12;      // 64 KiB of LDS per tile
+  int cf = prec == NT_C64 ? 4 : 3;          // 128-byte contiguous runs
+  *L = std::min(n, lmax);
+  *cfix = std::min(n, cf);
+  int r = std::max(2, std::min(4, *L - 6)); // >= 64 threads where possible
+  *R = std::min(r, *L);
+}
+
+Plan make_plan(const Circuit &c, int L, int R, int cfix) {
+  Plan P;
+  P.n = c.n;
+  P.L = L;
+  P.R = R;
+  P.cfix = cfix;
+  std::vector<HostOp> ops = classify(c);
+  const int n = c.n;
+  const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+  for (const HostOp &op : ops)
+    if (__builtin_popcount(op.need_mask()) > R)
+      throw Error(NT_ERR_UNSUPPORTED, "a two-qubit dense gate needs at least 2 register qubits");
+
+  std::vector<int> all_ops(ops.size());
+  std::iota(all_ops.begin(), all_ops.end(), 0);
+  Sched top(ops, n, all_ops);
+  const uint64_t fixed = (1ull << cfix) - 1;
+
+  std::vector<std::vector<int>> pass_ops;
+  std::vector<uint64_t> pass_mask;
+  if (ops.empty()) {
+    pass_ops.push_back({});
+    pass_mask.push_back(all & ((1ull << L) - 1));
+  }
+  while (!top.finished()) {
+    uint64_t lset = (L >= n) ? all : choose_set(top, fixed, all, L);
+    std::vector<int> sched;
+    top.drain(lset, &sched);
+    if (sched.empty()) throw Error(NT_ERR_UNSUPPORTED, "planner made no progress");
+    pass_ops.push_back(sched);
+    pass_mask.push_back(lset);
+  }
+
+  // Segments inside each pass.
+  for (size_t p = 0; p < pass_ops.size(); ++p) {
+    Pass ps;
+    ps.local_mask = pass_mask[p];
+    ps.seg_begin = (int)P.segs.size();
+    ps.op_begin = (int)P.ops.size();
+    Sched in(ops, n, pass_ops[p]);
+    if (pass_ops[p].empty()) {
+      Segment sg;
+      sg.op_begin = sg.op_end = (int)P.ops.size();
+      for (int q = 0; q < n && (int)sg.reg_q.size() < R; ++q)
+        if ((ps.local_mask >> q) & 1) sg.reg_q.push_back(q);
+      P.segs.push_back(sg);
+    }
+    while (!in.finished()) {
+      uint64_t rset = choose_set(in, 0, ps.local_mask, R);
+      std::vector<int> sched;
+      in.drain(rset, &sched);
+      if (sched.empty()) throw Error(NT_ERR_UNSUPPORTED, "segment planner made no progress");
+      Segment sg;
+      sg.op_begin = (int)P.ops.size();
+      for (int i : sched) P.ops.push_back(ops[i]);
+      sg.op_end = (int)P.ops.size();
+      for (int q = 0; q < n; ++q)
+        if ((rset >> q) & 1) sg.reg_q.push_back(q);
+      // pad to exactly R register qubits with other local qubits
+      for (int q = 0; q < n && (int)sg.reg_q.size() < R; ++q)
+        if (((ps.local_mask >> q) & 1) && !((rset >> q) & 1)) sg.reg_q.push_back(q);
+      std::sort(sg.reg_q.begin(), sg.reg_q.end());
+      P.segs.push_back(sg);
+    }
+    ps.seg_end = (int)P.segs.size();
+    ps.op_end = (int)P.ops.size();
+    P.passes.push_back(ps);
+  }
+
+  // Sites in application order.
+  std::vector<int64_t> site_base(c.gates.size());
+  int64_t s = 0;
+  for (size_t g = 0; g < c.gates.size(); ++g) {
+    site_base[g] = s;
+    s += c.gates[g].nq;
+  }
+  P.op_of_gate.assign(c.gates.size(), -1);
+  for (size_t o = 0; o < P.ops.size(); ++o) {
+    int g = P.ops[o].gate;
+    P.op_of_gate[g] = (int)o;
+    const HostGate &hg = c.gates[g];
+    for (int j = 0; j < hg.nq; ++j) {
+      P.app_site.push_back((int32_t)(site_base[g] + j));
+      P.app_tag.push_back(((uint32_t)o << 8) | ((uint32_t)hg.q[j] << 2));
+    }
+  }
+  return P;
+}
+
+}  // namespace nt
