@@ -25,6 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+# Vector ALU peak the gate kernels can reach: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32 without packed-FP32
+# instructions (kept off on the test machines), and the same for FP64.
+ALU_PEAK_TFLOPS = 78.6
 
 
 def main():
@@ -38,7 +42,18 @@ def main():
     ap.add_argument("--cpu-traj", type=int, default=1, help="oracle trajectories timed on the host")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON file with measured HBM bytes per pass launch (rocprofv3 counters)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a device copy of this many bytes (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_bytes:
+        import torch
+        x = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_bytes, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(trajectories would shard by range with one count all-reduce; not built).",
@@ -97,7 +112,7 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    launches, pass_ms, pass_bytes, pass_updates = P.nt_timing_read(ctx)
+    launches, pass_ms, pass_bytes, pass_updates, pass_flops = P.nt_timing_read(ctx)
     P.nt_timing_enable(ctx, False)
 
     n_traj = args.steps * B
@@ -108,6 +123,8 @@ def main():
     bytes_per_launch = pass_bytes / max(launches, 1)
     avg_launch_ms = pass_ms / max(launches, 1)
     achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
+    flops_per_launch = pass_flops / max(launches, 1)
+    achieved_tf = flops_per_launch / (avg_launch_ms / 1e3) / 1e12
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
         with open(args.traffic) as f:
@@ -126,6 +143,19 @@ def main():
                          f"FP64, OpenMP inside each gate, {dt:.1f} s wall (includes the oracle's own "
                          f"reference-state run)"}
 
+    hbm_frac = achieved / HBM_PEAK_GBS
+    alu_frac = achieved_tf / ALU_PEAK_TFLOPS
+    hbm_view = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm_frac, "traffic": traffic}
+    alu_view = {"bound": "alu", "achieved": achieved_tf, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": alu_frac, "traffic": traffic}
+    # the binding roofline is the one the kernel is closest to
+    roofline = dict(alu_view if alu_frac >= hbm_frac else hbm_view)
+    roofline.update({"kernel": "k_pass", "launches": launches, "avg_launch_ms": avg_launch_ms,
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "algorithmic_flops_per_launch": flops_per_launch,
+                     "pass_kernel_share_of_step": pass_ms / ms if ms > 0 else None,
+                     "hbm_view": hbm_view, "alu_view": alu_view})
     out = {
         "metric": "trajectory amplitude-updates/s (% HBM peak); time-to-tolerable-error-rate ±0.01",
         "value": value,
@@ -144,11 +174,7 @@ def main():
                    "trajectories_per_step": B, "n_qubits": n, "gates": G, "sites": S,
                    "amplitudes": args.prec, "passes_per_trajectory": n_pass, "segments": n_seg,
                    "tile_qubits": L, "parallelism": "single GPU, trajectory batch"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_pass", "launches": launches,
-                     "avg_launch_ms": avg_launch_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "pass_kernel_share_of_step": pass_ms / ms if ms > 0 else None},
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "successes": state["count"],
         "trajectories": n_traj,

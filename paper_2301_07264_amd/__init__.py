@@ -93,7 +93,7 @@ def lib() -> C.CDLL:
         "nt_reference_state": ([P, P, P, i64], i32),
         "nt_timing_enable": ([P, i32], i32),
         "nt_timing_reset": ([P], i32),
-        "nt_timing_read": ([P, P, P, P, P], i32),
+        "nt_timing_read": ([P, P, P, P, P, P], i32),
         "nt_last_error": ([], C.c_char_p),
         "nt_version": ([], C.c_char_p),
     }
@@ -305,8 +305,8 @@ def nt_timing_reset(ctx) -> None:
 
 
 def nt_timing_read(ctx):
-    """(launches, ms_total, algorithmic_bytes_total, updates_total)."""
+    """(launches, ms_total, algorithmic_bytes_total, updates_total, flops_total)."""
     n = C.c_int64()
-    ms, by, up = C.c_double(), C.c_double(), C.c_double()
-    _check(lib().nt_timing_read(ctx, C.byref(n), C.byref(ms), C.byref(by), C.byref(up)))
-    return n.value, ms.value, by.value, up.value
+    ms, by, up, fl = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    _check(lib().nt_timing_read(ctx, C.byref(n), C.byref(ms), C.byref(by), C.byref(up), C.byref(fl)))
+    return n.value, ms.value, by.value, up.value, fl.value

@@ -301,12 +301,12 @@ nt_status nt_timing_reset(nt_ctx *ctx) {
     nt::Ctx &cx = *ctx->impl;
     cx.timing_flush();
     cx.t_launches = 0;
-    cx.t_ms = cx.t_bytes = cx.t_updates = 0;
+    cx.t_ms = cx.t_bytes = cx.t_updates = cx.t_flops = 0;
   });
 }
 
 nt_status nt_timing_read(nt_ctx *ctx, int64_t *n_launches, double *ms_total, double *bytes_total,
-                         double *updates_total) {
+                         double *updates_total, double *flops_total) {
   if (!ctx) return fail(NT_ERR_INVALID_ARG, "ctx is NULL");
   return guard([&] {
     nt::Ctx &cx = *ctx->impl;
@@ -315,6 +315,7 @@ nt_status nt_timing_read(nt_ctx *ctx, int64_t *n_launches, double *ms_total, dou
     if (ms_total) *ms_total = cx.t_ms;
     if (bytes_total) *bytes_total = cx.t_bytes;
     if (updates_total) *updates_total = cx.t_updates;
+    if (flops_total) *flops_total = cx.t_flops;
   });
 }
 

@@ -110,37 +110,36 @@ static std::vector<int> thread_bit_order(const std::vector<int> &tpos, int SW) {
   return first;
 }
 
+// rsel per op (computed with the pass layouts): register bit of the dense
+// qubit for register-segment ops, tile-local positions for quad ops.
 template <typename T>
-static void upload_ops(DevPlan &dp, hipStream_t s) {
+static void upload_ops(DevPlan &dp, const std::vector<int32_t> &rsel, hipStream_t s) {
   const Plan &P = dp.plan;
   std::vector<ntk::DevOp<T>> ops(std::max<size_t>(P.ops.size(), 1));
   std::memset(ops.data(), 0, ops.size() * sizeof(ntk::DevOp<T>));
-  for (const Segment &sg : P.segs) {
-    auto rbit = [&](int q) {
-      for (size_t b = 0; b < sg.reg_q.size(); ++b)
-        if (sg.reg_q[b] == q) return (int)b;
-      return -1;
-    };
-    for (int o = sg.op_begin; o < sg.op_end; ++o) {
-      const HostOp &h = P.ops[o];
-      ntk::DevOp<T> &d = ops[o];
-      d.cls = h.cls;
-      d.qa = h.qa;
-      d.qb = h.qb;
-      int nent = 0;
-      switch (h.cls) {
-        case OPC_G1: d.rsel = rbit(h.qa); nent = 4; break;
-        case OPC_C1: d.rsel = rbit(h.qa); nent = 4; break;
-        case OPC_D1: d.rsel = 0; nent = 2; break;
-        case OPC_D2: d.rsel = 0; nent = 4; break;
-        case OPC_G2: d.rsel = rbit(h.qa) | (rbit(h.qb) << 4); nent = 16; break;
-      }
-      if ((h.cls == OPC_G1 || h.cls == OPC_C1 || h.cls == OPC_G2) && (d.rsel < 0 || (d.rsel >> 4) < 0))
-        throw Error(NT_ERR_UNSUPPORTED, "internal: dense op outside its segment's registers");
-      for (int i = 0; i < nent; ++i) {
-        d.m[2 * i] = (T)h.m[i].real();
-        d.m[2 * i + 1] = (T)h.m[i].imag();
-      }
+  for (size_t o = 0; o < P.ops.size(); ++o) {
+    const HostOp &h = P.ops[o];
+    ntk::DevOp<T> &d = ops[o];
+    d.cls = h.cls;
+    d.qa = h.qa;
+    d.qb = h.qb;
+    d.rsel = rsel[o];
+    int nent = 0;
+    switch (h.cls) {
+      case OPC_G1: nent = 4; break;
+      case OPC_C1:
+        nent = 4;
+        if (!(h.m[0] == cd(0) && h.m[1] == cd(1) && h.m[2] == cd(1) && h.m[3] == cd(0)))
+          throw Error(NT_ERR_UNSUPPORTED, "internal: controlled op other than CNOT");
+        d.rsel |= ntk::RSEL_CX;
+        break;
+      case OPC_D1: nent = 2; break;
+      case OPC_D2: nent = 4; break;
+      case OPC_G2: nent = 16; break;
+    }
+    for (int i = 0; i < nent; ++i) {
+      d.m[2 * i] = (T)h.m[i].real();
+      d.m[2 * i + 1] = (T)h.m[i].imag();
     }
   }
   dp.ops.ensure(ops.size() * sizeof(ntk::DevOp<T>));
@@ -162,11 +161,28 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
   const Plan &P = dp->plan;
   dp->nthreads = 1 << (L - R);
   const int SW = pr == NT_C64 ? 4 : 3;
+  // Algorithmic flops per amplitude of each op class (complex multiply 6,
+  // complex add 2): dense 2x2: (4 mul + 2 add) per pair -> 14 per amplitude;
+  // diagonal: 6; controlled X: a permutation, 0; dense 4x4: (16 mul + 12 add)
+  // per quad -> 30.
+  for (const Pass &ps : P.passes) {
+    double f = 0;
+    for (int o = ps.op_begin; o < ps.op_end; ++o) {
+      switch (P.ops[o].cls) {
+        case OPC_G1: f += 14; break;
+        case OPC_D1: case OPC_D2: f += 6; break;
+        case OPC_C1: break;
+        case OPC_G2: f += 30; break;
+      }
+    }
+    dp->pass_flops_per_amp.push_back(f);
+  }
 
   std::vector<ntk::DevSeg> segs(std::max<size_t>(P.segs.size(), 1));
   std::memset(segs.data(), 0, segs.size() * sizeof(ntk::DevSeg));
   std::vector<ntk::DevPass> dpass(P.passes.size());
   std::memset(dpass.data(), 0, dpass.size() * sizeof(ntk::DevPass));
+  std::vector<int32_t> rsel(P.ops.size(), 0);
   for (size_t p = 0; p < P.passes.size(); ++p) {
     const Pass &ps = P.passes[p];
     std::vector<int> loc, nl;
@@ -179,8 +195,25 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
     for (int s = ps.seg_begin; s < ps.seg_end; ++s) {
       const Segment &sg = P.segs[s];
       ntk::DevSeg &d = segs[s];
+      d.kind = sg.kind == SEG_QUAD ? ntk::SEG_KIND_QUAD : ntk::SEG_KIND_REG;
       d.op_begin = sg.op_begin;
       d.op_end = sg.op_end;
+      auto local_pos = [&](int q) { return (int)(std::find(loc.begin(), loc.end(), q) - loc.begin()); };
+      for (int o = sg.op_begin; o < sg.op_end; ++o) {
+        const HostOp &h = P.ops[o];
+        if (sg.kind == SEG_QUAD) {
+          if (h.cls != OPC_G2) throw Error(NT_ERR_UNSUPPORTED, "internal: quad segment without a dense 2q op");
+          const int pa = local_pos(h.qa), pb = local_pos(h.qb);
+          if (pa >= L || pb >= L) throw Error(NT_ERR_UNSUPPORTED, "internal: quad op qubit not local");
+          rsel[o] = pa | (pb << 4);
+        } else if (h.cls == OPC_G1 || h.cls == OPC_C1) {
+          auto it = std::find(sg.reg_q.begin(), sg.reg_q.end(), h.qa);
+          if (it == sg.reg_q.end()) throw Error(NT_ERR_UNSUPPORTED, "internal: dense op outside its segment's registers");
+          rsel[o] = (int32_t)(it - sg.reg_q.begin());
+        } else if (h.cls == OPC_G2) {
+          throw Error(NT_ERR_UNSUPPORTED, "internal: dense 2q op in a register segment");
+        }
+      }
       std::vector<int> is_reg(L, 0);
       for (int b = 0; b < R; ++b) {
         int lp = (int)(std::find(loc.begin(), loc.end(), sg.reg_q[b]) - loc.begin());
@@ -205,8 +238,8 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
   dp->segs.ensure(segs.size() * sizeof(ntk::DevSeg));
   check_hip(hipMemcpyAsync(dp->segs.p, segs.data(), segs.size() * sizeof(ntk::DevSeg), hipMemcpyHostToDevice, stream),
             "upload segments");
-  if (pr == NT_C64) upload_ops<float>(*dp, stream);
-  else upload_ops<double>(*dp, stream);
+  if (pr == NT_C64) upload_ops<float>(*dp, rsel, stream);
+  else upload_ops<double>(*dp, rsel, stream);
 
   const size_t S = std::max<size_t>(P.app_site.size(), 1);
   std::vector<int32_t> ident(S);
@@ -270,6 +303,7 @@ void Ctx::timing_flush() {
     t_ms += ms;
     t_bytes += ev_bytes[i];
     t_updates += ev_updates[i];
+    t_flops += ev_flops[i];
     ++t_launches;
     ev_pool.push_back(ev_pending[i].first);
     ev_pool.push_back(ev_pending[i].second);
@@ -277,6 +311,7 @@ void Ctx::timing_flush() {
   ev_pending.clear();
   ev_bytes.clear();
   ev_updates.clear();
+  ev_flops.clear();
 }
 
 template <typename T>
@@ -328,6 +363,8 @@ static void run_passes(Ctx &cx, const Circuit &c, DevPlan &dp, ntk::cx<T> *state
       cx.ev_pending.emplace_back(e0, e1);
       cx.ev_bytes.push_back(per_state * B * (reads + writes + refr));
       cx.ev_updates.push_back((double)dim * B * (ps.op_end - ps.op_begin));
+      double fl = dp.pass_flops_per_amp[p] + ((a.flags & ntk::PF_SCORE) ? 8.0 : 0.0);
+      cx.ev_flops.push_back((double)dim * B * fl);
       if (cx.ev_pending.size() >= 2048) cx.timing_flush();
     }
   }

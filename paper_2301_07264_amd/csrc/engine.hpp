@@ -29,6 +29,7 @@ struct DevPlan {
   DevBuf ops, segs, passes, app_order, app_tag, site_order, site_tag;
   DevBuf ref, nref, ref_partials;
   bool ref_ready = false;
+  std::vector<double> pass_flops_per_amp;   // algorithmic flops per amplitude, per pass
 };
 
 struct Ctx {
@@ -43,10 +44,10 @@ struct Ctx {
   // timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
-  std::vector<double> ev_bytes, ev_updates;
+  std::vector<double> ev_bytes, ev_updates, ev_flops;
   std::vector<hipEvent_t> ev_pool;
   int64_t t_launches = 0;
-  double t_ms = 0, t_bytes = 0, t_updates = 0;
+  double t_ms = 0, t_bytes = 0, t_updates = 0, t_flops = 0;
 
   Ctx(int dev, void *stream);
   ~Ctx();

@@ -170,43 +170,47 @@ DEV void g1_apply(cx<T> (&v)[1 << R], cx<T> m00, cx<T> m01, cx<T> m10, cx<T> m11
   }
 }
 
-// Control bit of slot r = lane bit (thread / tile part of the index) or the
-// slot's own bit when the control is a register qubit (cmask: its register
-// bit, uniform).
+// Controlled +-X on register bit B (a CNOT conjugated by the frame: the
+// target's X part leaves X unchanged, its Z part flips the sign).  sbit is
+// the IEEE sign mask to XOR in (0 or the sign bit), uniform.
+template <typename T> struct SignBits;
+template <> struct SignBits<float> {
+  using U = uint32_t;
+  static DEV float flip(float v, U s) { return __uint_as_float(__float_as_uint(v) ^ s); }
+  static constexpr U sign = 0x80000000u;
+};
+template <> struct SignBits<double> {
+  using U = uint64_t;
+  static DEV double flip(double v, U s) {
+    return __longlong_as_double((long long)((uint64_t)__double_as_longlong(v) ^ s));
+  }
+  static constexpr U sign = 0x8000000000000000ull;
+};
+
 template <int B, int R, typename T>
-DEV void c1_apply(cx<T> (&v)[1 << R], cx<T> m00, cx<T> m01, cx<T> m10, cx<T> m11, uint32_t clane,
-                  uint32_t cmask, uint32_t cv) {
+DEV void cx_apply(cx<T> (&v)[1 << R], typename SignBits<T>::U sbit, uint32_t clane, uint32_t cmask, uint32_t cv) {
+  using SB = SignBits<T>;
 #pragma unroll
   for (int r = 0; r < (1 << R); ++r) {
     if (r & (1 << B)) continue;
     const cx<T> x = v[r], y = v[r | (1 << B)];
     const bool take = (clane | (((uint32_t)r & cmask) ? 1u : 0u)) == cv;
-    const cx<T> n0 = mac2(m00, x, m01, y), n1 = mac2(m10, x, m11, y);
-    v[r] = take ? n0 : x;
-    v[r | (1 << B)] = take ? n1 : y;
-    __builtin_amdgcn_sched_barrier(0);
+    const cx<T> ny{SB::flip(y.x, sbit), SB::flip(y.y, sbit)};
+    const cx<T> nx{SB::flip(x.x, sbit), SB::flip(x.y, sbit)};
+    v[r] = take ? ny : x;
+    v[r | (1 << B)] = take ? nx : y;
   }
 }
 
-template <int B0, int B1, int R, typename T>
-DEV void g2_apply(cx<T> (&v)[1 << R], const cx<T> (&m)[16]) {
-#pragma unroll
-  for (int r = 0; r < (1 << R); ++r) {
-    if (r & ((1 << B0) | (1 << B1))) continue;
-    const int i0 = r, i1 = r | (1 << B0), i2 = r | (1 << B1), i3 = r | (1 << B0) | (1 << B1);
-    const cx<T> a0 = v[i0], a1 = v[i1], a2 = v[i2], a3 = v[i3];
-    cx<T> o[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      cx<T> s = mac2(m[4 * i + 0], a0, m[4 * i + 1], a1);
-      cx<T> t = mac2(m[4 * i + 2], a2, m[4 * i + 3], a3);
-      o[i] = cx<T>{s.x + t.x, s.y + t.y};
-    }
-    v[i0] = o[0];
-    v[i1] = o[1];
-    v[i2] = o[2];
-    v[i3] = o[3];
-    __builtin_amdgcn_sched_barrier(0);
+template <int R, typename T>
+DEV void dispatch_cx(int B, cx<T> (&v)[1 << R], typename SignBits<T>::U sbit, uint32_t clane, uint32_t cmask,
+                     uint32_t cv) {
+  switch (B) {
+    case 0: cx_apply<0, R>(v, sbit, clane, cmask, cv); break;
+    case 1: if constexpr (R > 1) cx_apply<1, R>(v, sbit, clane, cmask, cv); break;
+    case 2: if constexpr (R > 2) cx_apply<2, R>(v, sbit, clane, cmask, cv); break;
+    case 3: if constexpr (R > 3) cx_apply<3, R>(v, sbit, clane, cmask, cv); break;
+    default: break;
   }
 }
 
@@ -221,42 +225,6 @@ DEV void dispatch_g1(int B, cx<T> (&v)[1 << R], cx<T> m00, cx<T> m01, cx<T> m10,
   }
 }
 
-template <int R, typename T>
-DEV void dispatch_c1(int B, cx<T> (&v)[1 << R], cx<T> m00, cx<T> m01, cx<T> m10, cx<T> m11,
-                     uint32_t clane, uint32_t cmask, uint32_t cv) {
-  switch (B) {
-    case 0: c1_apply<0, R>(v, m00, m01, m10, m11, clane, cmask, cv); break;
-    case 1: if constexpr (R > 1) c1_apply<1, R>(v, m00, m01, m10, m11, clane, cmask, cv); break;
-    case 2: if constexpr (R > 2) c1_apply<2, R>(v, m00, m01, m10, m11, clane, cmask, cv); break;
-    case 3: if constexpr (R > 3) c1_apply<3, R>(v, m00, m01, m10, m11, clane, cmask, cv); break;
-    default: break;
-  }
-}
-
-template <int B0, int B1, int R, typename T>
-DEV void g2_if(cx<T> (&v)[1 << R], const cx<T> (&m)[16]) {
-  if constexpr (B0 != B1 && B0 < R && B1 < R) g2_apply<B0, B1, R>(v, m);
-}
-
-template <int R, typename T>
-DEV void dispatch_g2(int sel, cx<T> (&v)[1 << R], const cx<T> (&m)[16]) {
-  switch (sel) {
-    case 0x10: g2_if<0, 1, R>(v, m); break;
-    case 0x20: g2_if<0, 2, R>(v, m); break;
-    case 0x30: g2_if<0, 3, R>(v, m); break;
-    case 0x01: g2_if<1, 0, R>(v, m); break;
-    case 0x21: g2_if<1, 2, R>(v, m); break;
-    case 0x31: g2_if<1, 3, R>(v, m); break;
-    case 0x02: g2_if<2, 0, R>(v, m); break;
-    case 0x12: g2_if<2, 1, R>(v, m); break;
-    case 0x32: g2_if<2, 3, R>(v, m); break;
-    case 0x03: g2_if<3, 0, R>(v, m); break;
-    case 0x13: g2_if<3, 1, R>(v, m); break;
-    case 0x23: g2_if<3, 2, R>(v, m); break;
-    default: break;
-  }
-}
-
 // Register bits of the segment that hold qubit q (0 or one bit), uniform.
 template <int R>
 DEV uint32_t reg_mask(const uint32_t (&rq)[R], uint32_t q) {
@@ -266,34 +234,69 @@ DEV uint32_t reg_mask(const uint32_t (&rq)[R], uint32_t q) {
   return m;
 }
 
-// Apply one op, conjugated by the current Pauli frame, to the register slots.
-// gb: the thread's global index with all register bits zero; rq: global
-// qubit of each register bit.  Index bit q of slot r is
+// Header and the first four complex matrix entries of an op: everything a
+// register-segment op needs (read with scalar loads, one op ahead).
+template <typename T>
+struct OpLite {
+  int32_t cls, qa, qb, rsel;
+  T m[8];
+};
+
+template <typename T>
+DEV OpLite<T> load_lite(const DevOp<T> *ops, int o) {
+  const DevOp<T> &op = ops[o];
+  OpLite<T> h;
+  h.cls = op.cls;
+  h.qa = op.qa;
+  h.qb = op.qb;
+  h.rsel = op.rsel;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) h.m[i] = op.m[i];
+  return h;
+}
+
+template <typename T>
+DEV cx<T> lent(const OpLite<T> &h, int i) {
+  return cx<T>{h.m[2 * i], h.m[2 * i + 1]};
+}
+
+// Entry i ^ xm of a 4-entry list, xm uniform in 0..3 (scalar selects).
+template <typename T>
+DEV cx<T> perm4(const OpLite<T> &h, int i, uint32_t xm) {
+  const cx<T> e0 = lent(h, i), e1 = lent(h, i ^ 1), e2 = lent(h, i ^ 2), e3 = lent(h, i ^ 3);
+  return xm == 0u ? e0 : (xm == 1u ? e1 : (xm == 2u ? e2 : e3));
+}
+
+// Apply one register-segment op, conjugated by the current Pauli frame, to
+// the register slots.  gb: the thread's global index with all register bits
+// zero; rq: global qubit of each register bit.  Index bit q of slot r is
 // ((gb >> q) & 1) | (r & reg_mask(q) != 0).
 template <int R, typename T>
-DEV void apply_op(const DevOp<T> &op, cx<T> (&v)[1 << R], uint32_t gb, const uint32_t (&rq)[R],
-                  uint32_t fx, uint32_t fz) {
+DEV void apply_reg_op(const OpLite<T> &op, cx<T> (&v)[1 << R], uint32_t gb, const uint32_t (&rq)[R],
+                      uint32_t fx, uint32_t fz) {
   constexpr int NS = 1 << R;
   const int cls = op.cls;
   const uint32_t qa = (uint32_t)op.qa;
   const uint32_t xa = (fx >> qa) & 1u, za = (fz >> qa) & 1u;
-  if (cls == OP_G1 || cls == OP_C1) {
+  if (cls == OP_C1) {
+    // controlled X: conjugation by X^x Z^z on the target gives (-1)^z X; an
+    // X on the control flips the control value.
+    const uint32_t qc = (uint32_t)op.qb;
+    const uint32_t cv = 1u ^ ((fx >> qc) & 1u);
+    const typename SignBits<T>::U sbit = za ? SignBits<T>::sign : 0;
+    dispatch_cx<R, T>(op.rsel & 15, v, sbit, (gb >> qc) & 1u, reg_mask<R>(rq, qc), cv);
+  } else if (cls == OP_G1) {
     // (Z^z X^x) M (X^x Z^z): entry (i, j) = (-1)^{z(i+j)} M[i^x][j^x]
-    cx<T> m00 = ment(op, (0u ^ xa) * 2u + (0u ^ xa)), m01 = ment(op, (0u ^ xa) * 2u + (1u ^ xa));
-    cx<T> m10 = ment(op, (1u ^ xa) * 2u + (0u ^ xa)), m11 = ment(op, (1u ^ xa) * 2u + (1u ^ xa));
+    const cx<T> m00 = lent(op, 0), m01 = lent(op, 1), m10 = lent(op, 2), m11 = lent(op, 3);
+    cx<T> c00 = xa ? m11 : m00, c01 = xa ? m10 : m01, c10 = xa ? m01 : m10, c11 = xa ? m00 : m11;
     if (za) {
-      m01 = cneg(m01);
-      m10 = cneg(m10);
+      c01 = cneg(c01);
+      c10 = cneg(c10);
     }
-    if (cls == OP_G1) {
-      dispatch_g1<R>(op.rsel & 15, v, m00, m01, m10, m11);
-    } else {
-      const uint32_t qc = (uint32_t)op.qb;
-      const uint32_t cv = 1u ^ ((fx >> qc) & 1u);
-      dispatch_c1<R>(op.rsel & 15, v, m00, m01, m10, m11, (gb >> qc) & 1u, reg_mask<R>(rq, qc), cv);
-    }
+    dispatch_g1<R>(op.rsel & 15, v, c00, c01, c10, c11);
   } else if (cls == OP_D1) {
-    const cx<T> d0 = ment(op, 0u ^ xa), d1 = ment(op, 1u ^ xa);
+    const cx<T> e0 = lent(op, 0), e1 = lent(op, 1);
+    const cx<T> d0 = xa ? e1 : e0, d1 = xa ? e0 : e1;
     const uint32_t lane = (gb >> qa) & 1u, am = reg_mask<R>(rq, qa);
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
@@ -303,7 +306,7 @@ DEV void apply_op(const DevOp<T> &op, cx<T> (&v)[1 << R], uint32_t gb, const uin
   } else if (cls == OP_D2) {
     const uint32_t qb = (uint32_t)op.qb;
     const uint32_t xm = xa | (((fx >> qb) & 1u) << 1);
-    const cx<T> d0 = ment(op, 0u ^ xm), d1 = ment(op, 1u ^ xm), d2 = ment(op, 2u ^ xm), d3 = ment(op, 3u ^ xm);
+    const cx<T> d0 = perm4(op, 0, xm), d1 = perm4(op, 1, xm), d2 = perm4(op, 2, xm), d3 = perm4(op, 3, xm);
     const uint32_t la = (gb >> qa) & 1u, lb = (gb >> qb) & 1u;
     const uint32_t am = reg_mask<R>(rq, qa), bm = reg_mask<R>(rq, qb);
 #pragma unroll
@@ -313,20 +316,45 @@ DEV void apply_op(const DevOp<T> &op, cx<T> (&v)[1 << R], uint32_t gb, const uin
       const cx<T> d = bb ? (ba ? d3 : d2) : (ba ? d1 : d0);
       v[r] = cmul(d, v[r]);
     }
-  } else if (cls == OP_G2) {
-    const uint32_t qb = (uint32_t)op.qb;
-    const uint32_t xm = xa | (((fx >> qb) & 1u) << 1);
-    const uint32_t zm = za | (((fz >> qb) & 1u) << 1);
-    cx<T> m[16];
+  }
+}
+
+// Dense two-qubit op applied directly to the tile in LDS (quad segment).
+// rsel holds the tile-local bit positions of qa (bits 0..3) and qb (4..7).
+template <typename T>
+DEV void apply_quad_lds(const DevOp<T> &op, cx<T> *lds, int L, uint32_t fx, uint32_t fz) {
+  const uint32_t qa = (uint32_t)op.qa, qb = (uint32_t)op.qb;
+  const uint32_t pa = (uint32_t)op.rsel & 15u, pb = ((uint32_t)op.rsel >> 4) & 15u;
+  const uint32_t xm = ((fx >> qa) & 1u) | (((fx >> qb) & 1u) << 1);
+  const uint32_t zm = ((fz >> qa) & 1u) | (((fz >> qb) & 1u) << 1);
+  cx<T> m[16];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        cx<T> e = ment(op, ((uint32_t)i ^ xm) * 4u + ((uint32_t)j ^ xm));
-        const uint32_t neg = (__popc(zm & (uint32_t)i) + __popc(zm & (uint32_t)j)) & 1u;
-        m[4 * i + j] = neg ? cneg(e) : e;
-      }
-    dispatch_g2<R>(op.rsel & 0xff, v, m);
+    for (int j = 0; j < 4; ++j) {
+      cx<T> e = ment(op, ((uint32_t)i ^ xm) * 4u + ((uint32_t)j ^ xm));
+      const uint32_t neg = (__popc(zm & (uint32_t)i) + __popc(zm & (uint32_t)j)) & 1u;
+      m[4 * i + j] = neg ? cneg(e) : e;
+    }
+  const uint32_t lo = pa < pb ? pa : pb, hi = pa < pb ? pb : pa;
+  const uint32_t nq = 1u << (L - 2);
+  for (uint32_t qi = threadIdx.x; qi < nq; qi += blockDim.x) {
+    uint32_t j = ((qi >> lo) << (lo + 1)) | (qi & ((1u << lo) - 1u));
+    j = ((j >> hi) << (hi + 1)) | (j & ((1u << hi) - 1u));
+    const uint32_t i0 = swz<T>(j), i1 = swz<T>(j | (1u << pa)), i2 = swz<T>(j | (1u << pb)),
+                   i3 = swz<T>(j | (1u << pa) | (1u << pb));
+    const cx<T> a0 = lds[i0], a1 = lds[i1], a2 = lds[i2], a3 = lds[i3];
+    cx<T> o[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const cx<T> s = mac2(m[4 * i + 0], a0, m[4 * i + 1], a1);
+      const cx<T> t = mac2(m[4 * i + 2], a2, m[4 * i + 3], a3);
+      o[i] = cx<T>{s.x + t.x, s.y + t.y};
+    }
+    lds[i0] = o[0];
+    lds[i1] = o[1];
+    lds[i2] = o[2];
+    lds[i3] = o[3];
   }
 }
 
@@ -410,20 +438,41 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   }
   __syncthreads();
 
-  // Pauli frame at the start of this pass.
+  // Pauli frame at the start of this pass; next_op is the op index of the
+  // trajectory's next error event (~0 when there is none).
   const uint32_t *ev = a.events + (size_t)b * a.ev_stride;
   const int ne = a.ev_count[b];
   int ep = 0;
   uint32_t fx = 0, fz = 0, fc = 0;
+  uint32_t next_e = 0, next_op = 0xffffffffu;
   while (ep < ne) {
-    const uint32_t e = ev[ep];
-    if ((int)(e >> 8) >= a.op_begin) break;
-    frame_apply(e, fx, fz, fc);
+    next_e = ev[ep];
+    if ((int)(next_e >> 8) >= a.op_begin) break;
+    frame_apply(next_e, fx, fz, fc);
     ++ep;
   }
+  if (ep < ne) next_op = next_e >> 8;
+  auto take_events = [&](int o) {
+    while (next_op == (uint32_t)o) {
+      frame_apply(next_e, fx, fz, fc);
+      ++ep;
+      if (ep < ne) {
+        next_e = ev[ep];
+        next_op = next_e >> 8;
+      } else {
+        next_op = 0xffffffffu;
+      }
+    }
+  };
 
   for (int s = a.seg_begin; s < a.seg_end; ++s) {
     const DevSeg &sg = a.segs[s];
+    if (sg.kind == SEG_KIND_QUAD) {
+      apply_quad_lds<T>(a.ops[sg.op_begin], lds, a.L, fx, fz);
+      take_events(sg.op_begin);
+      __syncthreads();
+      continue;
+    }
     uint32_t jb = 0, gb = tilebase;
     for (int i = 0; i < lt; ++i) {
       const uint32_t bit = (tid >> i) & 1u;
@@ -446,13 +495,14 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     cx<T> v[NS];
 #pragma unroll
     for (int r = 0; r < NS; ++r) v[r] = lds[jaddr(r)];
-    for (int o = sg.op_begin; o < sg.op_end; ++o) {
-      apply_op<R, T>(a.ops[o], v, gb, rq, fx, fz);
-      while (ep < ne) {
-        const uint32_t e = ev[ep];
-        if ((int)(e >> 8) != o) break;
-        frame_apply(e, fx, fz, fc);
-        ++ep;
+    if (sg.op_begin < sg.op_end) {
+      OpLite<T> cur = load_lite(a.ops, sg.op_begin);
+      for (int o = sg.op_begin; o < sg.op_end; ++o) {
+        OpLite<T> nxt = cur;
+        if (o + 1 < sg.op_end) nxt = load_lite(a.ops, o + 1);   // next op's loads in flight
+        apply_reg_op<R, T>(cur, v, gb, rq, fx, fz);
+        take_events(o);
+        cur = nxt;
       }
     }
 #pragma unroll

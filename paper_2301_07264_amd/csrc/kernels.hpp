@@ -15,8 +15,9 @@ struct alignas(2 * sizeof(T)) cx {
 //   cls  : op class (G1 dense 2x2, D1 diagonal 1q, C1 controlled 2x2,
 //          D2 diagonal 2q, G2 dense 4x4)
 //   qa,qb: qubits (C1: qa = target, qb = control)
-//   rsel : register-bit position(s) of the dense qubit(s) in the segment
-//          that applies the op: qa's in bits 0..3, qb's in bits 4..7
+//   rsel : G1 / C1: register bit of qa in the segment that applies the op;
+//          G2: tile-local bit positions of qa (bits 0..3) and qb (bits 4..7);
+//          RSEL_CX marks a controlled X (the only C1 the host emits)
 //   m    : matrix data, (re, im) interleaved; G1/C1 2x2 row-major, D1 (d0,d1),
 //          D2 (d0..d3) on local index b_qa + 2 b_qb, G2 4x4 row-major
 template <typename T>
@@ -26,10 +27,17 @@ struct DevOp {
 };
 
 enum : int32_t { OP_G1 = 0, OP_D1 = 1, OP_C1 = 2, OP_D2 = 3, OP_G2 = 4 };
+// rsel flag: the C1 op's target matrix is exactly X (a CNOT).
+enum : int32_t { RSEL_CX = 0x100 };
 
 // One register segment: which local bits / global qubits the thread's
 // register slots and thread-id bits map to.
+// kind: SEG_KIND_REG (ops on amplitudes held in registers) or SEG_KIND_QUAD
+// (one dense two-qubit op applied directly to the tile in LDS).
+enum : int32_t { SEG_KIND_REG = 0, SEG_KIND_QUAD = 1 };
+
 struct DevSeg {
+  int32_t kind;
   int32_t op_begin, op_end;
   uint8_t rpos[4];   // local bit position of register bit b
   uint8_t rq[4];     // global qubit of register bit b

@@ -50,7 +50,13 @@ struct HostOp {
   uint32_t need_mask() const;
 };
 
+// Segment kinds: a register segment applies one-qubit, controlled-X and
+// diagonal ops to amplitudes held in registers; a quad segment applies one
+// dense two-qubit op directly to the tile in LDS.
+enum SegKind : int { SEG_REG = 0, SEG_QUAD = 1 };
+
 struct Segment {
+  int kind = SEG_REG;
   int op_begin = 0, op_end = 0;       // into Plan::ops (application order)
   std::vector<int> reg_q;             // register qubits (global ids), size R
 };

@@ -55,7 +55,8 @@ struct Sched {
   // Schedule every ready op whose needed qubits are in `allowed`.  With
   // out != nullptr the schedule is committed and the ops appended in order;
   // otherwise heads are restored and only the count is returned.
-  int drain(uint64_t allowed, std::vector<int> *out) {
+  // mode 0: any op; mode 1: no dense two-qubit ops (register segments).
+  int drain(uint64_t allowed, std::vector<int> *out, int mode = 0) {
     std::vector<int> saved;
     if (!out) saved = head;
     int cnt = 0;
@@ -72,6 +73,7 @@ struct Sched {
         int other = (op.qa == q) ? op.qb : op.qa;
         if (other >= 0 && (head[other] >= (int)queue[other].size() || queue[other][head[other]] != i)) break;
         if ((uint64_t)op.need_mask() & ~allowed) break;
+        if (mode == 1 && op.cls == OPC_G2) break;
         head[q]++;
         if (other >= 0) {
           head[other]++;
@@ -85,6 +87,25 @@ struct Sched {
     return cnt;
   }
 
+  // A ready dense two-qubit op, or -1.
+  int ready_g2() const {
+    for (int q = 0; q < n; ++q) {
+      if (head[q] >= (int)queue[q].size()) continue;
+      int i = queue[q][head[q]];
+      const HostOp &op = (*ops)[i];
+      if (op.cls != OPC_G2) continue;
+      int other = (op.qa == q) ? op.qb : op.qa;
+      if (head[other] < (int)queue[other].size() && queue[other][head[other]] == i) return i;
+    }
+    return -1;
+  }
+
+  void commit(int i) {
+    const HostOp &op = (*ops)[i];
+    head[op.qa]++;
+    if (op.qb >= 0) head[op.qb]++;
+  }
+
   // Op index at the head of qubit q's queue (or a large value).
   int head_op(int q) const { return head[q] < (int)queue[q].size() ? queue[q][head[q]] : (1 << 30); }
 };
@@ -92,14 +113,14 @@ struct Sched {
 // Greedy choice of a qubit set of size k within `pool`, starting from
 // `base`: add one qubit at a time, taking the one that lets the most ops be
 // scheduled; ties go to the qubit whose next op comes first.
-uint64_t choose_set(Sched &s, uint64_t base, uint64_t pool, int k) {
+uint64_t choose_set(Sched &s, uint64_t base, uint64_t pool, int k, int mode = 0) {
   uint64_t set = base;
   int have = __builtin_popcountll(base);
   while (have < k) {
     int best = -1, best_cnt = -1, best_head = 1 << 30;
     for (int q = 0; q < s.n; ++q) {
       if (!((pool >> q) & 1) || ((set >> q) & 1)) continue;
-      int c = s.drain(set | (1ull << q), nullptr);
+      int c = s.drain(set | (1ull << q), nullptr, mode);
       int h = s.head_op(q);
       if (c > best_cnt || (c == best_cnt && h < best_head)) {
         best = q; best_cnt = c; best_head = h;
@@ -134,8 +155,8 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix) {
   const int n = c.n;
   const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
   for (const HostOp &op : ops)
-    if (__builtin_popcount(op.need_mask()) > R)
-      throw Error(NT_ERR_UNSUPPORTED, "a two-qubit dense gate needs at least 2 register qubits");
+    if (op.cls != OPC_G2 && __builtin_popcount(op.need_mask()) > R)
+      throw Error(NT_ERR_UNSUPPORTED, "internal: op needs more register qubits than the plan has");
 
   std::vector<int> all_ops(ops.size());
   std::iota(all_ops.begin(), all_ops.end(), 0);
@@ -172,9 +193,23 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix) {
       P.segs.push_back(sg);
     }
     while (!in.finished()) {
-      uint64_t rset = choose_set(in, 0, ps.local_mask, R);
+      // dense two-qubit ops go to quad segments as soon as they are ready
+      int g2 = in.ready_g2();
+      if (g2 >= 0) {
+        Segment sg;
+        sg.kind = SEG_QUAD;
+        sg.op_begin = (int)P.ops.size();
+        P.ops.push_back(ops[g2]);
+        sg.op_end = (int)P.ops.size();
+        for (int q = 0; q < n && (int)sg.reg_q.size() < R; ++q)
+          if ((ps.local_mask >> q) & 1) sg.reg_q.push_back(q);
+        in.commit(g2);
+        P.segs.push_back(sg);
+        continue;
+      }
+      uint64_t rset = choose_set(in, 0, ps.local_mask, R, 1);
       std::vector<int> sched;
-      in.drain(rset, &sched);
+      in.drain(rset, &sched, 1);
       if (sched.empty()) throw Error(NT_ERR_UNSUPPORTED, "segment planner made no progress");
       Segment sg;
       sg.op_begin = (int)P.ops.size();

@@ -141,8 +141,10 @@ def _check_plan(P, c, prec):
         need = _needs(c.gates[g])
         pm = int(ex["pass_local_mask"][ex["op_pass"][o]])
         sm = int(ex["segment_reg_mask"][ex["op_segment"][o]])
+        dense2 = c.gates[g].name in ("SWAP", "U2Q")       # applied in LDS, not registers
         for q in need:
-            assert (pm >> q) & 1 and (sm >> q) & 1
+            assert (pm >> q) & 1
+            assert dense2 or (sm >> q) & 1
     assert np.all(np.diff(ex["op_pass"]) >= 0) and np.all(np.diff(ex["op_segment"]) >= 0)
     P.nt_circuit_free(h)
     return npass, og
