@@ -110,31 +110,45 @@ static std::vector<int> thread_bit_order(const std::vector<int> &tpos, int SW) {
   return first;
 }
 
-// rsel per op (computed with the pass layouts): register bit of the dense
-// qubit for register-segment ops, tile-local positions for quad ops.
+// Dispatch code of a register-segment op (kind * 4 + register bit of the
+// target) or of a quad op; rbit: the target's register bit (or 0).
+static int32_t op_code(const HostOp &h, int rbit) {
+  auto real = [](cd v) { return v.imag() == 0.0; };
+  auto imag = [](cd v) { return v.real() == 0.0; };
+  switch (h.cls) {
+    case OPC_G1:
+      if (real(h.m[0]) && real(h.m[1]) && real(h.m[2]) && real(h.m[3])) return ntk::OPK_G1R * 4 + rbit;
+      if (h.m[0] == h.m[3] && real(h.m[0]) && h.m[1] == h.m[2] && imag(h.m[1])) return ntk::OPK_G1X * 4 + rbit;
+      return ntk::OPK_G1 * 4 + rbit;
+    case OPC_C1:
+      if (!(h.m[0] == cd(0) && h.m[1] == cd(1) && h.m[2] == cd(1) && h.m[3] == cd(0)))
+        throw Error(NT_ERR_UNSUPPORTED, "internal: controlled op other than CNOT");
+      return ntk::OPK_CX * 4 + rbit;
+    case OPC_D1: return ntk::OPK_D1 * 4;
+    case OPC_D2: return ntk::OPK_D2 * 4;
+    default: return ntk::OPK_G2 * 4;
+  }
+}
+
+// rsel / code per op are computed with the pass layouts (register bit of the
+// dense qubit for register-segment ops, tile-local positions for quad ops).
 template <typename T>
-static void upload_ops(DevPlan &dp, const std::vector<int32_t> &rsel, hipStream_t s) {
+static void upload_ops(DevPlan &dp, const std::vector<int32_t> &code, const std::vector<int32_t> &rsel,
+                       hipStream_t s) {
   const Plan &P = dp.plan;
   std::vector<ntk::DevOp<T>> ops(std::max<size_t>(P.ops.size(), 1));
   std::memset(ops.data(), 0, ops.size() * sizeof(ntk::DevOp<T>));
   for (size_t o = 0; o < P.ops.size(); ++o) {
     const HostOp &h = P.ops[o];
     ntk::DevOp<T> &d = ops[o];
-    d.cls = h.cls;
+    d.cls = code[o];
     d.qa = h.qa;
     d.qb = h.qb;
     d.rsel = rsel[o];
     int nent = 0;
     switch (h.cls) {
-      case OPC_G1: nent = 4; break;
-      case OPC_C1:
-        nent = 4;
-        if (!(h.m[0] == cd(0) && h.m[1] == cd(1) && h.m[2] == cd(1) && h.m[3] == cd(0)))
-          throw Error(NT_ERR_UNSUPPORTED, "internal: controlled op other than CNOT");
-        d.rsel |= ntk::RSEL_CX;
-        break;
+      case OPC_G1: case OPC_C1: case OPC_D2: nent = 4; break;
       case OPC_D1: nent = 2; break;
-      case OPC_D2: nent = 4; break;
       case OPC_G2: nent = 16; break;
     }
     for (int i = 0; i < nent; ++i) {
@@ -182,7 +196,7 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
   std::memset(segs.data(), 0, segs.size() * sizeof(ntk::DevSeg));
   std::vector<ntk::DevPass> dpass(P.passes.size());
   std::memset(dpass.data(), 0, dpass.size() * sizeof(ntk::DevPass));
-  std::vector<int32_t> rsel(P.ops.size(), 0);
+  std::vector<int32_t> rsel(P.ops.size(), 0), code(P.ops.size(), 0);
   for (size_t p = 0; p < P.passes.size(); ++p) {
     const Pass &ps = P.passes[p];
     std::vector<int> loc, nl;
@@ -206,11 +220,22 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
           const int pa = local_pos(h.qa), pb = local_pos(h.qb);
           if (pa >= L || pb >= L) throw Error(NT_ERR_UNSUPPORTED, "internal: quad op qubit not local");
           rsel[o] = pa | (pb << 4);
-        } else if (h.cls == OPC_G1 || h.cls == OPC_C1) {
-          auto it = std::find(sg.reg_q.begin(), sg.reg_q.end(), h.qa);
-          if (it == sg.reg_q.end()) throw Error(NT_ERR_UNSUPPORTED, "internal: dense op outside its segment's registers");
-          rsel[o] = (int32_t)(it - sg.reg_q.begin());
-        } else if (h.cls == OPC_G2) {
+          code[o] = op_code(h, 0);
+        } else if (h.cls == OPC_G1 || h.cls == OPC_C1 || h.cls == OPC_D1 || h.cls == OPC_D2) {
+          auto rmask = [&](int q) -> int32_t {
+            if (q < 0) return 0;
+            auto it = std::find(sg.reg_q.begin(), sg.reg_q.end(), q);
+            return it == sg.reg_q.end() ? 0 : (int32_t)(1u << (it - sg.reg_q.begin()));
+          };
+          const int32_t am = rmask(h.qa), bm = rmask(h.qb);
+          rsel[o] = am | (bm << 4);
+          int rb = 0;
+          if (h.cls == OPC_G1 || h.cls == OPC_C1) {
+            if (!am) throw Error(NT_ERR_UNSUPPORTED, "internal: dense op outside its segment's registers");
+            rb = __builtin_ctz((unsigned)am);
+          }
+          code[o] = op_code(h, rb);
+        } else {
           throw Error(NT_ERR_UNSUPPORTED, "internal: dense 2q op in a register segment");
         }
       }
@@ -238,8 +263,8 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
   dp->segs.ensure(segs.size() * sizeof(ntk::DevSeg));
   check_hip(hipMemcpyAsync(dp->segs.p, segs.data(), segs.size() * sizeof(ntk::DevSeg), hipMemcpyHostToDevice, stream),
             "upload segments");
-  if (pr == NT_C64) upload_ops<float>(*dp, rsel, stream);
-  else upload_ops<double>(*dp, rsel, stream);
+  if (pr == NT_C64) upload_ops<float>(*dp, code, rsel, stream);
+  else upload_ops<double>(*dp, code, rsel, stream);
 
   const size_t S = std::max<size_t>(P.app_site.size(), 1);
   std::vector<int32_t> ident(S);

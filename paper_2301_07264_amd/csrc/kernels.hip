@@ -143,21 +143,26 @@ DEV uint32_t swz(uint32_t j) {
 // Pauli frame update F <- P_q F for F = i^c X^x Z^z (P = X: x ^= q;
 // P = Z: c += 2 x_q, z ^= q; P = Y = iXZ: c += 1 + 2 x_q, x ^= q, z ^= q).
 // Written without branches so the frame stays in scalar registers.
+// The frame is the same for the whole work-group (one trajectory); the
+// readfirstlane keeps it, and all conjugations derived from it, scalar.
 DEV void frame_apply(uint32_t e, uint32_t &fx, uint32_t &fz, uint32_t &fc) {
   const uint32_t q = (e >> 2) & 31u, p = e & 3u, bit = 1u << q;
   const uint32_t xq = (fx >> q) & 1u;
   const uint32_t has_x = (p == 1u || p == 2u) ? 1u : 0u;
   const uint32_t has_z = (p >= 2u) ? 1u : 0u;
   const uint32_t dc = (p == 2u ? 1u : 0u) + has_z * 2u * xq;
-  fx = fx ^ (has_x * bit);
-  fz = fz ^ (has_z * bit);
-  fc = fc + dc;
+  fx = __builtin_amdgcn_readfirstlane(fx ^ (has_x * bit));
+  fz = __builtin_amdgcn_readfirstlane(fz ^ (has_z * bit));
+  fc = __builtin_amdgcn_readfirstlane(fc + dc);
 }
 
 // ---------------------------------------------------------------------------
 // Register-slot gate application.  v[r] holds the amplitude whose register
-// bits are r; a dense op acts on register bit B (and B1).
+// bits are r; a dense op acts on the pairs (r, r | 1 << B).  Every body is
+// specialized at compile time on B; the host picks the body through a flat
+// dispatch code (OpCode), so that each op is one jump.
 
+// general complex 2x2: 16 FMA per pair
 template <int B, int R, typename T>
 DEV void g1_apply(cx<T> (&v)[1 << R], cx<T> m00, cx<T> m01, cx<T> m10, cx<T> m11) {
 #pragma unroll
@@ -166,13 +171,36 @@ DEV void g1_apply(cx<T> (&v)[1 << R], cx<T> m00, cx<T> m01, cx<T> m10, cx<T> m11
     const cx<T> x = v[r], y = v[r | (1 << B)];
     v[r] = mac2(m00, x, m01, y);
     v[r | (1 << B)] = mac2(m10, x, m11, y);
-    __builtin_amdgcn_sched_barrier(0);   // one pair at a time: bounded register use
+  }
+}
+
+// real 2x2 (H, RY, X, and their frame conjugates): 8 FMA per pair
+template <int B, int R, typename T>
+DEV void g1r_apply(cx<T> (&v)[1 << R], T m00, T m01, T m10, T m11) {
+#pragma unroll
+  for (int r = 0; r < (1 << R); ++r) {
+    if (r & (1 << B)) continue;
+    const cx<T> x = v[r], y = v[r | (1 << B)];
+    v[r] = cx<T>{fmat(m01, y.x, m00 * x.x), fmat(m01, y.y, m00 * x.y)};
+    v[r | (1 << B)] = cx<T>{fmat(m11, y.x, m10 * x.x), fmat(m11, y.y, m10 * x.y)};
+  }
+}
+
+// [[c, i w], [i w, c]] with c, w real (RX(t): c = cos t/2, w = -sin t/2; a
+// Z in the frame flips w, an X leaves it): 8 FMA per pair
+template <int B, int R, typename T>
+DEV void g1x_apply(cx<T> (&v)[1 << R], T c, T w) {
+#pragma unroll
+  for (int r = 0; r < (1 << R); ++r) {
+    if (r & (1 << B)) continue;
+    const cx<T> x = v[r], y = v[r | (1 << B)];
+    v[r] = cx<T>{fmat(-w, y.y, c * x.x), fmat(w, y.x, c * x.y)};
+    v[r | (1 << B)] = cx<T>{fmat(-w, x.y, c * y.x), fmat(w, x.x, c * y.y)};
   }
 }
 
 // Controlled +-X on register bit B (a CNOT conjugated by the frame: the
-// target's X part leaves X unchanged, its Z part flips the sign).  sbit is
-// the IEEE sign mask to XOR in (0 or the sign bit), uniform.
+// target's X part leaves X unchanged, its Z part flips the sign).
 template <typename T> struct SignBits;
 template <> struct SignBits<float> {
   using U = uint32_t;
@@ -187,58 +215,35 @@ template <> struct SignBits<double> {
   static constexpr U sign = 0x8000000000000000ull;
 };
 
+// take_lane: control condition for a control outside the registers (per
+// lane); cmask: register bit of the control (0 if none); creg: whether a set
+// register control bit satisfies the control value (uniform).
 template <int B, int R, typename T>
-DEV void cx_apply(cx<T> (&v)[1 << R], typename SignBits<T>::U sbit, uint32_t clane, uint32_t cmask, uint32_t cv) {
+DEV void cx_apply(cx<T> (&v)[1 << R], bool neg, bool take_lane, uint32_t cmask, bool creg) {
   using SB = SignBits<T>;
+  const typename SB::U sbit = neg ? SB::sign : 0;
 #pragma unroll
   for (int r = 0; r < (1 << R); ++r) {
     if (r & (1 << B)) continue;
     const cx<T> x = v[r], y = v[r | (1 << B)];
-    const bool take = (clane | (((uint32_t)r & cmask) ? 1u : 0u)) == cv;
-    const cx<T> ny{SB::flip(y.x, sbit), SB::flip(y.y, sbit)};
-    const cx<T> nx{SB::flip(x.x, sbit), SB::flip(x.y, sbit)};
-    v[r] = take ? ny : x;
-    v[r | (1 << B)] = take ? nx : y;
+    const bool take = ((uint32_t)r & cmask) ? creg : take_lane;
+    if (neg) {
+      const cx<T> ny{SB::flip(y.x, sbit), SB::flip(y.y, sbit)};
+      const cx<T> nx{SB::flip(x.x, sbit), SB::flip(x.y, sbit)};
+      v[r] = take ? ny : x;
+      v[r | (1 << B)] = take ? nx : y;
+    } else {
+      v[r] = take ? y : x;
+      v[r | (1 << B)] = take ? x : y;
+    }
   }
-}
-
-template <int R, typename T>
-DEV void dispatch_cx(int B, cx<T> (&v)[1 << R], typename SignBits<T>::U sbit, uint32_t clane, uint32_t cmask,
-                     uint32_t cv) {
-  switch (B) {
-    case 0: cx_apply<0, R>(v, sbit, clane, cmask, cv); break;
-    case 1: if constexpr (R > 1) cx_apply<1, R>(v, sbit, clane, cmask, cv); break;
-    case 2: if constexpr (R > 2) cx_apply<2, R>(v, sbit, clane, cmask, cv); break;
-    case 3: if constexpr (R > 3) cx_apply<3, R>(v, sbit, clane, cmask, cv); break;
-    default: break;
-  }
-}
-
-template <int R, typename T>
-DEV void dispatch_g1(int B, cx<T> (&v)[1 << R], cx<T> m00, cx<T> m01, cx<T> m10, cx<T> m11) {
-  switch (B) {
-    case 0: g1_apply<0, R>(v, m00, m01, m10, m11); break;
-    case 1: if constexpr (R > 1) g1_apply<1, R>(v, m00, m01, m10, m11); break;
-    case 2: if constexpr (R > 2) g1_apply<2, R>(v, m00, m01, m10, m11); break;
-    case 3: if constexpr (R > 3) g1_apply<3, R>(v, m00, m01, m10, m11); break;
-    default: break;
-  }
-}
-
-// Register bits of the segment that hold qubit q (0 or one bit), uniform.
-template <int R>
-DEV uint32_t reg_mask(const uint32_t (&rq)[R], uint32_t q) {
-  uint32_t m = 0;
-#pragma unroll
-  for (int b = 0; b < R; ++b) m |= (rq[b] == q ? 1u : 0u) << b;
-  return m;
 }
 
 // Header and the first four complex matrix entries of an op: everything a
 // register-segment op needs (read with scalar loads, one op ahead).
 template <typename T>
 struct OpLite {
-  int32_t cls, qa, qb, rsel;
+  int32_t code, qa, qb, rsel;
   T m[8];
 };
 
@@ -246,7 +251,7 @@ template <typename T>
 DEV OpLite<T> load_lite(const DevOp<T> *ops, int o) {
   const DevOp<T> &op = ops[o];
   OpLite<T> h;
-  h.cls = op.cls;
+  h.code = op.cls;
   h.qa = op.qa;
   h.qb = op.qb;
   h.rsel = op.rsel;
@@ -267,55 +272,100 @@ DEV cx<T> perm4(const OpLite<T> &h, int i, uint32_t xm) {
   return xm == 0u ? e0 : (xm == 1u ? e1 : (xm == 2u ? e2 : e3));
 }
 
+// Diagonal on one qubit: a uniform phase per slot when the qubit is a
+// register qubit, one phase per lane otherwise.
+template <int R, typename T>
+DEV void d1_apply(cx<T> (&v)[1 << R], cx<T> d0, cx<T> d1, uint32_t lane, uint32_t am) {
+  if (am) {
+#pragma unroll
+    for (int r = 0; r < (1 << R); ++r) v[r] = cmul(((uint32_t)r & am) ? d1 : d0, v[r]);
+  } else {
+    const cx<T> d = lane ? d1 : d0;
+#pragma unroll
+    for (int r = 0; r < (1 << R); ++r) v[r] = cmul(d, v[r]);
+  }
+}
+
+// Diagonal on two qubits, entries d[b_a + 2 b_b].
+template <int R, typename T>
+DEV void d2_apply(cx<T> (&v)[1 << R], cx<T> d0, cx<T> d1, cx<T> d2, cx<T> d3, uint32_t la, uint32_t lb,
+                  uint32_t am, uint32_t bm) {
+  if (!am && !bm) {
+    const cx<T> d = lb ? (la ? d3 : d2) : (la ? d1 : d0);
+#pragma unroll
+    for (int r = 0; r < (1 << R); ++r) v[r] = cmul(d, v[r]);
+  } else if (am && bm) {
+#pragma unroll
+    for (int r = 0; r < (1 << R); ++r) {
+      const bool ba = ((uint32_t)r & am) != 0, bb = ((uint32_t)r & bm) != 0;
+      v[r] = cmul(bb ? (ba ? d3 : d2) : (ba ? d1 : d0), v[r]);
+    }
+  } else if (am) {
+    const cx<T> p0 = lb ? d2 : d0, p1 = lb ? d3 : d1;   // by the register bit of qa
+#pragma unroll
+    for (int r = 0; r < (1 << R); ++r) v[r] = cmul(((uint32_t)r & am) ? p1 : p0, v[r]);
+  } else {
+    const cx<T> p0 = la ? d1 : d0, p1 = la ? d3 : d2;   // by the register bit of qb
+#pragma unroll
+    for (int r = 0; r < (1 << R); ++r) v[r] = cmul(((uint32_t)r & bm) ? p1 : p0, v[r]);
+  }
+}
+
 // Apply one register-segment op, conjugated by the current Pauli frame, to
 // the register slots.  gb: the thread's global index with all register bits
-// zero; rq: global qubit of each register bit.  Index bit q of slot r is
-// ((gb >> q) & 1) | (r & reg_mask(q) != 0).
+// zero.  Index bit q of slot r is ((gb >> q) & 1) | (r & mask(q) != 0), where
+// mask(q) is the register bit holding q (0 if none).  Conjugation by X^x Z^z of a 2x2
+// M gives entries (i, j) = (-1)^{z(i+j)} M[i^x][j^x].
 template <int R, typename T>
-DEV void apply_reg_op(const OpLite<T> &op, cx<T> (&v)[1 << R], uint32_t gb, const uint32_t (&rq)[R],
-                      uint32_t fx, uint32_t fz) {
-  constexpr int NS = 1 << R;
-  const int cls = op.cls;
+DEV void apply_reg_op(const OpLite<T> &op, cx<T> (&v)[1 << R], uint32_t gb, uint32_t fx, uint32_t fz) {
+  const int code = op.code;
   const uint32_t qa = (uint32_t)op.qa;
   const uint32_t xa = (fx >> qa) & 1u, za = (fz >> qa) & 1u;
-  if (cls == OP_C1) {
-    // controlled X: conjugation by X^x Z^z on the target gives (-1)^z X; an
-    // X on the control flips the control value.
-    const uint32_t qc = (uint32_t)op.qb;
-    const uint32_t cv = 1u ^ ((fx >> qc) & 1u);
-    const typename SignBits<T>::U sbit = za ? SignBits<T>::sign : 0;
-    dispatch_cx<R, T>(op.rsel & 15, v, sbit, (gb >> qc) & 1u, reg_mask<R>(rq, qc), cv);
-  } else if (cls == OP_G1) {
-    // (Z^z X^x) M (X^x Z^z): entry (i, j) = (-1)^{z(i+j)} M[i^x][j^x]
-    const cx<T> m00 = lent(op, 0), m01 = lent(op, 1), m10 = lent(op, 2), m11 = lent(op, 3);
-    cx<T> c00 = xa ? m11 : m00, c01 = xa ? m10 : m01, c10 = xa ? m01 : m10, c11 = xa ? m00 : m11;
-    if (za) {
-      c01 = cneg(c01);
-      c10 = cneg(c10);
+  // rsel: register-bit masks of qa (bits 0..3) and qb (bits 4..7) in this
+  // op's segment (0 when the qubit is not a register qubit), from the host.
+  const uint32_t am = (uint32_t)op.rsel & 15u, bm = ((uint32_t)op.rsel >> 4) & 15u;
+  // dense general 2x2
+  const cx<T> m00 = lent(op, 0), m01 = lent(op, 1), m10 = lent(op, 2), m11 = lent(op, 3);
+  cx<T> c00 = xa ? m11 : m00, c01 = xa ? m10 : m01, c10 = xa ? m01 : m10, c11 = xa ? m00 : m11;
+  if (za) {
+    c01 = cneg(c01);
+    c10 = cneg(c10);
+  }
+  // controlled X (control qb)
+  const uint32_t qc = (uint32_t)op.qb;
+  const uint32_t cv = 1u ^ ((fx >> qc) & 1u);
+  switch (code) {
+#define NT_G1(b)                                                                          \
+  case OPK_G1 * 4 + b:                                                                    \
+    if constexpr (b < R) g1_apply<b, R>(v, c00, c01, c10, c11);                           \
+    break;                                                                                \
+  case OPK_G1R * 4 + b:                                                                   \
+    if constexpr (b < R) g1r_apply<b, R>(v, c00.x, c01.x, c10.x, c11.x);                  \
+    break;                                                                                \
+  case OPK_G1X * 4 + b:                                                                   \
+    if constexpr (b < R) g1x_apply<b, R>(v, m00.x, za ? -m01.y : m01.y);                  \
+    break;                                                                                \
+  case OPK_CX * 4 + b:                                                                    \
+    if constexpr (b < R) cx_apply<b, R>(v, za != 0u, ((gb >> qc) & 1u) == cv, bm, cv == 1u); \
+    break;
+    NT_G1(0)
+    NT_G1(1)
+    NT_G1(2)
+    NT_G1(3)
+#undef NT_G1
+    case OPK_D1 * 4: {
+      d1_apply<R>(v, xa ? m01 : m00, xa ? m00 : m01, (gb >> qa) & 1u, am);
+      break;
     }
-    dispatch_g1<R>(op.rsel & 15, v, c00, c01, c10, c11);
-  } else if (cls == OP_D1) {
-    const cx<T> e0 = lent(op, 0), e1 = lent(op, 1);
-    const cx<T> d0 = xa ? e1 : e0, d1 = xa ? e0 : e1;
-    const uint32_t lane = (gb >> qa) & 1u, am = reg_mask<R>(rq, qa);
-#pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      const bool hi = lane | (((uint32_t)r & am) ? 1u : 0u);
-      v[r] = cmul(hi ? d1 : d0, v[r]);
+    case OPK_D2 * 4: {
+      const uint32_t qb = (uint32_t)op.qb;
+      const uint32_t xm = xa | (((fx >> qb) & 1u) << 1);
+      d2_apply<R>(v, perm4(op, 0, xm), perm4(op, 1, xm), perm4(op, 2, xm), perm4(op, 3, xm), (gb >> qa) & 1u,
+                  (gb >> qb) & 1u, am, bm);
+      break;
     }
-  } else if (cls == OP_D2) {
-    const uint32_t qb = (uint32_t)op.qb;
-    const uint32_t xm = xa | (((fx >> qb) & 1u) << 1);
-    const cx<T> d0 = perm4(op, 0, xm), d1 = perm4(op, 1, xm), d2 = perm4(op, 2, xm), d3 = perm4(op, 3, xm);
-    const uint32_t la = (gb >> qa) & 1u, lb = (gb >> qb) & 1u;
-    const uint32_t am = reg_mask<R>(rq, qa), bm = reg_mask<R>(rq, qb);
-#pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      const bool ba = la | (((uint32_t)r & am) ? 1u : 0u);
-      const bool bb = lb | (((uint32_t)r & bm) ? 1u : 0u);
-      const cx<T> d = bb ? (ba ? d3 : d2) : (ba ? d1 : d0);
-      v[r] = cmul(d, v[r]);
-    }
+    default:
+      break;
   }
 }
 
@@ -410,7 +460,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   uint32_t dlo = 0;
   for (int i = 0; i < lt; ++i) dlo |= ((tid >> i) & 1u) << ps.locq[i];
   // Global-index bits of the coalesced layout's slot k: OR of hbit[b] over
-  // the set bits b of k.
+  // the set bits b of k (uniform).
   uint32_t hbit[R];
 #pragma unroll
   for (int bb = 0; bb < R; ++bb) hbit[bb] = 1u << ps.locq[lt + bb];
@@ -421,32 +471,39 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
       if ((k >> bb) & 1) v |= hbit[bb];
     return v;
   };
+  // The swizzle is linear over GF(2), so the LDS byte offset of coalesced
+  // slot k is swz(tid) ^ swz(k * NT), the second term uniform.
+  const uint32_t lds_tid = swz<T>(tid) * (uint32_t)sizeof(cx<T>);
+  auto lds_k = [&](int k) -> cx<T> & {
+    return *reinterpret_cast<cx<T> *>(smem_raw + (lds_tid ^ (swz<T>((uint32_t)k * NT) * (uint32_t)sizeof(cx<T>))));
+  };
+  const cx<T> *sp = st + (tilebase | dlo);   // dhi(k) bits are disjoint from tilebase | dlo
 
   // Load the tile (coalesced: thread-id bits are the low local bits).
   if (a.flags & PF_FIRST) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const uint32_t g = tilebase | dlo | dhi(k);
-      lds[swz<T>((uint32_t)k * NT + tid)] = cx<T>{g == a.init_index ? T(1) : T(0), T(0)};
+      lds_k(k) = cx<T>{g == a.init_index ? T(1) : T(0), T(0)};
     }
   } else {
     cx<T> v[NS];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) v[k] = st[tilebase | dlo | dhi(k)];
+    for (int k = 0; k < NS; ++k) v[k] = sp[dhi(k)];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) lds[swz<T>((uint32_t)k * NT + tid)] = v[k];
+    for (int k = 0; k < NS; ++k) lds_k(k) = v[k];
   }
   __syncthreads();
 
   // Pauli frame at the start of this pass; next_op is the op index of the
   // trajectory's next error event (~0 when there is none).
   const uint32_t *ev = a.events + (size_t)b * a.ev_stride;
-  const int ne = a.ev_count[b];
+  const int ne = __builtin_amdgcn_readfirstlane(a.ev_count[b]);
   int ep = 0;
   uint32_t fx = 0, fz = 0, fc = 0;
   uint32_t next_e = 0, next_op = 0xffffffffu;
   while (ep < ne) {
-    next_e = ev[ep];
+    next_e = __builtin_amdgcn_readfirstlane(ev[ep]);
     if ((int)(next_e >> 8) >= a.op_begin) break;
     frame_apply(next_e, fx, fz, fc);
     ++ep;
@@ -457,7 +514,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
       frame_apply(next_e, fx, fz, fc);
       ++ep;
       if (ep < ne) {
-        next_e = ev[ep];
+        next_e = __builtin_amdgcn_readfirstlane(ev[ep]);
         next_op = next_e >> 8;
       } else {
         next_op = 0xffffffffu;
@@ -479,34 +536,34 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
       jb |= bit << sg.tpos[i];
       gb |= bit << sg.tq[i];
     }
-    uint32_t jbit[R], rq[R];
+    // LDS byte offset of slot r: swz(jb) ^ XOR of swz(bit of register b) over
+    // the set bits b of r (linear swizzle; the second term is uniform).
+    uint32_t sbit[R];
 #pragma unroll
-    for (int bb = 0; bb < R; ++bb) {
-      jbit[bb] = 1u << sg.rpos[bb];
-      rq[bb] = sg.rq[bb];
-    }
-    auto jaddr = [&](int r) {
-      uint32_t j = jb;
+    for (int bb = 0; bb < R; ++bb) sbit[bb] = swz<T>(1u << sg.rpos[bb]) * (uint32_t)sizeof(cx<T>);
+    const uint32_t sjb = swz<T>(jb) * (uint32_t)sizeof(cx<T>);
+    auto slot = [&](int r) -> cx<T> & {
+      uint32_t u = 0;
 #pragma unroll
       for (int bb = 0; bb < R; ++bb)
-        if ((r >> bb) & 1) j |= jbit[bb];
-      return swz<T>(j);
+        if ((r >> bb) & 1) u ^= sbit[bb];
+      return *reinterpret_cast<cx<T> *>(smem_raw + (sjb ^ u));
     };
     cx<T> v[NS];
 #pragma unroll
-    for (int r = 0; r < NS; ++r) v[r] = lds[jaddr(r)];
+    for (int r = 0; r < NS; ++r) v[r] = slot(r);
     if (sg.op_begin < sg.op_end) {
       OpLite<T> cur = load_lite(a.ops, sg.op_begin);
       for (int o = sg.op_begin; o < sg.op_end; ++o) {
         OpLite<T> nxt = cur;
         if (o + 1 < sg.op_end) nxt = load_lite(a.ops, o + 1);   // next op's loads in flight
-        apply_reg_op<R, T>(cur, v, gb, rq, fx, fz);
+        apply_reg_op<R, T>(cur, v, gb, fx, fz);
         take_events(o);
         cur = nxt;
       }
     }
 #pragma unroll
-    for (int r = 0; r < NS; ++r) lds[jaddr(r)] = v[r];
+    for (int r = 0; r < NS; ++r) slot(r) = v[r];
     __syncthreads();
   }
 
@@ -519,7 +576,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const uint32_t g = tilebase | dlo | dhi(k);
-      const cx<T> s = lds[swz<T>((uint32_t)k * NT + tid)];
+      const cx<T> s = lds_k(k);
       const cx<T> r = a.ref[g ^ fx];
       double sr = (double)s.x, si = (double)s.y;
       if (__popc(fz & g) & 1u) {
@@ -537,7 +594,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const uint32_t g = tilebase | dlo | dhi(k);
-      const cx<T> s = lds[swz<T>((uint32_t)k * NT + tid)];
+      const cx<T> s = lds_k(k);
       st[g] = s;
       const double sr = (double)s.x, si = (double)s.y;
       nrm = __dadd_rn(nrm, __fma_rn(si, si, __dmul_rn(sr, sr)));

@@ -12,12 +12,11 @@ struct alignas(2 * sizeof(T)) cx {
 };
 
 // One gate of the plan, as the kernels read it (uniform per work-group).
-//   cls  : op class (G1 dense 2x2, D1 diagonal 1q, C1 controlled 2x2,
-//          D2 diagonal 2q, G2 dense 4x4)
+//   cls  : dispatch code (OPK_* kind * 4 + register bit of the target)
 //   qa,qb: qubits (C1: qa = target, qb = control)
-//   rsel : G1 / C1: register bit of qa in the segment that applies the op;
-//          G2: tile-local bit positions of qa (bits 0..3) and qb (bits 4..7);
-//          RSEL_CX marks a controlled X (the only C1 the host emits)
+//   rsel : register-segment ops: register-bit masks of qa (bits 0..3) and qb
+//          (bits 4..7) in the op's segment, 0 for a non-register qubit;
+//          G2: tile-local bit positions of qa (bits 0..3) and qb (bits 4..7)
 //   m    : matrix data, (re, im) interleaved; G1/C1 2x2 row-major, D1 (d0,d1),
 //          D2 (d0..d3) on local index b_qa + 2 b_qb, G2 4x4 row-major
 template <typename T>
@@ -26,9 +25,17 @@ struct DevOp {
   T m[32];
 };
 
-enum : int32_t { OP_G1 = 0, OP_D1 = 1, OP_C1 = 2, OP_D2 = 3, OP_G2 = 4 };
-// rsel flag: the C1 op's target matrix is exactly X (a CNOT).
-enum : int32_t { RSEL_CX = 0x100 };
+// Op dispatch codes: kind * 4 + register bit (kinds with a register target)
+// or kind * 4 (diagonal kinds).  G2 ops live in quad segments.
+enum : int32_t {
+  OPK_G1 = 0,   // general complex 2x2, m = 4 entries
+  OPK_G1R = 1,  // real 2x2 (imaginary parts zero)
+  OPK_G1X = 2,  // [[c, -i s], [-i s, c]]: m00 = c, m01 = -i s
+  OPK_CX = 3,   // controlled X: qa target, qb control
+  OPK_D1 = 4,   // diagonal (d0, d1) on qa
+  OPK_D2 = 5,   // diagonal (d0..d3) on local index b_qa + 2 b_qb
+  OPK_G2 = 6,   // dense 4x4 (quad segment)
+};
 
 // One register segment: which local bits / global qubits the thread's
 // register slots and thread-id bits map to.
