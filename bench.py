@@ -46,6 +46,10 @@ def main():
     ap.add_argument("--cpu-traj", type=int, default=1, help="oracle trajectories timed on the host")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON file with measured HBM bytes per pass launch (rocprofv3 counters)")
+    ap.add_argument("--ttr", action="store_true",
+                    help="also time the tolerable-rate search (P* = 0.66 +- 0.01, 10^4 trajectories per probe, "
+                         "exact short-cuts on)")
+    ap.add_argument("--ttr-traj", type=int, default=10000)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device copy of this many bytes (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -141,6 +145,38 @@ def main():
         with open(args.traffic) as f:
             traffic = json.load(f).get("bytes_per_launch")
 
+    ttr = None
+    if args.ttr:
+        # Time-to-tolerable-rate: regula falsi (Illinois) in log10 p with the
+        # same trajectories at every probe.  Zero-fired trajectories and
+        # error-free prefixes are not simulated (bit-identical results), and a
+        # trajectory is scored after its last error against the error-free
+        # state there (the common unitary suffix keeps the overlap: exact in
+        # arithmetic, equal to the full run up to rounding).
+        P.nt_set_shortcuts(ctx, P.NT_SHORTCUT_ZERO_FIRED | P.NT_SHORTCUT_CHECKPOINT | P.NT_SHORTCUT_LAST_ERROR)
+        P.nt_set_max_batch(ctx, 0)
+        print("bench: timing the tolerable-rate search ...", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        # upper end: the tolerable rate is below 1/G whenever the target exceeds
+        # the one-error success probability (Sec. IV-D); widen if not bracketed
+        bracket = [1e-5, 1.0 / G]
+        try:
+            p_star, probes = P.nt_tolerable_rate(ctx, h, 0.66, 0.01, bracket[0], bracket[1], 0, args.ttr_traj, tau)
+        except P.NtError as e:
+            if e.status != P.NT_ERR_NOT_BRACKETED:
+                raise
+            bracket = [1e-5, 1e-2]
+            p_star, probes = P.nt_tolerable_rate(ctx, h, 0.66, 0.01, bracket[0], bracket[1], 0, args.ttr_traj, tau)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        P.nt_set_shortcuts(ctx, 0)
+        ttr = {"seconds": dt, "p_star": p_star, "probes": probes, "P_target": 0.66, "tol": 0.01,
+               "trajectories_per_probe": args.ttr_traj, "bracket": bracket, "search": "Illinois in log10 p",
+               "shortcuts": "zero-fired skipped and start at the first-error checkpoint (bit-identical); "
+                            "scored after the last error (exact in arithmetic)",
+               "one_over_G": 1.0 / G}
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -200,6 +236,7 @@ def main():
                    "tile_qubits": L, "parallelism": "single GPU, trajectory batch"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "time_to_tolerable_rate": ttr,
         "successes": state["count"],
         "trajectories": n_traj,
     }

@@ -164,15 +164,63 @@ nt_status nt_run(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_
 nt_status nt_sweep(nt_ctx *ctx, const nt_circuit *c, const double *rates, int R, uint64_t seed,
                    uint64_t n_traj, double tau, double *p_out);
 
-/* Tolerable uniform rate (Sec. IV-D, Monte Carlo branch, Fig. 3): bisection
- * in log10(p) over [p_lo, p_hi] with the same trajectories [0, n_traj) at
- * every probe.  Returns the first probe whose success probability is within
- * tol of P_target, else the midpoint once p_hi/p_lo <= 1.001.
+/* Tolerable uniform rate (Sec. IV-D, Monte Carlo branch, Fig. 3).  The paper
+ * names Powell's method without its settings; here: a safeguarded regula
+ * falsi (Illinois) in x = log10(p) on f = P(10^x) - P_target over the
+ * bracket [p_lo, p_hi], with the same trajectories [0, n_traj) at every
+ * probe.  Each step probes the secant root of the bracket (its midpoint if
+ * the root falls outside); an end kept twice in a row has its f halved.
+ * Returns the first probe whose success probability is within tol of
+ * P_target, else the bracket midpoint once p_hi/p_lo <= 1.001.
  * NT_ERR_NOT_BRACKETED if P(p_lo) < P_target or P(p_hi) > P_target.
  * *n_probes counts every Monte Carlo evaluation, including the two ends. */
 nt_status nt_tolerable_rate(nt_ctx *ctx, const nt_circuit *c, double P_target, double tol,
                             double p_lo, double p_hi, uint64_t seed, uint64_t n_traj,
                             double tau, double *p_star, int *n_probes);
+
+/* Exact short-cuts for Monte Carlo runs (results stay bit-identical):
+ * NT_SHORTCUT_ZERO_FIRED -- a trajectory with no fired site ends in the
+ *   error-free state, so its fidelity is 1 without simulating it;
+ * NT_SHORTCUT_CHECKPOINT -- the error-free state before every pass is kept in
+ *   device memory and a trajectory starts at the pass holding its first
+ *   error (silently off when the checkpoints do not fit).
+ * NT_SHORTCUT_LAST_ERROR -- a trajectory is scored right after the pass
+ *   holding its last error, against the error-free state at that point: the
+ *   rest of the circuit is one unitary applied to both states and leaves
+ *   their overlap unchanged.  Exact in arithmetic; fidelities differ from
+ *   the full run by rounding only (needs the checkpoints).
+ * Default 0 (every trajectory simulated in full). */
+enum { NT_SHORTCUT_ZERO_FIRED = 1, NT_SHORTCUT_CHECKPOINT = 2, NT_SHORTCUT_LAST_ERROR = 4 };
+nt_status nt_set_shortcuts(nt_ctx *ctx, int flags);
+
+/* ---- exhaustive single-error branch (Sec. IV-B.1, IV-C, IV-D) ---------------- */
+
+/* Exhaustive Pauli error simulation (Sec. IV-B.1, Eq. 3): the circuit with
+ * exactly one X, Y or Z error at each of its S sites (3S runs), scored by
+ * the fidelity criterion.  fid_out (host, may be NULL): [S][3] fidelities,
+ * columns X, Y, Z.  P_e[0..2]: success probability averaged over the states
+ * with the same Pauli type (X, Y, Z); *P_R: success of the reference state
+ * (Sec. IV-C). */
+nt_status nt_exhaustive(nt_ctx *ctx, const nt_circuit *c, double tau, double *fid_out, double P_e[3],
+                        double *P_R);
+
+/* Eq. 4: P = sum_e P_e E_e + P_R (1 - sum_e E_e) for expected error counts
+ * E_e (e = X, Y, Z).  Host arithmetic. */
+nt_status nt_eq4(const double P_e[3], double P_R, const double E_e[3], double *P);
+
+/* Eq. 5: tolerable uniform rate p = (1/units) (P - P_R) / (sum_e P_e/3 - P_R)
+ * for target P; `units` is the number of error locations per circuit (the
+ * paper writes G; the site count S makes Eq. 4 the first-order term of the
+ * Monte Carlo model).  Host arithmetic; NT_ERR_INVALID_ARG if the
+ * denominator is zero. */
+nt_status nt_eq5(double P_target, const double P_e[3], double P_R, double units, double *p);
+
+/* Success probability with the paper's method switch (Sec. IV-C, Fig. 2):
+ * with E(N) = S (p_x + p_y + p_z) <= 1 expected errors, exhaustive
+ * simulation and Eq. 4 (E_e = S p_e); otherwise Monte Carlo over trajectories
+ * [0, n_traj).  *method: 0 = exhaustive + Eq. 4, 1 = Monte Carlo. */
+nt_status nt_success_probability(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t n_traj, double tau,
+                                 double *P, int *method);
 
 /* ---- parity and debug exports ---------------------------------------------- */
 

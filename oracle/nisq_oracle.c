@@ -42,8 +42,9 @@
  *     nested across rates (common random numbers);
  *   - the fidelity criterion is the indicator F >= tau, with
  *     F = |<R|psi>|^2 / (<R|R><psi|psi>);
- *   - the tolerable-rate search is a bisection in log10(p) on common random
- *     numbers (the paper names Powell's method without its settings).
+ *   - the tolerable-rate search is a safeguarded regula falsi (Illinois) in
+ *     log10(p) on common random numbers (the paper names Powell's method
+ *     without its settings).
  */
 #include <complex.h>
 #include <math.h>
@@ -518,39 +519,57 @@ int orc_sweep(int n, int64_t G, const int32_t *kind, const int32_t *q0, const in
   return 0;
 }
 
-/* Tolerable uniform rate (Sec. IV-D, MC branch): bisection in log10 p over
- * [p_lo, p_hi] with the same trajectories at every probe.  Returns the first
- * probe with |P - P*| <= tol, else the midpoint once p_hi/p_lo <= 1.001.
+/* Tolerable uniform rate (Sec. IV-D, MC branch; the paper names Powell's
+ * method without its settings, the reading here is a safeguarded regula falsi
+ * (Illinois) in x = log10 p on f(x) = P(10^x) - P*, with the same trajectories
+ * at every probe).  Start from the bracket [p_lo, p_hi]; each step probes the
+ * secant root of the bracket (the midpoint if that falls outside); returns the
+ * first probe with |P - P*| <= tol, else the bracket midpoint once
+ * p_hi/p_lo <= 1.001.  When one end is kept twice in a row, its f is halved.
  * Returns 1 if not bracketed (P(p_lo) < P* or P(p_hi) > P*). */
+static double mc_success(int n, int64_t G, const int32_t *kind, const int32_t *q0, const int32_t *q1,
+                         const double *params, const double *umats, double p, uint64_t seed, uint64_t cid,
+                         uint64_t N, double tau, int nthreads, int *rc) {
+  uint64_t cnt = 0;
+  double p3 = p / 3.0;
+  *rc = orc_run(n, G, kind, q0, q1, params, umats, p3, p3, p3, seed, cid, 0, N, tau, nthreads, NULL, &cnt, NULL);
+  return (double)cnt / (double)N;
+}
+
 int orc_tolerable_rate(int n, int64_t G, const int32_t *kind, const int32_t *q0,
                        const int32_t *q1, const double *params, const double *umats,
                        double P_target, double tol, double p_lo, double p_hi,
                        uint64_t seed, uint64_t cid, uint64_t N, double tau, int nthreads,
                        double *p_star, int *n_probes) {
-  uint64_t cnt;
-  double P_lo, P_hi;
-  int probes = 0, rc;
-  double l3 = p_lo / 3.0, h3 = p_hi / 3.0;
-  rc = orc_run(n, G, kind, q0, q1, params, umats, l3, l3, l3, seed, cid, 0, N, tau, nthreads, NULL, &cnt, NULL);
+  int rc, probes = 0;
+  double a = log10(p_lo), b = log10(p_hi);
+  double fa = mc_success(n, G, kind, q0, q1, params, umats, p_lo, seed, cid, N, tau, nthreads, &rc) - P_target;
   if (rc) return rc;
-  P_lo = (double)cnt / N; ++probes;
-  rc = orc_run(n, G, kind, q0, q1, params, umats, h3, h3, h3, seed, cid, 0, N, tau, nthreads, NULL, &cnt, NULL);
+  ++probes;
+  double fb = mc_success(n, G, kind, q0, q1, params, umats, p_hi, seed, cid, N, tau, nthreads, &rc) - P_target;
   if (rc) return rc;
-  P_hi = (double)cnt / N; ++probes;
+  ++probes;
   *n_probes = probes;
-  if (P_lo < P_target || P_hi > P_target) return 1;
-  double lo = log10(p_lo), hi = log10(p_hi);
+  if (fa < 0 || fb > 0) return 1;
+  int side = 0;
   for (;;) {
-    double mid = 0.5 * (lo + hi);
-    double pm = pow(10.0, mid);
-    if (pow(10.0, hi - lo) <= 1.001) { *p_star = pm; break; }
-    double m3 = pm / 3.0;
-    rc = orc_run(n, G, kind, q0, q1, params, umats, m3, m3, m3, seed, cid, 0, N, tau, nthreads, NULL, &cnt, NULL);
+    if (pow(10.0, b - a) <= 1.001) { *p_star = pow(10.0, 0.5 * (a + b)); break; }
+    double x = (fa == fb) ? 0.5 * (a + b) : (a * fb - b * fa) / (fb - fa);
+    if (!(x > a && x < b)) x = 0.5 * (a + b);
+    double px = pow(10.0, x);
+    double fx = mc_success(n, G, kind, q0, q1, params, umats, px, seed, cid, N, tau, nthreads, &rc) - P_target;
     if (rc) return rc;
     ++probes;
-    double P = (double)cnt / N;
-    if (fabs(P - P_target) <= tol) { *p_star = pm; break; }
-    if (P > P_target) lo = mid; else hi = mid;
+    if (fabs(fx) <= tol) { *p_star = px; break; }
+    if (fx > 0) {
+      a = x; fa = fx;
+      if (side == 1) fb *= 0.5;
+      side = 1;
+    } else {
+      b = x; fb = fx;
+      if (side == -1) fa *= 0.5;
+      side = -1;
+    }
   }
   *n_probes = probes;
   return 0;

@@ -45,7 +45,12 @@ EXPORTED = [
     "nt_circuit_set_id", "nt_plan_info", "nt_plan_export", "nt_run", "nt_sweep", "nt_tolerable_rate",
     "nt_sample_sites", "nt_final_state", "nt_reference_state", "nt_timing_enable",
     "nt_timing_reset", "nt_timing_read", "nt_last_error", "nt_version",
+    "nt_set_shortcuts", "nt_exhaustive", "nt_eq4", "nt_eq5", "nt_success_probability",
 ]
+
+NT_SHORTCUT_ZERO_FIRED = 1
+NT_SHORTCUT_CHECKPOINT = 2
+NT_SHORTCUT_LAST_ERROR = 4
 
 
 class nt_gate(C.Structure):
@@ -94,6 +99,11 @@ def lib() -> C.CDLL:
         "nt_timing_enable": ([P, i32], i32),
         "nt_timing_reset": ([P], i32),
         "nt_timing_read": ([P, P, P, P, P, P], i32),
+        "nt_set_shortcuts": ([P, i32], i32),
+        "nt_exhaustive": ([P, P, dbl, P, P, P], i32),
+        "nt_eq4": ([P, dbl, P, P], i32),
+        "nt_eq5": ([dbl, P, dbl, dbl, P], i32),
+        "nt_success_probability": ([P, P, u64, u64, dbl, P, P], i32),
         "nt_last_error": ([], C.c_char_p),
         "nt_version": ([], C.c_char_p),
     }
@@ -294,6 +304,43 @@ def nt_reference_state(ctx, circ, prec: int) -> np.ndarray:
     out = _state_buffer(circ, prec)
     _check(lib().nt_reference_state(ctx, circ, _ptr(out), out.size))
     return out
+
+
+def nt_set_shortcuts(ctx, flags: int) -> None:
+    _check(lib().nt_set_shortcuts(ctx, flags))
+
+
+def nt_exhaustive(ctx, circ, tau: float):
+    """Returns (fid[S, 3], P_e[3] (X, Y, Z), P_R)."""
+    _, _, S = nt_circuit_info(circ)
+    fid = np.zeros((max(S, 1), 3), np.float64)
+    pe = np.zeros(3, np.float64)
+    pr = C.c_double()
+    _check(lib().nt_exhaustive(ctx, circ, tau, _ptr(fid), _ptr(pe), C.byref(pr)))
+    return fid[:S], pe, pr.value
+
+
+def nt_eq4(P_e, P_R: float, E_e) -> float:
+    a = np.ascontiguousarray(P_e, np.float64)
+    b = np.ascontiguousarray(E_e, np.float64)
+    out = C.c_double()
+    _check(lib().nt_eq4(_ptr(a), P_R, _ptr(b), C.byref(out)))
+    return out.value
+
+
+def nt_eq5(P_target: float, P_e, P_R: float, units: float) -> float:
+    a = np.ascontiguousarray(P_e, np.float64)
+    out = C.c_double()
+    _check(lib().nt_eq5(P_target, _ptr(a), P_R, units, C.byref(out)))
+    return out.value
+
+
+def nt_success_probability(ctx, circ, seed: int, n_traj: int, tau: float):
+    """Returns (P, method) with method 0 = exhaustive + Eq. 4, 1 = Monte Carlo."""
+    P = C.c_double()
+    m = C.c_int()
+    _check(lib().nt_success_probability(ctx, circ, seed, n_traj, tau, C.byref(P), C.byref(m)))
+    return P.value, m.value
 
 
 def nt_timing_enable(ctx, enable: bool) -> None:

@@ -240,18 +240,31 @@ nt_status nt_tolerable_rate(nt_ctx *ctx, const nt_circuit *c, double P_target, d
       return (double)cnt / (double)n_traj;
     };
     try {
-      const double Plo = P_at(p_lo), Phi = P_at(p_hi);
-      if (Plo < P_target || Phi > P_target) {
+      // Safeguarded regula falsi (Illinois) in x = log10 p on
+      // f(x) = P(10^x) - P_target, same trajectories at every probe.
+      double a = std::log10(p_lo), b = std::log10(p_hi);
+      double fa = P_at(p_lo) - P_target;
+      double fb = P_at(p_hi) - P_target;
+      if (fa < 0 || fb > 0) {
         bracketed = false;
       } else {
-        double lo = std::log10(p_lo), hi = std::log10(p_hi);
+        int side = 0;
         for (;;) {
-          const double mid = 0.5 * (lo + hi);
-          const double pm = std::pow(10.0, mid);
-          if (std::pow(10.0, hi - lo) <= 1.001) { *p_star = pm; break; }
-          const double P = P_at(pm);
-          if (std::fabs(P - P_target) <= tol) { *p_star = pm; break; }
-          if (P > P_target) lo = mid; else hi = mid;
+          if (std::pow(10.0, b - a) <= 1.001) { *p_star = std::pow(10.0, 0.5 * (a + b)); break; }
+          double x = (fa == fb) ? 0.5 * (a + b) : (a * fb - b * fa) / (fb - fa);
+          if (!(x > a && x < b)) x = 0.5 * (a + b);
+          const double px = std::pow(10.0, x);
+          const double fx = P_at(px) - P_target;
+          if (std::fabs(fx) <= tol) { *p_star = px; break; }
+          if (fx > 0) {
+            a = x; fa = fx;
+            if (side == 1) fb *= 0.5;
+            side = 1;
+          } else {
+            b = x; fb = fx;
+            if (side == -1) fa *= 0.5;
+            side = -1;
+          }
         }
       }
     } catch (...) {
@@ -264,6 +277,76 @@ nt_status nt_tolerable_rate(nt_ctx *ctx, const nt_circuit *c, double P_target, d
   if (st) return st;
   if (!bracketed) return fail(NT_ERR_NOT_BRACKETED, "target success probability not bracketed by [p_lo, p_hi]");
   return NT_OK;
+}
+
+nt_status nt_set_shortcuts(nt_ctx *ctx, int flags) {
+  if (!ctx) return fail(NT_ERR_INVALID_ARG, "ctx is NULL");
+  if (flags & ~(NT_SHORTCUT_ZERO_FIRED | NT_SHORTCUT_CHECKPOINT | NT_SHORTCUT_LAST_ERROR))
+    return fail(NT_ERR_INVALID_ARG, "unknown shortcut flag");
+  ctx->impl->shortcuts = flags;
+  g_last_error.clear();
+  return NT_OK;
+}
+
+nt_status nt_exhaustive(nt_ctx *ctx, const nt_circuit *c, double tau, double *fid_out, double P_e[3],
+                        double *P_R) {
+  nt_status s = check_run_args(ctx, c, tau);
+  if (s) return s;
+  if (!P_e || !P_R) return fail(NT_ERR_INVALID_ARG, "P_e / P_R is NULL");
+  return guard([&] { ctx->impl->exhaustive(*c->impl, tau, fid_out, P_e, P_R); });
+}
+
+nt_status nt_eq4(const double P_e[3], double P_R, const double E_e[3], double *P) {
+  if (!P_e || !E_e || !P) return fail(NT_ERR_INVALID_ARG, "NULL argument");
+  double sum = 0, se = 0;
+  for (int e = 0; e < 3; ++e) {
+    sum += P_e[e] * E_e[e];
+    se += E_e[e];
+  }
+  *P = sum + P_R * (1.0 - se);
+  g_last_error.clear();
+  return NT_OK;
+}
+
+nt_status nt_eq5(double P_target, const double P_e[3], double P_R, double units, double *p) {
+  if (!P_e || !p) return fail(NT_ERR_INVALID_ARG, "NULL argument");
+  if (!(units > 0)) return fail(NT_ERR_INVALID_ARG, "units must be > 0");
+  const double avg = (P_e[0] + P_e[1] + P_e[2]) / 3.0;
+  if (avg == P_R) return fail(NT_ERR_INVALID_ARG, "single errors do not change the success probability");
+  *p = (P_target - P_R) / (avg - P_R) / units;
+  g_last_error.clear();
+  return NT_OK;
+}
+
+nt_status nt_success_probability(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t n_traj, double tau,
+                                 double *P, int *method) {
+  nt_status s = check_run_args(ctx, c, tau);
+  if (s) return s;
+  if (!P) return fail(NT_ERR_INVALID_ARG, "P is NULL");
+  return guard([&] {
+    nt::Ctx &cx = *ctx->impl;
+    const double S = (double)c->impl->S;
+    const double EN = S * (cx.px + cx.py + cx.pz);
+    if (EN <= 1.0) {
+      double P_e[3], P_R;
+      cx.exhaustive(*c->impl, tau, nullptr, P_e, &P_R);
+      // Pauli types in the order X, Y, Z
+      const double E_e[3] = {S * cx.px, S * cx.py, S * cx.pz};
+      double sum = 0, se = 0;
+      for (int e = 0; e < 3; ++e) {
+        sum += P_e[e] * E_e[e];
+        se += E_e[e];
+      }
+      *P = sum + P_R * (1.0 - se);
+      if (method) *method = 0;
+    } else {
+      if (n_traj == 0) throw nt::Error(NT_ERR_INVALID_ARG, "n_traj must be > 0 for the Monte Carlo branch");
+      uint64_t cnt = 0;
+      cx.run(*c->impl, seed, 0, n_traj, tau, nullptr, &cnt);
+      *P = (double)cnt / (double)n_traj;
+      if (method) *method = 1;
+    }
+  });
 }
 
 nt_status nt_sample_sites(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_begin, uint64_t n_traj,

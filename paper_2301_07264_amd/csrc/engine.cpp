@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <tuple>
 
 namespace nt {
 
@@ -191,6 +192,9 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
     }
     dp->pass_flops_per_amp.push_back(f);
   }
+  dp->pass_of_op.assign(P.ops.size(), 0);
+  for (size_t p = 0; p < P.passes.size(); ++p)
+    for (int o = P.passes[p].op_begin; o < P.passes[p].op_end; ++o) dp->pass_of_op[o] = (int)p;
 
   std::vector<ntk::DevSeg> segs(std::max<size_t>(P.segs.size(), 1));
   std::memset(segs.data(), 0, segs.size() * sizeof(ntk::DevSeg));
@@ -339,14 +343,20 @@ void Ctx::timing_flush() {
   ev_flops.clear();
 }
 
+// One launch of every pass of the plan over a batch.  With `start`, batch
+// entries are sorted by their first pass and pass p runs the prefix
+// active[p] of them; entries starting at p > 0 load the error-free checkpoint
+// taken before pass p.  With `capture`, the state of entry 0 is copied into
+// the checkpoint slots after each pass (error-free reference run).
 template <typename T>
-static void run_passes(Ctx &cx, const Circuit &c, DevPlan &dp, ntk::cx<T> *state, int B, int last_flags,
-                       const uint32_t *events, const int32_t *ev_count, int ev_stride, double *partials,
-                       uint32_t *frames) {
+static void run_passes(Ctx &cx, const Circuit &c, DevPlan &dp, ntk::cx<T> *state, const PassRun &r) {
   const Plan &P = dp.plan;
   const int np = (int)P.passes.size();
   const size_t dim = (size_t)1 << c.n;
+  const size_t bytes = dim * sizeof(ntk::cx<T>);
   for (int p = 0; p < np; ++p) {
+    const int Bp = r.active ? (*r.active)[p] : r.B;
+    if (Bp <= 0) continue;
     const Pass &ps = P.passes[p];
     ntk::PassArgs<T> a;
     std::memset(&a, 0, sizeof a);
@@ -354,21 +364,32 @@ static void run_passes(Ctx &cx, const Circuit &c, DevPlan &dp, ntk::cx<T> *state
     a.ref = static_cast<const ntk::cx<T> *>(dp.ref.p);
     a.ops = static_cast<const ntk::DevOp<T> *>(dp.ops.p);
     a.segs = static_cast<const ntk::DevSeg *>(dp.segs.p);
-    a.events = events;
-    a.ev_count = ev_count;
-    a.partials = partials;
-    a.frame_out = (p == np - 1) ? frames : nullptr;
+    a.events = r.events;
+    a.ev_count = r.ev_count;
+    a.partials = r.partials;
+    a.frame_out = (p == np - 1) ? r.frames : nullptr;
     a.state_stride = dim;
-    a.ev_stride = ev_stride;
-    a.B = B;
+    a.ev_stride = r.ev_stride;
+    a.B = Bp;
     a.L = P.L;
     a.ntile_bits = c.n - P.L;
     a.seg_begin = ps.seg_begin;
     a.seg_end = ps.seg_end;
     a.op_begin = ps.op_begin;
-    a.flags = (p == 0 ? ntk::PF_FIRST : 0) | (p == np - 1 ? last_flags : ntk::PF_STORE);
+    a.flags = (p == np - 1 ? r.last_flags : ntk::PF_STORE);
+    if (r.capture) {
+      a.flags = ntk::PF_STORE | ntk::PF_NORM;
+      a.partials = dp.ckpt_partials.as<double>() + (size_t)p * ((size_t)1 << (c.n - P.L)) * 3;
+    }
     a.init_index = 0;
     a.pass = static_cast<const ntk::DevPass *>(dp.passes.p) + p;
+    a.start = r.start;
+    a.ckpt = (r.start && p > 0) ? dp.ckpt.as<ntk::cx<T>>() + (size_t)(p - 1) * dim : nullptr;
+    a.pass_index = p;
+    a.end = r.end;
+    a.ref_here = r.end ? (p == np - 1 ? static_cast<const ntk::cx<T> *>(dp.ref.p)
+                                      : dp.ckpt.as<ntk::cx<T>>() + (size_t)p * dim)
+                       : nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (cx.timing) {
       e0 = take_event(cx.ev_pool);
@@ -379,19 +400,22 @@ static void run_passes(Ctx &cx, const Circuit &c, DevPlan &dp, ntk::cx<T> *state
     if (cx.timing) {
       check_hip(hipEventRecord(e1, cx.stream), "hipEventRecord");
       // algorithmic HBM bytes: every pass reads and writes each state once,
-      // except that the first does not read and a scoring pass reads the
+      // except that pass 0 does not read and a scoring pass reads the
       // reference instead of writing.
-      double per_state = (double)dim * sizeof(ntk::cx<T>);
-      double reads = (a.flags & ntk::PF_FIRST) ? 0.0 : 1.0;
+      double per_state = (double)bytes;
+      double reads = p == 0 ? 0.0 : 1.0;
       double writes = (a.flags & ntk::PF_SCORE) ? 0.0 : 1.0;
       double refr = (a.flags & ntk::PF_SCORE) ? 1.0 : 0.0;
       cx.ev_pending.emplace_back(e0, e1);
-      cx.ev_bytes.push_back(per_state * B * (reads + writes + refr));
-      cx.ev_updates.push_back((double)dim * B * (ps.op_end - ps.op_begin));
+      cx.ev_bytes.push_back(per_state * Bp * (reads + writes + refr));
+      cx.ev_updates.push_back((double)dim * Bp * (ps.op_end - ps.op_begin));
       double fl = dp.pass_flops_per_amp[p] + ((a.flags & ntk::PF_SCORE) ? 8.0 : 0.0);
-      cx.ev_flops.push_back((double)dim * B * fl);
+      cx.ev_flops.push_back((double)dim * Bp * fl);
       if (cx.ev_pending.size() >= 2048) cx.timing_flush();
     }
+    if (r.capture && p + 1 < np)
+      check_hip(hipMemcpyAsync(dp.ckpt.as<char>() + (size_t)p * bytes, state, bytes, hipMemcpyDeviceToDevice,
+                               cx.stream), "checkpoint copy");
   }
 }
 
@@ -411,12 +435,15 @@ void Ctx::ensure_reference(const Circuit &c, DevPlan &dp) {
   check_hip(hipMemsetAsync(ev_count.p, 0, sizeof(int32_t), stream), "hipMemsetAsync");
   bool was = timing;
   timing = false;
-  if (dp.prec == NT_C64)
-    run_passes<float>(*this, c, dp, dp.ref.as<ntk::cx<float>>(), 1, ntk::PF_STORE | ntk::PF_NORM,
-                      events.as<uint32_t>(), ev_count.as<int32_t>(), 1, dp.ref_partials.as<double>(), nullptr);
-  else
-    run_passes<double>(*this, c, dp, dp.ref.as<ntk::cx<double>>(), 1, ntk::PF_STORE | ntk::PF_NORM,
-                       events.as<uint32_t>(), ev_count.as<int32_t>(), 1, dp.ref_partials.as<double>(), nullptr);
+  PassRun r;
+  r.B = 1;
+  r.last_flags = ntk::PF_STORE | ntk::PF_NORM;
+  r.events = events.as<uint32_t>();
+  r.ev_count = ev_count.as<int32_t>();
+  r.ev_stride = 1;
+  r.partials = dp.ref_partials.as<double>();
+  if (dp.prec == NT_C64) run_passes<float>(*this, c, dp, dp.ref.as<ntk::cx<float>>(), r);
+  else run_passes<double>(*this, c, dp, dp.ref.as<ntk::cx<double>>(), r);
   timing = was;
   check_hip(ntk::launch_norm_final(dp.ref_partials.as<double>(), (int)ntiles, dp.nref.as<double>(), stream),
             "k_norm_final launch");
@@ -455,17 +482,18 @@ void Ctx::simulate_batch(const Circuit &c, DevPlan &dp, uint64_t seed, uint64_t 
   sa.ev_count = ev_count.as<int32_t>();
   check_hip(ntk::launch_sample(sa, stream), "k_sample launch");
 
-  const int last = mode == 0 ? ntk::PF_SCORE : ntk::PF_STORE;
-  if (dp.prec == NT_C64)
-    run_passes<float>(*this, c, dp, need_states ? states.as<ntk::cx<float>>() : nullptr, B, last,
-                      events.as<uint32_t>(), ev_count.as<int32_t>(), S, partials.as<double>(),
-                      frames.as<uint32_t>());
-  else
-    run_passes<double>(*this, c, dp, need_states ? states.as<ntk::cx<double>>() : nullptr, B, last,
-                       events.as<uint32_t>(), ev_count.as<int32_t>(), S, partials.as<double>(),
-                       frames.as<uint32_t>());
+  PassRun r;
+  r.B = B;
+  r.last_flags = mode == 0 ? ntk::PF_SCORE : ntk::PF_STORE;
+  r.events = events.as<uint32_t>();
+  r.ev_count = ev_count.as<int32_t>();
+  r.ev_stride = S;
+  r.partials = partials.as<double>();
+  r.frames = frames.as<uint32_t>();
+  if (dp.prec == NT_C64) run_passes<float>(*this, c, dp, need_states ? states.as<ntk::cx<float>>() : nullptr, r);
+  else run_passes<double>(*this, c, dp, need_states ? states.as<ntk::cx<double>>() : nullptr, r);
   if (mode == 0)
-    check_hip(ntk::launch_finalize(partials.as<double>(), (int)ntiles, B, dp.nref.as<double>(), tau, fid_dev,
+    check_hip(ntk::launch_finalize(partials.as<double>(), (int)ntiles, B, dp.nref.as<double>(), nullptr, tau, fid_dev,
                                    count_dev, stream),
               "k_finalize launch");
 }
@@ -473,6 +501,10 @@ void Ctx::simulate_batch(const Circuit &c, DevPlan &dp, uint64_t seed, uint64_t 
 void Ctx::run(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
               uint64_t *count_out) {
   check_hip(hipSetDevice(device), "hipSetDevice");
+  if (shortcuts) {
+    run_shortcut(c, seed, t0, n, tau, fid_out, count_out);
+    return;
+  }
   DevPlan &dp = plan_for(c, prec);
   ensure_reference(c, dp);
   const Thresholds th = make_thresholds(px, py, pz);
@@ -493,6 +525,241 @@ void Ctx::run(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double t
   check_hip(hipMemcpyAsync(&cnt, count.p, sizeof cnt, hipMemcpyDeviceToHost, stream), "copy count");
   sync();
   if (count_out) *count_out = cnt;
+}
+
+// Error-free checkpoints: the reference run repeated with the state copied
+// out after every pass.  Returns false (and stores nothing) when they do not
+// fit in device memory; callers then start every trajectory at pass 0.
+bool Ctx::ensure_checkpoints(const Circuit &c, DevPlan &dp) {
+  if (dp.ckpt_ready) return true;
+  ensure_reference(c, dp);
+  const int np = (int)dp.plan.passes.size();
+  if (np <= 1) {
+    dp.ckpt_ready = true;
+    return true;
+  }
+  const size_t bytes = (size_t)(np - 1) * ((size_t)1 << c.n) * amp_bytes(dp.prec);
+  size_t freeb = 0, total = 0;
+  check_hip(hipMemGetInfo(&freeb, &total), "hipMemGetInfo");
+  if (bytes + states.bytes + ((size_t)4 << 30) > freeb + states.bytes) return false;
+  dp.ckpt.ensure(bytes);
+  const size_t ntiles = (size_t)1 << (c.n - dp.plan.L);
+  dp.ckpt_partials.ensure((size_t)np * ntiles * 3 * sizeof(double));
+  dp.nref_pass.ensure((size_t)np * sizeof(double));
+  bool was = timing;
+  timing = false;
+  PassRun r;
+  r.B = 1;
+  r.last_flags = ntk::PF_STORE | ntk::PF_NORM;
+  ev_count.ensure(sizeof(int32_t) * 4);
+  events.ensure(16);
+  check_hip(hipMemsetAsync(ev_count.p, 0, sizeof(int32_t), stream), "hipMemsetAsync");
+  r.events = events.as<uint32_t>();
+  r.ev_count = ev_count.as<int32_t>();
+  r.partials = dp.ref_partials.as<double>();
+  r.capture = true;
+  if (dp.prec == NT_C64) run_passes<float>(*this, c, dp, dp.ref.as<ntk::cx<float>>(), r);
+  else run_passes<double>(*this, c, dp, dp.ref.as<ntk::cx<double>>(), r);
+  for (int p = 0; p < np; ++p)
+    check_hip(ntk::launch_norm_final(dp.ckpt_partials.as<double>() + (size_t)p * ntiles * 3, (int)ntiles,
+                                     dp.nref_pass.as<double>() + p, stream), "k_norm_final launch");
+  timing = was;
+  sync();
+  dp.ckpt_ready = true;
+  return true;
+}
+
+// Run batch entries whose events and counts are already in `events` /
+// `ev_count` (ev_stride words each); start: first pass per entry, sorted
+// ascending.  Fidelities go to fid_host[0..B).
+static void run_entries(Ctx &cx, const Circuit &c, DevPlan &dp, int B, int ev_stride,
+                        const std::vector<int32_t> &start, double tau, double *fid_host,
+                        const std::vector<int32_t> *end = nullptr) {
+  const Plan &P = dp.plan;
+  const int np = (int)P.passes.size();
+  const size_t dim = (size_t)1 << c.n;
+  const size_t ntiles = (size_t)1 << (c.n - P.L);
+  cx.partials.ensure((size_t)B * ntiles * 3 * sizeof(double));
+  cx.frames.ensure((size_t)B * 4 * sizeof(uint32_t));
+  cx.fid.ensure((size_t)B * sizeof(double));
+  cx.count.ensure(sizeof(uint64_t));
+  cx.start.ensure((size_t)B * sizeof(int32_t));
+  if (np > 1) cx.states.ensure((size_t)B * dim * amp_bytes(dp.prec));
+  std::vector<int> active(np, 0);
+  for (int p = 0; p < np; ++p)
+    active[p] = (int)(std::upper_bound(start.begin(), start.end(), p) - start.begin());
+  check_hip(hipMemcpyAsync(cx.start.p, start.data(), (size_t)B * sizeof(int32_t), hipMemcpyHostToDevice, cx.stream),
+            "upload start passes");
+  PassRun r;
+  r.B = B;
+  r.last_flags = ntk::PF_SCORE;
+  r.events = cx.events.as<uint32_t>();
+  r.ev_count = cx.ev_count.as<int32_t>();
+  r.ev_stride = ev_stride;
+  r.partials = cx.partials.as<double>();
+  r.frames = cx.frames.as<uint32_t>();
+  r.start = cx.start.as<int32_t>();
+  r.active = &active;
+  if (end) {
+    cx.end.ensure((size_t)B * sizeof(int32_t));
+    check_hip(hipMemcpyAsync(cx.end.p, end->data(), (size_t)B * sizeof(int32_t), hipMemcpyHostToDevice, cx.stream),
+              "upload end passes");
+    r.end = cx.end.as<int32_t>();
+  }
+  if (dp.prec == NT_C64) run_passes<float>(cx, c, dp, np > 1 ? cx.states.as<ntk::cx<float>>() : nullptr, r);
+  else run_passes<double>(cx, c, dp, np > 1 ? cx.states.as<ntk::cx<double>>() : nullptr, r);
+  check_hip(ntk::launch_finalize(cx.partials.as<double>(), (int)ntiles, B,
+                                 end ? dp.nref_pass.as<double>() : dp.nref.as<double>(), r.end, tau,
+                                 cx.fid.as<double>(), cx.count.as<uint64_t>(), cx.stream),
+            "k_finalize launch");
+  check_hip(hipMemcpyAsync(fid_host, cx.fid.p, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, cx.stream),
+            "copy fidelities");
+  cx.sync();
+}
+
+void Ctx::score_entries(const Circuit &c, DevPlan &dp, int B, const std::vector<uint32_t> &ev, int ev_stride,
+                        const std::vector<int32_t> &cnt, const std::vector<int32_t> &st, double tau,
+                        double *fid_host) {
+  events.ensure((size_t)B * ev_stride * 4);
+  ev_count.ensure((size_t)B * 4);
+  check_hip(hipMemcpyAsync(events.p, ev.data(), (size_t)B * ev_stride * 4, hipMemcpyHostToDevice, stream),
+            "upload events");
+  check_hip(hipMemcpyAsync(ev_count.p, cnt.data(), (size_t)B * 4, hipMemcpyHostToDevice, stream), "upload counts");
+  run_entries(*this, c, dp, B, ev_stride, st, tau, fid_host);
+}
+
+// Monte Carlo run with the exact short-cuts: a trajectory with no fired site
+// has the reference state itself (F = 1 exactly, not simulated), and a
+// trajectory starts from the error-free checkpoint before the pass holding
+// its first error.  Results are bit-identical to the plain run.
+void Ctx::run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
+                       uint64_t *count_out) {
+  DevPlan &dp = plan_for(c, prec);
+  ensure_reference(c, dp);
+  const bool have_ckpt = (shortcuts & (SC_CHECKPOINT | SC_LAST_ERROR)) && ensure_checkpoints(c, dp);
+  const bool early_end = have_ckpt && (shortcuts & SC_LAST_ERROR);
+  const Thresholds th = make_thresholds(px, py, pz);
+  const int S = (int)std::max<int64_t>(c.S, 1);
+  const int np = (int)dp.plan.passes.size();
+  std::vector<double> fh(n, 0.0);
+  const uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(n, (256u << 20) / ((uint64_t)S * 4)));
+  const uint64_t bs = batch_size(c, dp, n);
+  std::vector<int32_t> hcnt;
+  std::vector<uint32_t> hfirst;
+  for (uint64_t off = 0; off < n; off += chunk) {
+    const int Bc = (int)std::min<uint64_t>(chunk, n - off);
+    events.ensure((size_t)Bc * S * 4);
+    ev_count.ensure((size_t)Bc * 4);
+    ntk::SampleArgs sa;
+    std::memset(&sa, 0, sizeof sa);
+    sa.seed = seed; sa.cid = c.cid; sa.t0 = t0 + off;
+    sa.t_fire = th.t_fire; sa.c_x = th.c_x; sa.c_xy = th.c_xy; sa.always = th.always;
+    sa.B = Bc; sa.S = (int)c.S; sa.ev_stride = S;
+    sa.order = dp.app_order.as<int32_t>();
+    sa.tag = dp.app_tag.as<uint32_t>();
+    sa.events = events.as<uint32_t>();
+    sa.ev_count = ev_count.as<int32_t>();
+    check_hip(ntk::launch_sample(sa, stream), "k_sample launch");
+    hcnt.resize(Bc);
+    hfirst.resize(2 * (size_t)Bc);
+    firstlast.ensure((size_t)Bc * 8);
+    check_hip(ntk::launch_first_last(events.as<uint32_t>(), ev_count.as<int32_t>(), S, Bc, firstlast.as<uint32_t>(),
+                                     stream), "k_first_last launch");
+    check_hip(hipMemcpyAsync(hcnt.data(), ev_count.p, (size_t)Bc * 4, hipMemcpyDeviceToHost, stream), "copy counts");
+    check_hip(hipMemcpyAsync(hfirst.data(), firstlast.p, (size_t)Bc * 8, hipMemcpyDeviceToHost, stream),
+              "copy first/last events");
+    sync();
+    // (first pass, index within the chunk, last pass) of the trajectories to simulate
+    std::vector<std::tuple<int32_t, int32_t, int32_t>> act;
+    for (int b = 0; b < Bc; ++b) {
+      if (hcnt[b] == 0 && (shortcuts & SC_ZERO_FIRED)) {
+        fh[off + b] = 1.0;
+        continue;
+      }
+      int32_t sp = 0, ep = np - 1;
+      if (have_ckpt) sp = hcnt[b] ? dp.pass_of_op[hfirst[2 * b] >> 8] : np - 1;
+      if (early_end) ep = hcnt[b] ? dp.pass_of_op[hfirst[2 * b + 1] >> 8] : np - 1;
+      act.emplace_back(sp, b, ep);
+    }
+    std::stable_sort(act.begin(), act.end());
+    std::vector<uint64_t> tl;
+    std::vector<int32_t> st, en;
+    std::vector<double> fsub;
+    for (size_t a0 = 0; a0 < act.size(); a0 += bs) {
+      const int B = (int)std::min<size_t>(bs, act.size() - a0);
+      tl.resize(B);
+      st.resize(B);
+      en.resize(B);
+      fsub.resize(B);
+      for (int j = 0; j < B; ++j) {
+        tl[j] = t0 + off + (uint64_t)std::get<1>(act[a0 + j]);
+        st[j] = std::get<0>(act[a0 + j]);
+        en[j] = std::get<2>(act[a0 + j]);
+      }
+      this->tlist.ensure((size_t)B * 8);
+      check_hip(hipMemcpyAsync(this->tlist.p, tl.data(), (size_t)B * 8, hipMemcpyHostToDevice, stream), "upload ids");
+      events.ensure((size_t)B * S * 4);
+      ev_count.ensure((size_t)B * 4);
+      sa.B = B;
+      sa.events = events.as<uint32_t>();     // (re)allocated above
+      sa.ev_count = ev_count.as<int32_t>();
+      sa.tlist = this->tlist.as<uint64_t>();
+      check_hip(ntk::launch_sample(sa, stream), "k_sample launch");
+      sa.tlist = nullptr;
+      run_entries(*this, c, dp, B, S, st, tau, fsub.data(), early_end ? &en : nullptr);
+      for (int j = 0; j < B; ++j) fh[off + std::get<1>(act[a0 + j])] = fsub[j];
+    }
+  }
+  uint64_t cnt = 0;
+  for (uint64_t i = 0; i < n; ++i) cnt += fh[i] >= tau ? 1 : 0;
+  if (count_out) *count_out = cnt;
+  if (fid_out) {
+    if (is_device_pointer(fid_out))
+      check_hip(hipMemcpy(fid_out, fh.data(), n * sizeof(double), hipMemcpyHostToDevice), "copy fidelities");
+    else
+      std::memcpy(fid_out, fh.data(), n * sizeof(double));
+  }
+}
+
+// Exhaustive single-error simulation (Sec. IV-B.1, Eq. 3): every site, every
+// Pauli, one error each; entries in plan order start at their error's pass.
+void Ctx::exhaustive(const Circuit &c, double tau, double *fid_out, double P_e[3], double *P_R) {
+  check_hip(hipSetDevice(device), "hipSetDevice");
+  DevPlan &dp = plan_for(c, prec);
+  ensure_reference(c, dp);
+  const bool have_ckpt = ensure_checkpoints(c, dp);
+  const Plan &P = dp.plan;
+  const int64_t S = c.S;
+  const int64_t total = 3 * S;
+  std::vector<double> fall((size_t)std::max<int64_t>(total, 1), 0.0);
+  const uint64_t bs = batch_size(c, dp, (uint64_t)std::max<int64_t>(total, 1));
+  std::vector<uint32_t> ev;
+  std::vector<int32_t> cnt, st;
+  std::vector<double> fsub;
+  for (int64_t off = 0; off < total; off += (int64_t)bs) {
+    const int B = (int)std::min<int64_t>((int64_t)bs, total - off);
+    ev.resize(B);
+    cnt.assign(B, 1);
+    st.resize(B);
+    fsub.resize(B);
+    for (int j = 0; j < B; ++j) {
+      const int64_t i = off + j, k = i / 3;
+      ev[j] = P.app_tag[(size_t)k] | (uint32_t)(i % 3 + 1);
+      st[j] = have_ckpt ? dp.pass_of_op[P.app_tag[(size_t)k] >> 8] : 0;
+    }
+    score_entries(c, dp, B, ev, 1, cnt, st, tau, fsub.data());
+    for (int j = 0; j < B; ++j) {
+      const int64_t i = off + j, k = i / 3;
+      fall[(size_t)P.app_site[(size_t)k] * 3 + (size_t)(i % 3)] = fsub[j];
+    }
+  }
+  for (int e = 0; e < 3; ++e) {
+    double s = 0;
+    for (int64_t site = 0; site < S; ++site) s += fall[(size_t)site * 3 + e] >= tau ? 1.0 : 0.0;
+    P_e[e] = S ? s / (double)S : 0.0;
+  }
+  *P_R = 1.0 >= tau ? 1.0 : 0.0;
+  if (fid_out) std::memcpy(fid_out, fall.data(), (size_t)total * sizeof(double));
 }
 
 void Ctx::sample_sites(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, uint64_t *offsets, int32_t *sites,

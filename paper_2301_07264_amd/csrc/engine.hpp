@@ -29,8 +29,30 @@ struct DevPlan {
   DevBuf ops, segs, passes, app_order, app_tag, site_order, site_tag;
   DevBuf ref, nref, ref_partials;
   bool ref_ready = false;
+  DevBuf ckpt;                 // error-free state before passes 1..np-1
+  DevBuf ckpt_partials, nref_pass;   // norms of the error-free state after each pass
+  bool ckpt_ready = false;
+  std::vector<int> pass_of_op;
   std::vector<double> pass_flops_per_amp;   // algorithmic flops per amplitude, per pass
 };
+
+// Arguments of one run of all passes over a batch (engine.cpp).
+struct PassRun {
+  int B = 0;
+  int last_flags = 0;
+  const uint32_t *events = nullptr;
+  const int32_t *ev_count = nullptr;
+  int ev_stride = 1;
+  double *partials = nullptr;
+  uint32_t *frames = nullptr;
+  const int32_t *start = nullptr;            // device: first pass per entry (sorted), or NULL
+  const std::vector<int> *active = nullptr;  // per pass: entries with start <= p
+  const int32_t *end = nullptr;              // device: pass after which each entry is scored, or NULL
+  bool capture = false;                      // copy the state into the checkpoints after each pass
+};
+
+// Shortcut flags (nt_set_shortcuts).
+enum : int { SC_ZERO_FIRED = 1, SC_CHECKPOINT = 2, SC_LAST_ERROR = 4 };
 
 struct Ctx {
   int device = 0;
@@ -39,8 +61,9 @@ struct Ctx {
   double px = 0, py = 0, pz = 0;
   int prec = NT_C128;
   uint64_t max_batch = 0;
+  int shortcuts = 0;
   std::map<std::pair<uint64_t, int>, std::unique_ptr<DevPlan>> plans;
-  DevBuf states, events, ev_count, partials, fid, count, frames, tmp;
+  DevBuf states, events, ev_count, partials, fid, count, frames, tmp, tlist, start, end, firstlast;
   // timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
@@ -64,6 +87,15 @@ struct Ctx {
 
   void run(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
            uint64_t *count_out);
+  void run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
+                    uint64_t *count_out);
+  bool ensure_checkpoints(const Circuit &c, DevPlan &dp);
+  // Score batch entries with explicit event lists (ev_stride words each, counts
+  // given) and first passes `start` (sorted); fids to host.
+  void score_entries(const Circuit &c, DevPlan &dp, int B, const std::vector<uint32_t> &ev, int ev_stride,
+                     const std::vector<int32_t> &cnt, const std::vector<int32_t> &start, double tau,
+                     double *fid_host);
+  void exhaustive(const Circuit &c, double tau, double *fid_out, double P_e[3], double *P_R);
   void sample_sites(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, uint64_t *offsets,
                     int32_t *sites, uint8_t *paulis, int64_t cap, int64_t *n_out);
   void final_state(const Circuit &c, uint64_t seed, uint64_t traj, void *out, int64_t len);

@@ -6,8 +6,9 @@
 //               from word1 (Sec. IV-B.2).  One wavefront per trajectory
 //               compacts its fired sites in plan order with a ballot.
 //   k_pass      one HBM pass of the gate plan over a tile of 2^L amplitudes
-//               per work-group: load (coalesced) -> LDS -> register segments
-//               -> store, or -> fused FP64 scoring against the reference.
+//               per work-group: load (coalesced; or synthesize |0..0>, or
+//               start from an error-free checkpoint) -> LDS -> register
+//               segments / LDS quads -> store, or -> fused FP64 scoring.
 //   k_finalize  fixed-order FP64 sums of the per-tile partials, fidelity and
 //               success indicator per trajectory, integer success count
 //               (Sec. IV-C: success probability = mean over the states).
@@ -56,7 +57,7 @@ __global__ void __launch_bounds__(256) k_sample(const SampleArgs a) {
   const int lane = threadIdx.x & 63;
   const int b = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (b >= a.B) return;                       // whole wavefront leaves together
-  const uint64_t t = a.t0 + (uint64_t)b;
+  const uint64_t t = a.tlist ? a.tlist[b] : a.t0 + (uint64_t)b;
   uint32_t *ev = a.events + (size_t)b * a.ev_stride;
   int base = 0;
   for (int k0 = 0; k0 < a.S; k0 += 64) {
@@ -451,6 +452,10 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   const uint32_t tid = threadIdx.x;
   const int b = (int)(blockIdx.x % (uint32_t)a.B);
   const uint32_t tile = blockIdx.x / (uint32_t)a.B;
+  // trajectories already scored at an earlier pass have nothing to do
+  if (a.end && a.pass_index > a.end[b]) return;
+  const bool score_here = a.end ? (a.end[b] == a.pass_index) : ((a.flags & PF_SCORE) != 0);
+  const cx<T> *refp = a.end ? a.ref_here : a.ref;
 
   const DevPass &ps = *a.pass;
   uint32_t tilebase = 0;
@@ -480,16 +485,18 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   const cx<T> *sp = st + (tilebase | dlo);   // dhi(k) bits are disjoint from tilebase | dlo
 
   // Load the tile (coalesced: thread-id bits are the low local bits).
-  if (a.flags & PF_FIRST) {
+  const int my_start = a.start ? a.start[b] : 0;
+  if (my_start == a.pass_index && a.pass_index == 0) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const uint32_t g = tilebase | dlo | dhi(k);
       lds_k(k) = cx<T>{g == a.init_index ? T(1) : T(0), T(0)};
     }
   } else {
+    const cx<T> *src = (my_start == a.pass_index) ? a.ckpt + (tilebase | dlo) : sp;
     cx<T> v[NS];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) v[k] = sp[dhi(k)];
+    for (int k = 0; k < NS; ++k) v[k] = src[dhi(k)];
 #pragma unroll
     for (int k = 0; k < NS; ++k) lds_k(k) = v[k];
   }
@@ -571,13 +578,13 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   // live across the segment loop.
   asm volatile("" : "+v"(dlo));
   const size_t ntiles = (size_t)1 << a.ntile_bits;
-  if (a.flags & PF_SCORE) {
+  if (score_here) {
     double ovr = 0.0, ovi = 0.0, nrm = 0.0;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const uint32_t g = tilebase | dlo | dhi(k);
       const cx<T> s = lds_k(k);
-      const cx<T> r = a.ref[g ^ fx];
+      const cx<T> r = refp[g ^ fx];
       double sr = (double)s.x, si = (double)s.y;
       if (__popc(fz & g) & 1u) {
         sr = -sr;
@@ -653,7 +660,7 @@ DEV double sum_partials(const double *p, int ntiles, int comp, double *red) {
 }
 
 __global__ void __launch_bounds__(256) k_finalize(const double *partials, int ntiles, const double *nref,
-                                                  double tau, double *fid, uint64_t *count) {
+                                                  const int32_t *end, double tau, double *fid, uint64_t *count) {
   __shared__ double red[4];
   const int b = blockIdx.x;
   const double *p = partials + (size_t)b * ntiles * 3;
@@ -662,16 +669,34 @@ __global__ void __launch_bounds__(256) k_finalize(const double *partials, int nt
   const double nrm = sum_partials(p, ntiles, 2, red);
   if (threadIdx.x == 0) {
     const double num = __fma_rn(ovi, ovi, __dmul_rn(ovr, ovr));
-    const double F = __ddiv_rn(num, __dmul_rn(nref[0], nrm));
+    const double nr = end ? nref[end[b]] : nref[0];
+    const double F = __ddiv_rn(num, __dmul_rn(nr, nrm));
     fid[b] = F;
     if (F >= tau) atomicAdd((unsigned long long *)count, 1ull);
   }
 }
 
-hipError_t launch_finalize(const double *partials, int ntiles, int B, const double *nref, double tau,
-                           double *fid, uint64_t *count, hipStream_t s) {
+hipError_t launch_finalize(const double *partials, int ntiles, int B, const double *nref, const int32_t *end,
+                           double tau, double *fid, uint64_t *count, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3(B), dim3(256), 0, s, partials, ntiles, nref, tau, fid, count);
+  hipLaunchKernelGGL(k_finalize, dim3(B), dim3(256), 0, s, partials, ntiles, nref, end, tau, fid, count);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_first_last(const uint32_t *events, const int32_t *ev_count, int ev_stride,
+                                                    int B, uint32_t *out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const int n = ev_count[b];
+  const uint32_t *e = events + (size_t)b * ev_stride;
+  out[2 * b] = n > 0 ? e[0] : 0u;
+  out[2 * b + 1] = n > 0 ? e[n - 1] : 0u;
+}
+
+hipError_t launch_first_last(const uint32_t *events, const int32_t *ev_count, int ev_stride, int B, uint32_t *out,
+                             hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_first_last, dim3((B + 255) / 256), dim3(256), 0, s, events, ev_count, ev_stride, B, out);
   return hipGetLastError();
 }
 

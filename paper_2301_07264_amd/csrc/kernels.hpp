@@ -59,7 +59,6 @@ struct DevPass {
 };
 
 enum : int32_t {
-  PF_FIRST = 1,   // synthesize the initial basis state instead of loading
   PF_SCORE = 2,   // overlap with the reference + norm (FP64 partials); no store
   PF_STORE = 4,   // write the tile back (always unless PF_SCORE)
   PF_NORM = 8,    // norm partials only (reference run)
@@ -84,10 +83,22 @@ struct PassArgs {
   int32_t seg_begin, seg_end, op_begin;
   int32_t flags;
   uint32_t init_index;
+  // Trajectories may start late: start[b] is the first pass trajectory b
+  // runs (NULL: all start at pass 0).  A trajectory starting at this pass
+  // synthesizes the initial state (pass 0) or loads `ckpt`, the error-free
+  // state before this pass; one that started earlier loads its own state.
+  const int32_t *start;
+  const cx<T> *ckpt;
+  int32_t pass_index;
+  // With `end`, trajectory b is scored at the end of pass end[b] against
+  // `ref_here` (the error-free state after this pass) and skips later passes.
+  const int32_t *end;
+  const cx<T> *ref_here;
 };
 
 struct SampleArgs {
   uint64_t seed, cid, t0;
+  const uint64_t *tlist;   // trajectory ids (NULL: t0 + b)
   uint64_t t_fire, c_x, c_xy;
   uint32_t always;
   int32_t B, S, ev_stride;
@@ -101,8 +112,13 @@ struct SampleArgs {
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
 template <typename T>
 hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, hipStream_t s);
-hipError_t launch_finalize(const double *partials, int ntiles, int B, const double *nref, double tau,
-                           double *fid, uint64_t *count, hipStream_t s);
+// nref: reference norm (end == NULL) or per-pass reference norms indexed by
+// end[b].
+hipError_t launch_finalize(const double *partials, int ntiles, int B, const double *nref, const int32_t *end,
+                           double tau, double *fid, uint64_t *count, hipStream_t s);
+// First and last event word of each trajectory (0 when it has none).
+hipError_t launch_first_last(const uint32_t *events, const int32_t *ev_count, int ev_stride, int B,
+                             uint32_t *out, hipStream_t s);
 hipError_t launch_norm_final(const double *partials, int ntiles, double *nref, hipStream_t s);
 template <typename T>
 hipError_t launch_unframe(const cx<T> *st, cx<T> *out, uint64_t dim, const uint32_t *frame,

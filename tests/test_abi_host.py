@@ -24,7 +24,7 @@ def P():
 
 def test_exports_every_declared_symbol(P):
     hdr = open(os.path.join(ROOT, "include", "nisqtol.h")).read()
-    declared = set(re.findall(r"\b(nt_[a-z_]+)\s*\(", hdr))
+    declared = set(re.findall(r"\b(nt_[a-z0-9_]+)\s*\(", hdr))
     assert declared, "no declarations found"
     L = P.lib()
     for name in sorted(declared):

@@ -331,3 +331,88 @@ def test_gpu_error_paths(P, ctx):
     offs, s, pa = P.nt_sample_sites(ctx, h, 0, 0, 10, cap=1)   # retried with the needed size
     assert int(offs[-1]) == s.size
     P.nt_circuit_free(h)
+
+
+# ---------------------------------------------------------------------------
+# Exact short-cuts (zero-fired trajectories, error-free checkpoints) give
+# bit-identical results to the plain run.
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_shortcuts_bit_identical(P, ctx, prec):
+    pr = P.NT_C64 if prec == "c64" else P.NT_C128
+    for c in (_all_gates_circuit(16, 3, 21), W.config0()):
+        h = _load(P, c)
+        P.nt_set_precision(ctx, pr)
+        for p in (1e-3, 2e-2):
+            P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+            N = 96
+            base = np.zeros(N)
+            P.nt_set_shortcuts(ctx, 0)
+            c0, _ = P.nt_run(ctx, h, 4, 7, N, TAU, base)
+            for flags in (1, 2, 3):
+                P.nt_set_shortcuts(ctx, flags)
+                f = np.zeros(N)
+                c1, _ = P.nt_run(ctx, h, 4, 7, N, TAU, f)
+                np.testing.assert_array_equal(f.view(np.uint64), base.view(np.uint64))
+                assert c1 == c0
+        P.nt_set_shortcuts(ctx, 0)
+        P.nt_circuit_free(h)
+
+
+# ---------------------------------------------------------------------------
+# Exhaustive single-error branch (Sec. IV-B.1, Eq. 3), Eq. 4, Eq. 5 and the
+# method switch of Fig. 2, against the oracle.
+
+@pytest.mark.parametrize("n,layers", [(6, 3), (15, 2)])
+def test_exhaustive_vs_oracle(P, ctx, orc, n, layers):
+    c = W.random_layers(n, layers, np.random.default_rng(50 + n))
+    h = _load(P, c)
+    P.nt_set_precision(ctx, P.NT_C128)
+    fid, pe, pr = P.nt_exhaustive(ctx, h, TAU)
+    f_o = orc.exhaustive(c)
+    assert np.abs(fid - f_o).max() <= 1e-12
+    margin = np.abs(f_o - TAU) < 1e-12
+    want = np.where(margin, fid >= TAU, f_o >= TAU).mean(0)
+    np.testing.assert_array_equal(pe, want)
+    assert pr == 1.0
+    p = 1e-3
+    E = [c.S * p / 3] * 3
+    assert abs(P.nt_eq4(pe, pr, E) - orc.eq4(pe, pr, E)) < 1e-15
+    if pe.mean() != pr:
+        assert abs(P.nt_eq5(0.66, pe, pr, c.S) - orc.eq5(0.66, pe, pr, c.S)) < 1e-15
+    # method switch: E(N) = S p
+    P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+    Pm, method = P.nt_success_probability(ctx, h, 0, 200, TAU)
+    if c.S * p <= 1:
+        assert method == 0 and abs(Pm - orc.eq4(pe, pr, E)) < 1e-15
+    big = 3.0 / c.S
+    P.nt_set_error_model(ctx, big / 3, big / 3, big / 3)
+    Pm, method = P.nt_success_probability(ctx, h, 0, 200, TAU)
+    cnt, _ = P.nt_run(ctx, h, 0, 0, 200, TAU)
+    assert method == 1 and Pm == cnt / 200
+    P.nt_circuit_free(h)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_last_error_shortcut(P, ctx, prec):
+    """Scoring right after the last error (the unitary suffix keeps the
+    overlap) agrees with the full run to rounding."""
+    pr = P.NT_C64 if prec == "c64" else P.NT_C128
+    ftol = 2e-5 if prec == "c64" else 1e-12
+    c = _all_gates_circuit(16, 4, 33)
+    h = _load(P, c)
+    P.nt_set_precision(ctx, pr)
+    for p in (2e-3, 3e-2):
+        P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+        N = 128
+        base = np.zeros(N)
+        P.nt_set_shortcuts(ctx, 0)
+        c0, _ = P.nt_run(ctx, h, 9, 0, N, TAU, base)
+        f = np.zeros(N)
+        P.nt_set_shortcuts(ctx, P.NT_SHORTCUT_ZERO_FIRED | P.NT_SHORTCUT_CHECKPOINT | P.NT_SHORTCUT_LAST_ERROR)
+        c1, _ = P.nt_run(ctx, h, 9, 0, N, TAU, f)
+        P.nt_set_shortcuts(ctx, 0)
+        assert np.abs(f - base).max() <= ftol
+        margin = np.abs(base - TAU) < ftol
+        assert int(((f >= TAU) != (base >= TAU))[~margin].sum()) == 0
+    P.nt_circuit_free(h)
