@@ -84,6 +84,8 @@ def lib():
         L.orc_median_prob.restype = dbl
         L.orc_run_criterion.argtypes = circ + [dbl, dbl, dbl, u64, u64, u64, u64, i32, u64, i32, P]
         L.orc_run_criterion.restype = i32
+        L.orc_exhaustive_criterion.argtypes = circ + [i32, u64, i32, P, P]
+        L.orc_exhaustive_criterion.restype = i32
         _lib = L
     return _lib
 
@@ -243,6 +245,17 @@ def exhaustive(circuit, nthreads: int = 0) -> np.ndarray:
     rc = lib().orc_exhaustive(*oc.args(), nthreads, _p(out))
     assert rc == 0
     return out[:oc.S]
+
+
+def exhaustive_criterion(circuit, crit: int, target: int = 0, nthreads: int = 0):
+    """Criterion value of every single-error state, shape [S, 3] (X, Y, Z),
+    and of the reference state."""
+    oc = OCircuit(circuit)
+    out = np.zeros((max(oc.S, 1), 3), np.float64)
+    rv = C.c_double(0.0)
+    rc = lib().orc_exhaustive_criterion(*oc.args(), crit, target, nthreads, _p(out), C.byref(rv))
+    assert rc == 0
+    return out[:oc.S], rv.value
 
 
 def eq4(P_e, P_R, E_e) -> float:

@@ -659,6 +659,26 @@ double orc_median_prob(int n, const double *psi_ri) {
   return med;
 }
 
+/* Value of a criterion on the final state psi given the ideal state ref:
+ * crit 0 = fidelity, 1 = |psi_target|^2 / <psi|psi>, 2 = heavy-output
+ * probability (noisy mass on {k : |ref_k|^2 > med}) / <psi|psi>. */
+static double criterion_value(int n, const cplx *ref, const cplx *psi, int crit, uint64_t target, double med) {
+  if (crit == 0) return fidelity(n, ref, psi);
+  uint64_t dim = 1ULL << n;
+  double norm = 0, heavy = 0;
+  for (uint64_t k = 0; k < dim; ++k) {
+    double pk = creal(psi[k]) * creal(psi[k]) + cimag(psi[k]) * cimag(psi[k]);
+    double rk = creal(ref[k]) * creal(ref[k]) + cimag(ref[k]) * cimag(ref[k]);
+    norm += pk;
+    if (rk > med) heavy += pk;
+  }
+  if (crit == 1) {
+    double pt = creal(psi[target]) * creal(psi[target]) + cimag(psi[target]) * cimag(psi[target]);
+    return pt / norm;
+  }
+  return heavy / norm;
+}
+
 /* Per-trajectory values of a criterion: crit 1 = |a_target|^2 / <psi|psi>;
  * crit 2 = heavy-output probability.  Returns 0. */
 int orc_run_criterion(int n, int64_t G, const int32_t *kind, const int32_t *q0, const int32_t *q1,
@@ -683,21 +703,44 @@ int orc_run_criterion(int n, int64_t G, const int32_t *kind, const int32_t *q0, 
     for (int64_t i = 0; i < (int64_t)N; ++i) {
       int64_t nf = orc_sample_trajectory(seed, cid, t0 + (uint64_t)i, c.S, px, py, pz, fs, fp, c.S);
       run_trajectory(&c, 0, fs, fp, nf, psi, 0);
-      double norm = 0, heavy = 0;
-      for (uint64_t k = 0; k < dim; ++k) {
-        double pk = creal(psi[k]) * creal(psi[k]) + cimag(psi[k]) * cimag(psi[k]);
-        double rk = creal(ref[k]) * creal(ref[k]) + cimag(ref[k]) * cimag(ref[k]);
-        norm += pk;
-        if (rk > med) heavy += pk;
-      }
-      if (crit == 1) {
-        double pt = creal(psi[target]) * creal(psi[target]) + cimag(psi[target]) * cimag(psi[target]);
-        val_out[i] = pt / norm;
-      } else {
-        val_out[i] = heavy / norm;
-      }
+      val_out[i] = criterion_value(n, ref, psi, crit, target, med);
     }
     free(psi); free(fs); free(fp);
+  }
+  free(ref);
+  circuit_free(&c);
+  return 0;
+}
+
+/* Exhaustive single-error branch (Sec. IV-B.1) under any criterion: value of
+ * the criterion on each of the 3S single-error states, [S][3] (X, Y, Z), and
+ * on the reference state (*ref_val).  Small circuits only (one state per
+ * thread). */
+int orc_exhaustive_criterion(int n, int64_t G, const int32_t *kind, const int32_t *q0, const int32_t *q1,
+                             const double *params, const double *umats, int crit, uint64_t target,
+                             int nthreads, double *val_out, double *ref_val) {
+  circuit c;
+  if (circuit_init(&c, n, G, kind, q0, q1, params, umats)) { circuit_free(&c); return -1; }
+  uint64_t dim = 1ULL << n;
+  cplx *ref = (cplx *)malloc(dim * sizeof(cplx));
+  run_trajectory(&c, 0, NULL, NULL, 0, ref, 0);
+  double med = crit == 2 ? orc_median_prob(n, (const double *)ref) : 0.0;
+  *ref_val = criterion_value(n, ref, ref, crit, target, med);
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  int64_t total = 3 * c.S;
+#pragma omp parallel
+  {
+    cplx *psi = (cplx *)malloc(dim * sizeof(cplx));
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t i = 0; i < total; ++i) {
+      int32_t s = (int32_t)(i / 3);
+      uint8_t pa = (uint8_t)(1 + i % 3);
+      run_trajectory(&c, 0, &s, &pa, 1, psi, 0);
+      val_out[i] = criterion_value(n, ref, psi, crit, target, med);
+    }
+    free(psi);
   }
   free(ref);
   circuit_free(&c);

@@ -415,3 +415,64 @@ def test_fidelity_definition(orc):
     want = abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)
     assert abs(orc.fidelity(a, b, 4) - want) < 1e-15
     assert orc.fidelity(a, a, 4) == pytest.approx(1.0, abs=1e-15)
+
+
+# Exhaustive branch under the measurement criteria (Sec. IV-B.1 with Sec. II):
+# each single-error state against a brute-force statevector.
+def test_exhaustive_criteria_vs_bruteforce(orc):
+    c = W.random_layers(4, 3, np.random.default_rng(41))
+    ops = pinlib.circuit_unitaries(c)
+    ref = pinlib.simulate_pattern(c, [0] * c.S, ops)
+    pr = np.abs(ref) ** 2
+    heavy = pr > np.median(pr)
+    target = int(np.argmax(pr))
+    v1, r1 = orc.exhaustive_criterion(c, 1, target)
+    v2, r2 = orc.exhaustive_criterion(c, 2)
+    v0, r0 = orc.exhaustive_criterion(c, 0)
+    assert abs(r1 - pr[target] / pr.sum()) < 1e-14
+    assert abs(r2 - pr[heavy].sum() / pr.sum()) < 1e-14
+    assert abs(r0 - 1.0) < 1e-14
+    for s in range(c.S):
+        for e in range(3):
+            pat = [0] * c.S
+            pat[s] = e + 1
+            psi = pinlib.simulate_pattern(c, pat, ops)
+            pp = np.abs(psi) ** 2
+            assert abs(v1[s, e] - pp[target] / pp.sum()) < 1e-13
+            assert abs(v2[s, e] - pp[heavy].sum() / pp.sum()) < 1e-13
+            fid = abs(np.vdot(ref, psi)) ** 2 / (np.vdot(ref, ref).real * pp.sum())
+            assert abs(v0[s, e] - fid) < 1e-13
+
+
+# An error on a qubit's last site acts after every gate on that qubit: Z leaves
+# every measurement probability unchanged, X and Y move the target's
+# probability to the index with that bit flipped.
+def test_criteria_last_site_pauli_invariants(orc):
+    c = W.random_layers(5, 4, np.random.default_rng(42))
+    last = {}
+    s = 0
+    for g in c.gates:
+        for q in g.qubits:
+            last[q] = s
+            s += 1
+    ref = orc.final_state_pattern(c, [], [])
+    pr = np.abs(ref) ** 2 / np.vdot(ref, ref).real
+    target = 11
+    v1, r1 = orc.exhaustive_criterion(c, 1, target)
+    v2, r2 = orc.exhaustive_criterion(c, 2)
+    for q, site in last.items():
+        assert abs(v1[site, 2] - r1) < 1e-13          # Z
+        assert abs(v2[site, 2] - r2) < 1e-13
+        for e in (0, 1):                               # X, Y
+            assert abs(v1[site, e] - pr[target ^ (1 << q)]) < 1e-13
+
+
+# Heavy-output probability of a Haar-like state: for Porter-Thomas distributed
+# probabilities the mass above the median tends to (1 + ln 2) / 2 ~ 0.847.
+def test_heavy_output_porter_thomas(orc):
+    c = W.random_layers(12, 24, np.random.default_rng(43))
+    # |0...0>: median 0, the heavy set is {0} and holds all the mass
+    _, r2 = orc.exhaustive_criterion(W.Circuit(c.n, c.gates[:0]), 2)
+    assert r2 == 1.0
+    vals = orc.run_criterion(c, 0.0, 0.0, 0.0, 0, 0, 1, 2)
+    assert abs(vals[0] - (1 + math.log(2)) / 2) < 0.02
