@@ -147,13 +147,39 @@ nt_status nt_plan_info(const nt_circuit *c, int prec, int *n_passes, int *n_segm
 nt_status nt_plan_export(const nt_circuit *c, int prec, int32_t *op_gate, int32_t *op_pass,
                          int32_t *op_segment, uint64_t *pass_local_mask, uint64_t *segment_reg_mask);
 
+/* ---- success criterion (Sec. II, Sec. V) ----------------------------------- */
+
+/* Criterion every scoring call of the context evaluates on a final state psi
+ * (R = the error-free state):
+ * NT_CRIT_FIDELITY    -- F = |<R|psi>|^2 / (<R|R><psi|psi>); a state succeeds
+ *                        when F >= tau.  Default.
+ * NT_CRIT_TARGET_PROB -- probability of measuring basis state `target`,
+ *                        |psi_target|^2 / <psi|psi> (circuits with a single
+ *                        correct outcome).
+ * NT_CRIT_HEAVY       -- heavy-output probability: the mass of psi on the
+ *                        basis states whose error-free probability |R_k|^2
+ *                        exceeds the median of all 2^n of them (the mean of
+ *                        the two middle values); quantum-volume binning.
+ * For the two probability criteria a state's success is that probability
+ * itself: success probabilities are means over trajectories (and per error
+ * type in the exhaustive branch), while count_out still counts values >= tau.
+ * The heavy set is decided on the device's reference state in FP64; the
+ * median is selected exactly, once per circuit and precision.
+ * `target` is checked against the circuit at run time (NT_ERR_INVALID_ARG).
+ * The last-error short-cut does not apply to these two criteria (they are
+ * not invariant under the error-free rest of the circuit) and is skipped. */
+enum { NT_CRIT_FIDELITY = 0, NT_CRIT_TARGET_PROB = 1, NT_CRIT_HEAVY = 2 };
+nt_status nt_set_criterion(nt_ctx *ctx, int criterion, uint64_t target);
+
 /* ---- Monte Carlo runs ------------------------------------------------------ */
 
 /* Runs trajectories [traj_begin, traj_begin + n_traj) under the current
  * error model and precision and scores each against the error-free state
- * (Sec. IV-B.2, IV-C).  fid_out: n_traj doubles, host or device memory, may
- * be NULL.  count_out: number of trajectories with F >= tau (may be NULL).
- * p_out: count / n_traj (may be NULL). */
+ * (Sec. IV-B.2, IV-C) by the context's criterion.  fid_out: n_traj doubles
+ * (the criterion value of each trajectory), host or device memory, may be
+ * NULL.  count_out: number of trajectories with value >= tau (may be NULL).
+ * p_out (may be NULL): success probability, count / n_traj for the fidelity
+ * criterion, the mean value for the probability criteria. */
 nt_status nt_run(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_begin,
                  uint64_t n_traj, double tau, double *fid_out, uint64_t *count_out,
                  double *p_out);
@@ -180,7 +206,8 @@ nt_status nt_tolerable_rate(nt_ctx *ctx, const nt_circuit *c, double P_target, d
 
 /* Exact short-cuts for Monte Carlo runs (results stay bit-identical):
  * NT_SHORTCUT_ZERO_FIRED -- a trajectory with no fired site ends in the
- *   error-free state, so its fidelity is 1 without simulating it;
+ *   error-free state, so its fidelity is 1 without simulating it (for the
+ *   probability criteria: the error-free state's value, computed once);
  * NT_SHORTCUT_CHECKPOINT -- the error-free state before every pass is kept in
  *   device memory and a trajectory starts at the pass holding its first
  *   error (silently off when the checkpoints do not fit).
@@ -197,10 +224,10 @@ nt_status nt_set_shortcuts(nt_ctx *ctx, int flags);
 
 /* Exhaustive Pauli error simulation (Sec. IV-B.1, Eq. 3): the circuit with
  * exactly one X, Y or Z error at each of its S sites (3S runs), scored by
- * the fidelity criterion.  fid_out (host, may be NULL): [S][3] fidelities,
- * columns X, Y, Z.  P_e[0..2]: success probability averaged over the states
- * with the same Pauli type (X, Y, Z); *P_R: success of the reference state
- * (Sec. IV-C). */
+ * the context's criterion.  fid_out (host, may be NULL): [S][3] criterion
+ * values, columns X, Y, Z.  P_e[0..2]: success probability averaged over the
+ * states with the same Pauli type (X, Y, Z); *P_R: success of the reference
+ * state (Sec. IV-C). */
 nt_status nt_exhaustive(nt_ctx *ctx, const nt_circuit *c, double tau, double *fid_out, double P_e[3],
                         double *P_R);
 

@@ -46,8 +46,12 @@ EXPORTED = [
     "nt_sample_sites", "nt_final_state", "nt_reference_state", "nt_timing_enable",
     "nt_timing_reset", "nt_timing_read", "nt_last_error", "nt_version",
     "nt_set_shortcuts", "nt_exhaustive", "nt_eq4", "nt_eq5", "nt_success_probability",
+    "nt_set_criterion",
 ]
 
+NT_CRIT_FIDELITY = 0
+NT_CRIT_TARGET_PROB = 1
+NT_CRIT_HEAVY = 2
 NT_SHORTCUT_ZERO_FIRED = 1
 NT_SHORTCUT_CHECKPOINT = 2
 NT_SHORTCUT_LAST_ERROR = 4
@@ -100,6 +104,7 @@ def lib() -> C.CDLL:
         "nt_timing_reset": ([P], i32),
         "nt_timing_read": ([P, P, P, P, P, P], i32),
         "nt_set_shortcuts": ([P, i32], i32),
+        "nt_set_criterion": ([P, i32, u64], i32),
         "nt_exhaustive": ([P, P, dbl, P, P, P], i32),
         "nt_eq4": ([P, dbl, P, P], i32),
         "nt_eq5": ([dbl, P, dbl, dbl, P], i32),
@@ -308,6 +313,10 @@ def nt_reference_state(ctx, circ, prec: int) -> np.ndarray:
 
 def nt_set_shortcuts(ctx, flags: int) -> None:
     _check(lib().nt_set_shortcuts(ctx, flags))
+
+
+def nt_set_criterion(ctx, criterion: int, target: int = 0) -> None:
+    _check(lib().nt_set_criterion(ctx, criterion, target))
 
 
 def nt_exhaustive(ctx, circ, tau: float):

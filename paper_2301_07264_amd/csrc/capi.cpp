@@ -184,10 +184,13 @@ nt_status nt_run(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_
   if (s) return s;
   if (n_traj == 0) return fail(NT_ERR_INVALID_ARG, "n_traj must be > 0");
   return guard([&] {
+    nt::Ctx &cx = *ctx->impl;
     uint64_t cnt = 0;
-    ctx->impl->run(*c->impl, seed, traj_begin, n_traj, tau, fid_out, &cnt);
+    double sum = 0;
+    const bool fidc = cx.crit == NT_CRIT_FIDELITY;
+    cx.run(*c->impl, seed, traj_begin, n_traj, tau, fid_out, &cnt, (p_out && !fidc) ? &sum : nullptr);
     if (count_out) *count_out = cnt;
-    if (p_out) *p_out = (double)cnt / (double)n_traj;
+    if (p_out) *p_out = fidc ? (double)cnt / (double)n_traj : sum / (double)n_traj;
   });
 }
 
@@ -206,9 +209,7 @@ nt_status nt_sweep(nt_ctx *ctx, const nt_circuit *c, const double *rates, int R,
       for (int r = 0; r < R; ++r) {
         const double p3 = rates[r] / 3.0;
         cx.px = cx.py = cx.pz = p3;
-        uint64_t cnt = 0;
-        cx.run(*c->impl, seed, 0, n_traj, tau, nullptr, &cnt);
-        p_out[r] = (double)cnt / (double)n_traj;
+        p_out[r] = cx.success(*c->impl, seed, 0, n_traj, tau);
       }
     } catch (...) {
       cx.px = spx; cx.py = spy; cx.pz = spz;
@@ -234,10 +235,8 @@ nt_status nt_tolerable_rate(nt_ctx *ctx, const nt_circuit *c, double P_target, d
     const double spx = cx.px, spy = cx.py, spz = cx.pz;
     auto P_at = [&](double p) {
       cx.px = cx.py = cx.pz = p / 3.0;
-      uint64_t cnt = 0;
-      cx.run(*c->impl, seed, 0, n_traj, tau, nullptr, &cnt);
       ++probes;
-      return (double)cnt / (double)n_traj;
+      return cx.success(*c->impl, seed, 0, n_traj, tau);
     };
     try {
       // Safeguarded regula falsi (Illinois) in x = log10 p on
@@ -284,6 +283,18 @@ nt_status nt_set_shortcuts(nt_ctx *ctx, int flags) {
   if (flags & ~(NT_SHORTCUT_ZERO_FIRED | NT_SHORTCUT_CHECKPOINT | NT_SHORTCUT_LAST_ERROR))
     return fail(NT_ERR_INVALID_ARG, "unknown shortcut flag");
   ctx->impl->shortcuts = flags;
+  g_last_error.clear();
+  return NT_OK;
+}
+
+nt_status nt_set_criterion(nt_ctx *ctx, int criterion, uint64_t target) {
+  if (!ctx) return fail(NT_ERR_INVALID_ARG, "ctx is NULL");
+  if (criterion != NT_CRIT_FIDELITY && criterion != NT_CRIT_TARGET_PROB && criterion != NT_CRIT_HEAVY)
+    return fail(NT_ERR_INVALID_ARG, "unknown criterion");
+  if (criterion == NT_CRIT_TARGET_PROB && (target >> 32) != 0)
+    return fail(NT_ERR_INVALID_ARG, "target basis state beyond 32 qubits");
+  ctx->impl->crit = criterion;
+  ctx->impl->target = criterion == NT_CRIT_TARGET_PROB ? target : 0;
   g_last_error.clear();
   return NT_OK;
 }
@@ -341,9 +352,7 @@ nt_status nt_success_probability(nt_ctx *ctx, const nt_circuit *c, uint64_t seed
       if (method) *method = 0;
     } else {
       if (n_traj == 0) throw nt::Error(NT_ERR_INVALID_ARG, "n_traj must be > 0 for the Monte Carlo branch");
-      uint64_t cnt = 0;
-      cx.run(*c->impl, seed, 0, n_traj, tau, nullptr, &cnt);
-      *P = (double)cnt / (double)n_traj;
+      *P = cx.success(*c->impl, seed, 0, n_traj, tau);
       if (method) *method = 1;
     }
   });

@@ -379,7 +379,7 @@ static void run_passes(Ctx &cx, const Circuit &c, DevPlan &dp, ntk::cx<T> *state
     a.flags = (p == np - 1 ? r.last_flags : ntk::PF_STORE);
     if (r.capture) {
       a.flags = ntk::PF_STORE | ntk::PF_NORM;
-      a.partials = dp.ckpt_partials.as<double>() + (size_t)p * ((size_t)1 << (c.n - P.L)) * 3;
+      a.partials = dp.ckpt_partials.as<double>() + (size_t)p * ((size_t)1 << (c.n - P.L)) * ntk::NPART;
     }
     a.init_index = 0;
     a.pass = static_cast<const ntk::DevPass *>(dp.passes.p) + p;
@@ -390,6 +390,9 @@ static void run_passes(Ctx &cx, const Circuit &c, DevPlan &dp, ntk::cx<T> *state
     a.ref_here = r.end ? (p == np - 1 ? static_cast<const ntk::cx<T> *>(dp.ref.p)
                                       : dp.ckpt.as<ntk::cx<T>>() + (size_t)p * dim)
                        : nullptr;
+    a.crit = r.crit;
+    a.target = r.target;
+    a.heavy_med = r.heavy_med;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (cx.timing) {
       e0 = take_event(cx.ev_pool);
@@ -429,7 +432,7 @@ void Ctx::ensure_reference(const Circuit &c, DevPlan &dp) {
     throw Error(NT_ERR_OUT_OF_MEMORY, "not enough device memory for the reference state");
   dp.ref.ensure(dim * amp_bytes(dp.prec));
   dp.nref.ensure(sizeof(double));
-  dp.ref_partials.ensure(ntiles * 3 * sizeof(double));
+  dp.ref_partials.ensure(ntiles * ntk::NPART * sizeof(double));
   ev_count.ensure(sizeof(int32_t) * 4);
   events.ensure(16);
   check_hip(hipMemsetAsync(ev_count.p, 0, sizeof(int32_t), stream), "hipMemsetAsync");
@@ -459,7 +462,7 @@ void Ctx::simulate_batch(const Circuit &c, DevPlan &dp, uint64_t seed, uint64_t 
   const int S = (int)std::max<int64_t>(c.S, 1);
   events.ensure((size_t)B * S * 4);
   ev_count.ensure((size_t)B * 4);
-  partials.ensure((size_t)B * ntiles * 3 * sizeof(double));
+  partials.ensure((size_t)B * ntiles * ntk::NPART * sizeof(double));
   frames.ensure((size_t)B * 4 * sizeof(uint32_t));
   const bool need_states = P.passes.size() > 1 || mode == 1;
   if (need_states) states.ensure((size_t)B * dim * amp_bytes(dp.prec));
@@ -490,19 +493,21 @@ void Ctx::simulate_batch(const Circuit &c, DevPlan &dp, uint64_t seed, uint64_t 
   r.ev_stride = S;
   r.partials = partials.as<double>();
   r.frames = frames.as<uint32_t>();
+  if (mode == 0) criterion_args(c, dp, r);
   if (dp.prec == NT_C64) run_passes<float>(*this, c, dp, need_states ? states.as<ntk::cx<float>>() : nullptr, r);
   else run_passes<double>(*this, c, dp, need_states ? states.as<ntk::cx<double>>() : nullptr, r);
   if (mode == 0)
-    check_hip(ntk::launch_finalize(partials.as<double>(), (int)ntiles, B, dp.nref.as<double>(), nullptr, tau, fid_dev,
-                                   count_dev, stream),
+    check_hip(ntk::launch_finalize(partials.as<double>(), (int)ntiles, B, dp.nref.as<double>(), nullptr, r.crit, tau,
+                                   fid_dev, count_dev, stream),
               "k_finalize launch");
 }
 
 void Ctx::run(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
-              uint64_t *count_out) {
+              uint64_t *count_out, double *sum_out) {
   check_hip(hipSetDevice(device), "hipSetDevice");
+  check_target(c);
   if (shortcuts) {
-    run_shortcut(c, seed, t0, n, tau, fid_out, count_out);
+    run_shortcut(c, seed, t0, n, tau, fid_out, count_out, sum_out);
     return;
   }
   DevPlan &dp = plan_for(c, prec);
@@ -513,18 +518,102 @@ void Ctx::run(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double t
   count.ensure(sizeof(uint64_t));
   check_hip(hipMemsetAsync(count.p, 0, sizeof(uint64_t), stream), "hipMemsetAsync");
   if (!dev_out) fid.ensure((size_t)bs * sizeof(double));
+  // host copy of the values when their sum is asked for and fid_out is not on the host
+  std::vector<double> hv(sum_out && (!fid_out || dev_out) ? n : 0);
+  double *host_vals = sum_out ? (fid_out && !dev_out ? fid_out : hv.data()) : (dev_out ? nullptr : fid_out);
   for (uint64_t off = 0; off < n; off += bs) {
     const int B = (int)std::min<uint64_t>(bs, n - off);
     double *fd = dev_out ? fid_out + off : fid.as<double>();
     simulate_batch(c, dp, seed, t0 + off, B, 0, tau, fd, count.as<uint64_t>(), th);
-    if (fid_out && !dev_out)
-      check_hip(hipMemcpyAsync(fid_out + off, fd, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, stream),
+    if (host_vals)
+      check_hip(hipMemcpyAsync(host_vals + off, fd, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, stream),
                 "copy fidelities");
   }
   uint64_t cnt = 0;
   check_hip(hipMemcpyAsync(&cnt, count.p, sizeof cnt, hipMemcpyDeviceToHost, stream), "copy count");
   sync();
   if (count_out) *count_out = cnt;
+  if (sum_out) {
+    double sum = 0;
+    for (uint64_t i = 0; i < n; ++i) sum += host_vals[i];
+    *sum_out = sum;
+  }
+}
+
+void Ctx::check_target(const Circuit &c) const {
+  if (crit == NT_CRIT_TARGET_PROB && (target >> c.n) != 0)
+    throw Error(NT_ERR_INVALID_ARG, "target basis state out of range for this circuit");
+}
+
+double Ctx::success(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau) {
+  uint64_t cnt = 0;
+  double sum = 0;
+  run(c, seed, t0, n, tau, nullptr, &cnt, crit == NT_CRIT_FIDELITY ? nullptr : &sum);
+  return crit == NT_CRIT_FIDELITY ? (double)cnt / (double)n : sum / (double)n;
+}
+
+// Exact median of the error-free probabilities |a_k|^2 (FP64, computed as in
+// the scoring epilogue) by radix selection over their bit patterns: four
+// 16-bit digits, integer histograms on the device, the scan on the host.
+double Ctx::heavy_median(const Circuit &c, DevPlan &dp) {
+  if (dp.med_ready) return dp.heavy_med;
+  ensure_reference(c, dp);
+  const uint64_t dim = (uint64_t)1 << c.n;
+  hist.ensure(65536 * sizeof(uint32_t));
+  std::vector<uint32_t> h(65536);
+  auto select = [&](uint64_t k) {
+    uint64_t prefix = 0;
+    for (int shift = 48; shift >= 0; shift -= 16) {
+      check_hip(hipMemsetAsync(hist.p, 0, 65536 * sizeof(uint32_t), stream), "hipMemsetAsync");
+      if (dp.prec == NT_C64)
+        check_hip(ntk::launch_prob_hist<float>(dp.ref.as<ntk::cx<float>>(), dim, shift, prefix, hist.as<uint32_t>(),
+                                               stream), "k_prob_hist launch");
+      else
+        check_hip(ntk::launch_prob_hist<double>(dp.ref.as<ntk::cx<double>>(), dim, shift, prefix,
+                                                hist.as<uint32_t>(), stream), "k_prob_hist launch");
+      check_hip(hipMemcpyAsync(h.data(), hist.p, 65536 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream),
+                "copy histogram");
+      sync();
+      uint64_t d = 0;
+      for (; d < 65536; ++d) {
+        if (k < h[d]) break;
+        k -= h[d];
+      }
+      if (d == 65536) throw Error(NT_ERR_DEVICE, "median selection lost its rank");
+      prefix = (prefix << 16) | d;
+    }
+    double v;
+    std::memcpy(&v, &prefix, sizeof v);
+    return v;
+  };
+  double med;
+  if (dim & 1) med = select(dim / 2);
+  else med = 0.5 * (select(dim / 2 - 1) + select(dim / 2));
+  dp.heavy_med = med;
+  dp.med_ready = true;
+  return med;
+}
+
+double Ctx::reference_value(const Circuit &c, DevPlan &dp, double tau) {
+  if (crit == NT_CRIT_FIDELITY) return 1.0;   // F of the error-free state is exactly 1
+  const auto key = std::make_pair(crit, crit == NT_CRIT_TARGET_PROB ? target : (uint64_t)0);
+  auto it = dp.ref_value.find(key);
+  if (it != dp.ref_value.end()) return it->second;
+  // one entry without events, from the last checkpoint when there is one:
+  // bit-identical to an error-free trajectory run from pass 0
+  const int np = (int)dp.plan.passes.size();
+  const std::vector<uint32_t> ev(1, 0u);
+  const std::vector<int32_t> cnt(1, 0), st(1, (dp.ckpt_ready && np > 1) ? np - 1 : 0);
+  double v = 0;
+  score_entries(c, dp, 1, ev, 1, cnt, st, tau, &v);
+  dp.ref_value[key] = v;
+  return v;
+}
+
+void Ctx::criterion_args(const Circuit &c, DevPlan &dp, PassRun &r) {
+  r.crit = crit;
+  r.target = (uint32_t)target;
+  r.heavy_med = crit == NT_CRIT_HEAVY ? heavy_median(c, dp) : 0.0;
 }
 
 // Error-free checkpoints: the reference run repeated with the state copied
@@ -544,7 +633,7 @@ bool Ctx::ensure_checkpoints(const Circuit &c, DevPlan &dp) {
   if (bytes + states.bytes + ((size_t)4 << 30) > freeb + states.bytes) return false;
   dp.ckpt.ensure(bytes);
   const size_t ntiles = (size_t)1 << (c.n - dp.plan.L);
-  dp.ckpt_partials.ensure((size_t)np * ntiles * 3 * sizeof(double));
+  dp.ckpt_partials.ensure((size_t)np * ntiles * ntk::NPART * sizeof(double));
   dp.nref_pass.ensure((size_t)np * sizeof(double));
   bool was = timing;
   timing = false;
@@ -561,7 +650,7 @@ bool Ctx::ensure_checkpoints(const Circuit &c, DevPlan &dp) {
   if (dp.prec == NT_C64) run_passes<float>(*this, c, dp, dp.ref.as<ntk::cx<float>>(), r);
   else run_passes<double>(*this, c, dp, dp.ref.as<ntk::cx<double>>(), r);
   for (int p = 0; p < np; ++p)
-    check_hip(ntk::launch_norm_final(dp.ckpt_partials.as<double>() + (size_t)p * ntiles * 3, (int)ntiles,
+    check_hip(ntk::launch_norm_final(dp.ckpt_partials.as<double>() + (size_t)p * ntiles * ntk::NPART, (int)ntiles,
                                      dp.nref_pass.as<double>() + p, stream), "k_norm_final launch");
   timing = was;
   sync();
@@ -579,7 +668,7 @@ static void run_entries(Ctx &cx, const Circuit &c, DevPlan &dp, int B, int ev_st
   const int np = (int)P.passes.size();
   const size_t dim = (size_t)1 << c.n;
   const size_t ntiles = (size_t)1 << (c.n - P.L);
-  cx.partials.ensure((size_t)B * ntiles * 3 * sizeof(double));
+  cx.partials.ensure((size_t)B * ntiles * ntk::NPART * sizeof(double));
   cx.frames.ensure((size_t)B * 4 * sizeof(uint32_t));
   cx.fid.ensure((size_t)B * sizeof(double));
   cx.count.ensure(sizeof(uint64_t));
@@ -600,6 +689,7 @@ static void run_entries(Ctx &cx, const Circuit &c, DevPlan &dp, int B, int ev_st
   r.frames = cx.frames.as<uint32_t>();
   r.start = cx.start.as<int32_t>();
   r.active = &active;
+  cx.criterion_args(c, dp, r);
   if (end) {
     cx.end.ensure((size_t)B * sizeof(int32_t));
     check_hip(hipMemcpyAsync(cx.end.p, end->data(), (size_t)B * sizeof(int32_t), hipMemcpyHostToDevice, cx.stream),
@@ -609,7 +699,7 @@ static void run_entries(Ctx &cx, const Circuit &c, DevPlan &dp, int B, int ev_st
   if (dp.prec == NT_C64) run_passes<float>(cx, c, dp, np > 1 ? cx.states.as<ntk::cx<float>>() : nullptr, r);
   else run_passes<double>(cx, c, dp, np > 1 ? cx.states.as<ntk::cx<double>>() : nullptr, r);
   check_hip(ntk::launch_finalize(cx.partials.as<double>(), (int)ntiles, B,
-                                 end ? dp.nref_pass.as<double>() : dp.nref.as<double>(), r.end, tau,
+                                 end ? dp.nref_pass.as<double>() : dp.nref.as<double>(), r.end, r.crit, tau,
                                  cx.fid.as<double>(), cx.count.as<uint64_t>(), cx.stream),
             "k_finalize launch");
   check_hip(hipMemcpyAsync(fid_host, cx.fid.p, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, cx.stream),
@@ -633,11 +723,14 @@ void Ctx::score_entries(const Circuit &c, DevPlan &dp, int B, const std::vector<
 // trajectory starts from the error-free checkpoint before the pass holding
 // its first error.  Results are bit-identical to the plain run.
 void Ctx::run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
-                       uint64_t *count_out) {
+                       uint64_t *count_out, double *sum_out) {
   DevPlan &dp = plan_for(c, prec);
   ensure_reference(c, dp);
   const bool have_ckpt = (shortcuts & (SC_CHECKPOINT | SC_LAST_ERROR)) && ensure_checkpoints(c, dp);
-  const bool early_end = have_ckpt && (shortcuts & SC_LAST_ERROR);
+  // The measurement-probability criteria are not invariant under the
+  // error-free suffix of the circuit: no early scoring for them.
+  const bool early_end = have_ckpt && (shortcuts & SC_LAST_ERROR) && crit == NT_CRIT_FIDELITY;
+  const double v_ref = (shortcuts & SC_ZERO_FIRED) ? reference_value(c, dp, tau) : 0.0;
   const Thresholds th = make_thresholds(px, py, pz);
   const int S = (int)std::max<int64_t>(c.S, 1);
   const int np = (int)dp.plan.passes.size();
@@ -673,7 +766,7 @@ void Ctx::run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n,
     std::vector<std::tuple<int32_t, int32_t, int32_t>> act;
     for (int b = 0; b < Bc; ++b) {
       if (hcnt[b] == 0 && (shortcuts & SC_ZERO_FIRED)) {
-        fh[off + b] = 1.0;
+        fh[off + b] = v_ref;
         continue;
       }
       int32_t sp = 0, ep = np - 1;
@@ -711,8 +804,13 @@ void Ctx::run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n,
     }
   }
   uint64_t cnt = 0;
-  for (uint64_t i = 0; i < n; ++i) cnt += fh[i] >= tau ? 1 : 0;
+  double sum = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    cnt += fh[i] >= tau ? 1 : 0;
+    sum += fh[i];
+  }
   if (count_out) *count_out = cnt;
+  if (sum_out) *sum_out = sum;
   if (fid_out) {
     if (is_device_pointer(fid_out))
       check_hip(hipMemcpy(fid_out, fh.data(), n * sizeof(double), hipMemcpyHostToDevice), "copy fidelities");
@@ -725,6 +823,7 @@ void Ctx::run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n,
 // Pauli, one error each; entries in plan order start at their error's pass.
 void Ctx::exhaustive(const Circuit &c, double tau, double *fid_out, double P_e[3], double *P_R) {
   check_hip(hipSetDevice(device), "hipSetDevice");
+  check_target(c);
   DevPlan &dp = plan_for(c, prec);
   ensure_reference(c, dp);
   const bool have_ckpt = ensure_checkpoints(c, dp);
@@ -753,12 +852,18 @@ void Ctx::exhaustive(const Circuit &c, double tau, double *fid_out, double P_e[3
       fall[(size_t)P.app_site[(size_t)k] * 3 + (size_t)(i % 3)] = fsub[j];
     }
   }
+  // success of one state: F >= tau for the fidelity, the measurement
+  // probability itself for the other criteria
+  const bool fidc = crit == NT_CRIT_FIDELITY;
   for (int e = 0; e < 3; ++e) {
     double s = 0;
-    for (int64_t site = 0; site < S; ++site) s += fall[(size_t)site * 3 + e] >= tau ? 1.0 : 0.0;
+    for (int64_t site = 0; site < S; ++site) {
+      const double v = fall[(size_t)site * 3 + e];
+      s += fidc ? (v >= tau ? 1.0 : 0.0) : v;
+    }
     P_e[e] = S ? s / (double)S : 0.0;
   }
-  *P_R = 1.0 >= tau ? 1.0 : 0.0;
+  *P_R = fidc ? (1.0 >= tau ? 1.0 : 0.0) : reference_value(c, dp, tau);
   if (fid_out) std::memcpy(fid_out, fall.data(), (size_t)total * sizeof(double));
 }
 

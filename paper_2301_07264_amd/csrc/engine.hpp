@@ -32,6 +32,10 @@ struct DevPlan {
   DevBuf ckpt;                 // error-free state before passes 1..np-1
   DevBuf ckpt_partials, nref_pass;   // norms of the error-free state after each pass
   bool ckpt_ready = false;
+  double heavy_med = 0;        // median of the error-free probabilities (heavy criterion)
+  bool med_ready = false;
+  // criterion value of the error-free state, keyed by (criterion, target)
+  std::map<std::pair<int, uint64_t>, double> ref_value;
   std::vector<int> pass_of_op;
   std::vector<double> pass_flops_per_amp;   // algorithmic flops per amplitude, per pass
 };
@@ -49,6 +53,9 @@ struct PassRun {
   const std::vector<int> *active = nullptr;  // per pass: entries with start <= p
   const int32_t *end = nullptr;              // device: pass after which each entry is scored, or NULL
   bool capture = false;                      // copy the state into the checkpoints after each pass
+  int crit = 0;                              // success criterion of the scoring pass
+  uint32_t target = 0;
+  double heavy_med = 0;
 };
 
 // Shortcut flags (nt_set_shortcuts).
@@ -62,8 +69,10 @@ struct Ctx {
   int prec = NT_C128;
   uint64_t max_batch = 0;
   int shortcuts = 0;
+  int crit = 0;                // NT_CRIT_*
+  uint64_t target = 0;         // basis state of NT_CRIT_TARGET_PROB
   std::map<std::pair<uint64_t, int>, std::unique_ptr<DevPlan>> plans;
-  DevBuf states, events, ev_count, partials, fid, count, frames, tmp, tlist, start, end, firstlast;
+  DevBuf states, events, ev_count, partials, fid, count, frames, tmp, tlist, start, end, firstlast, hist;
   // timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
@@ -85,10 +94,22 @@ struct Ctx {
   void simulate_batch(const Circuit &c, DevPlan &dp, uint64_t seed, uint64_t t0, int B, int mode,
                       double tau, double *fid_dev, uint64_t *count_dev, const Thresholds &th);
 
+  // Per-trajectory criterion values to fid_out (host or device, may be
+  // NULL), the number of values >= tau to count_out, their sum (in
+  // trajectory order) to sum_out when given.
   void run(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
-           uint64_t *count_out);
+           uint64_t *count_out, double *sum_out = nullptr);
   void run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
-                    uint64_t *count_out);
+                    uint64_t *count_out, double *sum_out);
+  // Success probability of n trajectories: the fraction with F >= tau for
+  // the fidelity criterion, the mean measurement probability otherwise.
+  double success(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau);
+  // Criterion fields of a scoring run (computes the heavy-set median once).
+  void criterion_args(const Circuit &c, DevPlan &dp, PassRun &r);
+  double heavy_median(const Circuit &c, DevPlan &dp);
+  void check_target(const Circuit &c) const;
+  // Criterion value of the error-free state (1 for the fidelity).
+  double reference_value(const Circuit &c, DevPlan &dp, double tau);
   bool ensure_checkpoints(const Circuit &c, DevPlan &dp);
   // Score batch entries with explicit event lists (ev_stride words each, counts
   // given) and first passes `start` (sorted); fids to host.

@@ -409,35 +409,30 @@ DEV void apply_quad_lds(const DevOp<T> &op, cx<T> *lds, int L, uint32_t fx, uint
   }
 }
 
-// Deterministic block reduction of three doubles into out[0..2].
-DEV void block_reduce3(double v0, double v1, double v2, double *out, unsigned char *smem) {
+// Deterministic block reduction of NPART doubles into out[0..NPART).
+DEV void block_reduce(double (&v)[NPART], double *out, unsigned char *smem) {
   const int NT = blockDim.x;
   const int tid = threadIdx.x;
   const int width = NT < 64 ? NT : 64;
   for (int off = width >> 1; off > 0; off >>= 1) {
-    v0 = __dadd_rn(v0, __shfl_xor(v0, off, 64));
-    v1 = __dadd_rn(v1, __shfl_xor(v1, off, 64));
-    v2 = __dadd_rn(v2, __shfl_xor(v2, off, 64));
+#pragma unroll
+    for (int c = 0; c < NPART; ++c) v[c] = __dadd_rn(v[c], __shfl_xor(v[c], off, 64));
   }
   __syncthreads();                       // tile reads done; reuse LDS
   double *red = reinterpret_cast<double *>(smem);
   const int nw = (NT + 63) >> 6;
   if ((tid & 63) == 0) {
-    red[3 * (tid >> 6) + 0] = v0;
-    red[3 * (tid >> 6) + 1] = v1;
-    red[3 * (tid >> 6) + 2] = v2;
+#pragma unroll
+    for (int c = 0; c < NPART; ++c) red[NPART * (tid >> 6) + c] = v[c];
   }
   __syncthreads();
   if (tid == 0) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int w = 0; w < nw; ++w) {
-      s0 = __dadd_rn(s0, red[3 * w + 0]);
-      s1 = __dadd_rn(s1, red[3 * w + 1]);
-      s2 = __dadd_rn(s2, red[3 * w + 2]);
-    }
-    out[0] = s0;
-    out[1] = s1;
-    out[2] = s2;
+    double s[NPART] = {0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < nw; ++w)
+#pragma unroll
+      for (int c = 0; c < NPART; ++c) s[c] = __dadd_rn(s[c], red[NPART * w + c]);
+#pragma unroll
+    for (int c = 0; c < NPART; ++c) out[c] = s[c];
   }
 }
 
@@ -579,7 +574,8 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   asm volatile("" : "+v"(dlo));
   const size_t ntiles = (size_t)1 << a.ntile_bits;
   if (score_here) {
-    double ovr = 0.0, ovi = 0.0, nrm = 0.0;
+    double ovr = 0.0, ovi = 0.0, nrm = 0.0, mass = 0.0;
+    const uint32_t tgt = a.target ^ fx;   // psi[target] = +-s[target ^ x]
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const uint32_t g = tilebase | dlo | dhi(k);
@@ -593,9 +589,17 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
       const double rr = (double)r.x, ri = (double)r.y;
       ovr = __dadd_rn(ovr, __fma_rn(ri, si, __dmul_rn(rr, sr)));
       ovi = __dadd_rn(ovi, __fma_rn(-ri, sr, __dmul_rn(rr, si)));
-      nrm = __dadd_rn(nrm, __fma_rn(si, si, __dmul_rn(sr, sr)));
+      const double ps = __fma_rn(si, si, __dmul_rn(sr, sr));
+      nrm = __dadd_rn(nrm, ps);
+      if (a.crit == CRIT_TARGET) {
+        if (g == tgt) mass = __dadd_rn(mass, ps);
+      } else if (a.crit == CRIT_HEAVY) {
+        // heavy iff the error-free probability of index g ^ x exceeds the median
+        if (__fma_rn(ri, ri, __dmul_rn(rr, rr)) > a.heavy_med) mass = __dadd_rn(mass, ps);
+      }
     }
-    block_reduce3(ovr, ovi, nrm, a.partials + ((size_t)b * ntiles + tile) * 3, smem_raw);
+    double part[NPART] = {ovr, ovi, nrm, mass};
+    block_reduce(part, a.partials + ((size_t)b * ntiles + tile) * NPART, smem_raw);
   } else {
     double nrm = 0.0;
 #pragma unroll
@@ -606,8 +610,10 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
       const double sr = (double)s.x, si = (double)s.y;
       nrm = __dadd_rn(nrm, __fma_rn(si, si, __dmul_rn(sr, sr)));
     }
-    if (a.flags & PF_NORM)
-      block_reduce3(nrm, nrm, nrm, a.partials + ((size_t)b * ntiles + tile) * 3, smem_raw);
+    if (a.flags & PF_NORM) {
+      double part[NPART] = {nrm, 0.0, nrm, 0.0};
+      block_reduce(part, a.partials + ((size_t)b * ntiles + tile) * NPART, smem_raw);
+    }
   }
   if (a.frame_out && tile == 0 && tid == 0) {
     a.frame_out[4 * b + 0] = fx;
@@ -621,7 +627,7 @@ hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, hipStream_t s)
   const size_t ntiles = (size_t)1 << a.ntile_bits;
   const size_t blocks = ntiles * (size_t)a.B;
   size_t lds = ((size_t)1 << a.L) * sizeof(cx<T>);
-  if (lds < 16 * 3 * sizeof(double)) lds = 16 * 3 * sizeof(double);
+  if (lds < 16 * NPART * sizeof(double)) lds = 16 * NPART * sizeof(double);
   if (blocks == 0) return hipSuccess;
   if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
   // R = 4 work-groups are 2^(L-4) threads: 512 for complex64 (L = 13),
@@ -648,7 +654,7 @@ template hipError_t launch_pass<double>(const PassArgs<double> &, int, int, hipS
 DEV double sum_partials(const double *p, int ntiles, int comp, double *red) {
   const int tid = threadIdx.x, NT = blockDim.x;
   double acc = 0.0;
-  for (int t = tid; t < ntiles; t += NT) acc = __dadd_rn(acc, p[(size_t)t * 3 + comp]);
+  for (int t = tid; t < ntiles; t += NT) acc = __dadd_rn(acc, p[(size_t)t * NPART + comp]);
   for (int off = 32; off > 0; off >>= 1) acc = __dadd_rn(acc, __shfl_xor(acc, off, 64));
   __syncthreads();
   if ((tid & 63) == 0) red[tid >> 6] = acc;
@@ -660,28 +666,62 @@ DEV double sum_partials(const double *p, int ntiles, int comp, double *red) {
 }
 
 __global__ void __launch_bounds__(256) k_finalize(const double *partials, int ntiles, const double *nref,
-                                                  const int32_t *end, double tau, double *fid, uint64_t *count) {
+                                                  const int32_t *end, int crit, double tau, double *fid,
+                                                  uint64_t *count) {
   __shared__ double red[4];
   const int b = blockIdx.x;
-  const double *p = partials + (size_t)b * ntiles * 3;
+  const double *p = partials + (size_t)b * ntiles * NPART;
   const double ovr = sum_partials(p, ntiles, 0, red);
   const double ovi = sum_partials(p, ntiles, 1, red);
   const double nrm = sum_partials(p, ntiles, 2, red);
+  const double mass = sum_partials(p, ntiles, 3, red);
   if (threadIdx.x == 0) {
-    const double num = __fma_rn(ovi, ovi, __dmul_rn(ovr, ovr));
-    const double nr = end ? nref[end[b]] : nref[0];
-    const double F = __ddiv_rn(num, __dmul_rn(nr, nrm));
-    fid[b] = F;
-    if (F >= tau) atomicAdd((unsigned long long *)count, 1ull);
+    double v;
+    if (crit == CRIT_FIDELITY) {
+      const double num = __fma_rn(ovi, ovi, __dmul_rn(ovr, ovr));
+      const double nr = end ? nref[end[b]] : nref[0];
+      v = __ddiv_rn(num, __dmul_rn(nr, nrm));
+    } else {
+      v = __ddiv_rn(mass, nrm);
+    }
+    fid[b] = v;
+    if (v >= tau) atomicAdd((unsigned long long *)count, 1ull);
   }
 }
 
 hipError_t launch_finalize(const double *partials, int ntiles, int B, const double *nref, const int32_t *end,
-                           double tau, double *fid, uint64_t *count, hipStream_t s) {
+                           int crit, double tau, double *fid, uint64_t *count, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3(B), dim3(256), 0, s, partials, ntiles, nref, end, tau, fid, count);
+  hipLaunchKernelGGL(k_finalize, dim3(B), dim3(256), 0, s, partials, ntiles, nref, end, crit, tau, fid, count);
   return hipGetLastError();
 }
+
+// Radix-select step for the median of the error-free probabilities: the
+// probabilities are non-negative doubles, whose bit patterns order like the
+// values.  Integer atomics only, so the counts are exact.
+template <typename T>
+__global__ void __launch_bounds__(256) k_prob_hist(const cx<T> *a, uint64_t dim, int shift, uint64_t prefix,
+                                                   uint32_t *hist) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < dim; k += stride) {
+    const double re = (double)a[k].x, im = (double)a[k].y;
+    const uint64_t bits = (uint64_t)__double_as_longlong(__fma_rn(im, im, __dmul_rn(re, re)));
+    const uint64_t hi = (shift + 16 >= 64) ? 0 : (bits >> (shift + 16));
+    if (hi == prefix) atomicAdd(&hist[(bits >> shift) & 0xffffu], 1u);
+  }
+}
+
+template <typename T>
+hipError_t launch_prob_hist(const cx<T> *a, uint64_t dim, int shift, uint64_t prefix, uint32_t *hist,
+                            hipStream_t s) {
+  uint64_t blocks = (dim + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL((k_prob_hist<T>), dim3((uint32_t)blocks), dim3(256), 0, s, a, dim, shift, prefix, hist);
+  return hipGetLastError();
+}
+
+template hipError_t launch_prob_hist<float>(const cx<float> *, uint64_t, int, uint64_t, uint32_t *, hipStream_t);
+template hipError_t launch_prob_hist<double>(const cx<double> *, uint64_t, int, uint64_t, uint32_t *, hipStream_t);
 
 __global__ void __launch_bounds__(256) k_first_last(const uint32_t *events, const int32_t *ev_count, int ev_stride,
                                                     int B, uint32_t *out) {

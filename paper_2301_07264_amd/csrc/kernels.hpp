@@ -58,6 +58,16 @@ struct DevPass {
   uint8_t nlq[32];         // global qubit of tile-id bit i (ascending)
 };
 
+// Components of a per-tile scoring partial: overlap re, overlap im, norm of
+// the trajectory's state, criterion mass (probability of the target basis
+// state, or of the heavy set).
+constexpr int NPART = 4;
+
+// Success criteria (Sec. II): fidelity against the error-free state, the
+// probability of measuring one target basis state, the probability of the
+// heavy set (basis states whose error-free probability exceeds the median).
+enum : int32_t { CRIT_FIDELITY = 0, CRIT_TARGET = 1, CRIT_HEAVY = 2 };
+
 enum : int32_t {
   PF_SCORE = 2,   // overlap with the reference + norm (FP64 partials); no store
   PF_STORE = 4,   // write the tile back (always unless PF_SCORE)
@@ -73,7 +83,7 @@ struct PassArgs {
   const DevSeg *segs;
   const uint32_t *events;  // per trajectory, sorted by op: (op << 8) | (qubit << 2) | pauli
   const int32_t *ev_count;
-  double *partials;        // [B][ntiles][3]: overlap re, overlap im, norm
+  double *partials;        // [B][ntiles][NPART]
   uint32_t *frame_out;     // [B][4]: final Pauli frame x-mask, z-mask, phase
   uint64_t state_stride;
   int32_t ev_stride;
@@ -94,6 +104,9 @@ struct PassArgs {
   // `ref_here` (the error-free state after this pass) and skips later passes.
   const int32_t *end;
   const cx<T> *ref_here;
+  int32_t crit;            // CRIT_*
+  uint32_t target;         // CRIT_TARGET: basis state
+  double heavy_med;        // CRIT_HEAVY: median of the error-free probabilities
 };
 
 struct SampleArgs {
@@ -115,7 +128,12 @@ hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, hipStream_t s)
 // nref: reference norm (end == NULL) or per-pass reference norms indexed by
 // end[b].
 hipError_t launch_finalize(const double *partials, int ntiles, int B, const double *nref, const int32_t *end,
-                           double tau, double *fid, uint64_t *count, hipStream_t s);
+                           int crit, double tau, double *fid, uint64_t *count, hipStream_t s);
+// Histogram (65536 bins) of bits [shift, shift+16) of the FP64 probability
+// |a_k|^2 of every amplitude whose bits above shift+16 equal `prefix`.
+template <typename T>
+hipError_t launch_prob_hist(const cx<T> *a, uint64_t dim, int shift, uint64_t prefix, uint32_t *hist,
+                            hipStream_t s);
 // First and last event word of each trajectory (0 when it has none).
 hipError_t launch_first_last(const uint32_t *events, const int32_t *ev_count, int ev_stride, int B,
                              uint32_t *out, hipStream_t s);

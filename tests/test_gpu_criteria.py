@@ -1,0 +1,176 @@
+"""GPU parity of the measurement-probability criteria (Sec. II, Sec. V):
+probability of one target basis state, and heavy-output probability (mass on
+the basis states whose error-free probability exceeds the median).
+
+Bar, per trajectory value against the CPU oracle on identical seeds:
+  * complex128: |v_gpu - v_oracle| <= 1e-12;
+  * complex64:  |v_gpu - v_oracle| <= 3e-5.  A unit-norm state with L2 error
+    d moves any subset's mass by at most 2d + d^2, and the c64 state bar is
+    d <= 1e-5; the heavy set itself is decided on the device's reference
+    state, whose probabilities near the median differ from FP64 by ~1e-7
+    relative, which moves at most a few amplitudes of mass ~2^-n each.
+Success probabilities of these criteria are means of the values.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TAU = 0.5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2301_07264_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    c = P.nt_create(0)
+    yield c
+    P.nt_set_criterion(c, 0, 0)
+    P.nt_destroy(c)
+
+
+def _prec(P, prec):
+    return (P.NT_C64, 3e-5) if prec == "c64" else (P.NT_C128, 1e-12)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("n,layers", [(14, 6), (17, 5)])
+def test_criteria_monte_carlo_vs_oracle(P, ctx, orc, prec, n, layers):
+    pr, tol = _prec(P, prec)
+    c = W.random_layers(n, layers, np.random.default_rng(60 + n))
+    h = P.nt_circuit_load(None, c)
+    P.nt_set_precision(ctx, pr)
+    p = 0.02
+    P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+    N = 40
+    ref = orc.final_state_pattern(c, [], [])
+    target = int(np.argmax(np.abs(ref) ** 2))
+    for crit, tgt in ((P.NT_CRIT_TARGET_PROB, target), (P.NT_CRIT_HEAVY, 0)):
+        _say(f"criteria MC: n={n} prec={prec} crit={crit}")
+        P.nt_set_criterion(ctx, crit, tgt)
+        v = np.zeros(N)
+        cnt, Pm = P.nt_run(ctx, h, 3, 5, N, TAU, v)
+        want = orc.run_criterion(c, p / 3, p / 3, p / 3, 3, 5, N, crit, tgt)
+        assert np.abs(v - want).max() <= tol, (crit, np.abs(v - want).max())
+        s = 0.0
+        for x in v:
+            s += x
+        assert Pm == s / N
+        assert cnt == int((v >= TAU).sum())
+    P.nt_set_criterion(ctx, P.NT_CRIT_FIDELITY, 0)
+    P.nt_circuit_free(h)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_criteria_shortcuts_bit_identical(P, ctx, prec):
+    """Zero-fired and checkpoint short-cuts keep the values bit-identical; the
+    last-error short-cut is not applied to these criteria."""
+    pr, _ = _prec(P, prec)
+    c = W.random_layers(16, 5, np.random.default_rng(71))
+    h = P.nt_circuit_load(None, c)
+    P.nt_set_precision(ctx, pr)
+    P.nt_set_error_model(ctx, 1e-3 / 3, 1e-3 / 3, 1e-3 / 3)
+    N = 96
+    for crit, tgt in ((P.NT_CRIT_TARGET_PROB, 12345), (P.NT_CRIT_HEAVY, 0)):
+        _say(f"criteria shortcuts: prec={prec} crit={crit}")
+        P.nt_set_criterion(ctx, crit, tgt)
+        P.nt_set_shortcuts(ctx, 0)
+        base = np.zeros(N)
+        c0, p0 = P.nt_run(ctx, h, 4, 0, N, TAU, base)
+        for flags in (1, 2, 3, 7):
+            P.nt_set_shortcuts(ctx, flags)
+            f = np.zeros(N)
+            c1, p1 = P.nt_run(ctx, h, 4, 0, N, TAU, f)
+            np.testing.assert_array_equal(f.view(np.uint64), base.view(np.uint64))
+            assert c1 == c0 and p1 == p0
+    P.nt_set_shortcuts(ctx, 0)
+    P.nt_set_criterion(ctx, P.NT_CRIT_FIDELITY, 0)
+    P.nt_circuit_free(h)
+
+
+@pytest.mark.parametrize("n,layers", [(6, 3), (15, 2)])
+def test_criteria_exhaustive_vs_oracle(P, ctx, orc, n, layers):
+    c = W.random_layers(n, layers, np.random.default_rng(80 + n))
+    h = P.nt_circuit_load(None, c)
+    P.nt_set_precision(ctx, P.NT_C128)
+    ref = orc.final_state_pattern(c, [], [])
+    target = int(np.argmax(np.abs(ref) ** 2))
+    for crit, tgt in ((P.NT_CRIT_TARGET_PROB, target), (P.NT_CRIT_HEAVY, 0)):
+        _say(f"criteria exhaustive: n={n} crit={crit}")
+        P.nt_set_criterion(ctx, crit, tgt)
+        v, pe, pr = P.nt_exhaustive(ctx, h, TAU)
+        v_o, r_o = orc.exhaustive_criterion(c, crit, tgt)
+        assert np.abs(v - v_o).max() <= 1e-12
+        assert abs(pr - r_o) <= 1e-12
+        assert np.abs(pe - v_o.mean(0)).max() <= 1e-12
+        # method switch of Fig. 2 with these P_e, P_R
+        p = 1e-3
+        P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+        Pm, method = P.nt_success_probability(ctx, h, 0, 100, TAU)
+        E = [c.S * p / 3] * 3
+        if c.S * p <= 1:
+            assert method == 0 and abs(Pm - orc.eq4(pe, pr, E)) < 1e-15
+    P.nt_set_criterion(ctx, P.NT_CRIT_FIDELITY, 0)
+    P.nt_circuit_free(h)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_heavy_output_ghz_exact(P, ctx, orc, prec):
+    """GHZ: two basis states of probability 1/2, every other exactly 0, so the
+    median is 0 and ties are everywhere; single errors give values in
+    {0, 1/2, 1} that both sides must reproduce."""
+    pr, _ = _prec(P, prec)
+    c = W.ghz(10)
+    h = P.nt_circuit_load(None, c)
+    P.nt_set_precision(ctx, pr)
+    P.nt_set_criterion(ctx, P.NT_CRIT_HEAVY, 0)
+    v, pe, r = P.nt_exhaustive(ctx, h, TAU)
+    v_o, r_o = orc.exhaustive_criterion(c, 2)
+    assert r == 1.0 and r_o == 1.0
+    assert np.abs(v - v_o).max() <= 1e-6
+    P.nt_set_criterion(ctx, P.NT_CRIT_FIDELITY, 0)
+    P.nt_circuit_free(h)
+
+
+def test_criteria_sweep_vs_oracle(P, ctx, orc):
+    c = W.random_layers(12, 6, np.random.default_rng(90))
+    h = P.nt_circuit_load(None, c)
+    P.nt_set_precision(ctx, P.NT_C128)
+    P.nt_set_criterion(ctx, P.NT_CRIT_HEAVY, 0)
+    rates = [1e-3, 1e-2, 5e-2]
+    N = 64
+    ps = P.nt_sweep(ctx, h, rates, 6, N, TAU)
+    for r, pg in zip(rates, ps):
+        want = orc.run_criterion(c, r / 3, r / 3, r / 3, 6, 0, N, 2).mean()
+        assert abs(pg - want) <= 1e-12
+    P.nt_set_criterion(ctx, P.NT_CRIT_FIDELITY, 0)
+    P.nt_circuit_free(h)
+
+
+def test_criteria_error_paths(P, ctx):
+    with pytest.raises(P.NtError) as e:
+        P.nt_set_criterion(ctx, 3, 0)
+    assert e.value.status == P.NT_ERR_INVALID_ARG
+    c = W.random_layers(5, 1, np.random.default_rng(1))
+    h = P.nt_circuit_load(None, c)
+    P.nt_set_criterion(ctx, P.NT_CRIT_TARGET_PROB, 1 << 5)
+    with pytest.raises(P.NtError) as e:
+        P.nt_run(ctx, h, 0, 0, 4, TAU)
+    assert e.value.status == P.NT_ERR_INVALID_ARG
+    P.nt_set_criterion(ctx, P.NT_CRIT_FIDELITY, 0)
+    P.nt_circuit_free(h)
