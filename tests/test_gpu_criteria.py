@@ -174,3 +174,25 @@ def test_criteria_error_paths(P, ctx):
     assert e.value.status == P.NT_ERR_INVALID_ARG
     P.nt_set_criterion(ctx, P.NT_CRIT_FIDELITY, 0)
     P.nt_circuit_free(h)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_heavy_output_quantum_volume_vs_oracle(P, ctx, orc, prec):
+    """Quantum-volume model circuits (Haar-random U(4) on random pairs, all
+    general U2Q gates in LDS segments): heavy-output values per trajectory."""
+    pr, tol = _prec(P, prec)
+    P.nt_set_precision(ctx, pr)
+    P.nt_set_criterion(ctx, P.NT_CRIT_HEAVY, 0)
+    for n, d, s in ((10, 10, 3), (15, 15, 4)):
+        _say(f"QV heavy output: n={n} depth={d} prec={prec}")
+        c = W.quantum_volume(n, d, np.random.default_rng(s))
+        h = P.nt_circuit_load(None, c)
+        p = 0.01
+        P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+        N = 24
+        v = np.zeros(N)
+        P.nt_run(ctx, h, 1, 0, N, TAU, v)
+        want = orc.run_criterion(c, p / 3, p / 3, p / 3, 1, 0, N, 2)
+        assert np.abs(v - want).max() <= tol
+        P.nt_circuit_free(h)
+    P.nt_set_criterion(ctx, P.NT_CRIT_FIDELITY, 0)

@@ -476,3 +476,19 @@ def test_heavy_output_porter_thomas(orc):
     assert r2 == 1.0
     vals = orc.run_criterion(c, 0.0, 0.0, 0.0, 0, 0, 1, 2)
     assert abs(vals[0] - (1 + math.log(2)) / 2) < 0.02
+
+
+# Quantum-volume model circuits (general U2Q): the noiseless heavy-output
+# probability of a square model circuit approaches (1 + ln 2) / 2, and the
+# Pauli-twirled depolarizing limit (p -> 3/4 per touched qubit, uniform Paulis)
+# gives the uniform distribution, whose heavy mass is exactly 1/2.
+def test_heavy_output_quantum_volume(orc):
+    vals = []
+    for s in range(6):
+        c = W.quantum_volume(10, 10, np.random.default_rng(500 + s))
+        vals.append(orc.run_criterion(c, 0.0, 0.0, 0.0, 0, 0, 1, 2)[0])
+    assert abs(np.mean(vals) - (1 + math.log(2)) / 2) < 0.03
+    c = W.quantum_volume(6, 6, np.random.default_rng(7))
+    v = orc.run_criterion(c, 0.25, 0.25, 0.25, 0, 0, 400, 2)
+    # 400 trajectories of a fully scrambled state: mean 1/2 within ~5 sigma
+    assert abs(v.mean() - 0.5) < 0.05

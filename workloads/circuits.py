@@ -14,6 +14,8 @@ Workloads (all seeded with ``numpy.random.default_rng``):
   * GHZ preparation: H(0), CNOT(i -> i+1) for i = 0..n-2;
   * QFT: for j = n-1 down to 0: H(j), then for m = j-1 down to 0 a controlled
     phase CP(pi / 2**(j-m)) on (m, j); finally SWAP(q, n-1-q) for q < n//2;
+  * quantum-volume model circuits: per layer a random pairing with a
+    Haar-random U(4) on every pair;
   * alternating-layer circuit on a random 3-regular graph: H on every qubit,
     then R rounds of RZZ(gamma_r) on the edges (lexicographic, i < j) followed by
     RX(beta_r) on every qubit, gamma_r and beta_r uniform in [0, pi).
@@ -111,6 +113,27 @@ def qft(n: int) -> Circuit:
     for q in range(n // 2):
         gates.append(Gate("SWAP", (q, n - 1 - q)))
     return Circuit(n, gates, "qft")
+
+
+def haar_unitary(dim: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar-random dim x dim unitary: QR of a complex Gaussian matrix with the
+    phases of R's diagonal moved into Q (Mezzadri's recipe)."""
+    z = (rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))) / math.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    d = np.diag(r)
+    return q * (d / np.abs(d))
+
+
+def quantum_volume(n: int, depth: int, rng: np.random.Generator) -> Circuit:
+    """Quantum-volume-style model circuit: depth layers, each a random pairing
+    perm = rng.permutation(n) with a Haar-random U(4) (one U2Q gate) on
+    (perm[2i], perm[2i+1]); for odd n the last qubit of perm idles."""
+    gates: List[Gate] = []
+    for _ in range(depth):
+        perm = rng.permutation(n)
+        for i in range(n // 2):
+            gates.append(Gate("U2Q", (int(perm[2 * i]), int(perm[2 * i + 1])), (), haar_unitary(4, rng)))
+    return Circuit(n, gates, f"qv{n}x{depth}")
 
 
 def random_regular_graph(n: int, d: int, rng: np.random.Generator):
