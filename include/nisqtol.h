@@ -184,6 +184,23 @@ nt_status nt_run(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_
                  uint64_t n_traj, double tau, double *fid_out, uint64_t *count_out,
                  double *p_out);
 
+/* Batched Monte Carlo over many independent circuits (instances of
+ * different sizes): for each circuit i, trajectories [traj_begin,
+ * traj_begin + n_traj) under the context's error model, precision and
+ * criterion, with Philox key (seed, circuit id of circuits[i]).  Values are
+ * bit-identical to nt_run on each circuit alone (short-cuts are not applied).
+ * Circuits whose plan is a single pass over one tile share launches (one
+ * work-group per trajectory, per-circuit plan tables); larger ones run back
+ * to back without host synchronization.
+ * circuits: n_circ handles (a handle may repeat).  vals_out: [n_circ][n_traj]
+ * doubles, host or device, may be NULL.  count_out, p_out: n_circ entries on
+ * the host, may be NULL; p_out as in nt_run.  Device memory: the reference
+ * states of the circuits (held in the context's plan cache) plus one batch
+ * of trajectory states for the largest circuit. */
+nt_status nt_run_batch(nt_ctx *ctx, const nt_circuit *const *circuits, int n_circ, uint64_t seed,
+                       uint64_t traj_begin, uint64_t n_traj, double tau, double *vals_out,
+                       uint64_t *count_out, double *p_out);
+
 /* Success probability at each uniform rate rates[r] (p/3 per Pauli) with the
  * same trajectories [0, n_traj) at every rate.  p_out: R doubles (host).
  * The context's error model is left unchanged. */

@@ -46,7 +46,7 @@ EXPORTED = [
     "nt_sample_sites", "nt_final_state", "nt_reference_state", "nt_timing_enable",
     "nt_timing_reset", "nt_timing_read", "nt_last_error", "nt_version",
     "nt_set_shortcuts", "nt_exhaustive", "nt_eq4", "nt_eq5", "nt_success_probability",
-    "nt_set_criterion",
+    "nt_set_criterion", "nt_run_batch",
 ]
 
 NT_CRIT_FIDELITY = 0
@@ -78,6 +78,14 @@ def lib() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libnisqtol.so not built ({LIB_PATH}); run paper_2301_07264_amd.build.build()")
+    # PyTorch ships its own HIP runtime under the same soname.  Loaded first,
+    # it is the one the library binds to, so torch's device pointers and
+    # streams are valid here and the process holds a single runtime; loaded
+    # after the library, it would bring a second runtime that sees no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P, i32, i64, u64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_double
     PP = C.POINTER(C.c_void_p)
@@ -105,6 +113,7 @@ def lib() -> C.CDLL:
         "nt_timing_read": ([P, P, P, P, P, P], i32),
         "nt_set_shortcuts": ([P, i32], i32),
         "nt_set_criterion": ([P, i32, u64], i32),
+        "nt_run_batch": ([P, P, i32, u64, u64, u64, dbl, P, P, P], i32),
         "nt_exhaustive": ([P, P, dbl, P, P, P], i32),
         "nt_eq4": ([P, dbl, P, P], i32),
         "nt_eq5": ([dbl, P, dbl, dbl, P], i32),
@@ -254,6 +263,23 @@ def nt_run(ctx, circ, seed: int, traj_begin: int, n_traj: int, tau: float,
         fp = None
     _check(lib().nt_run(ctx, circ, seed, traj_begin, n_traj, tau, fp, C.byref(cnt), C.byref(p)))
     return cnt.value, p.value
+
+
+def nt_run_batch(ctx, circs, seed: int, traj_begin: int, n_traj: int, tau: float,
+                 vals_out: Optional[np.ndarray] = None, vals_out_ptr: Optional[int] = None):
+    """Many circuits at once.  Returns (counts[n_circ], p[n_circ]).  vals_out:
+    host float64 array [n_circ, n_traj], or vals_out_ptr: a device pointer."""
+    k = len(circs)
+    arr = (C.c_void_p * k)(*[C.c_void_p(h.value if isinstance(h, C.c_void_p) else h) for h in circs])
+    cnt = np.zeros(k, np.uint64)
+    p = np.zeros(k, np.float64)
+    if vals_out is not None:
+        assert vals_out.dtype == np.float64 and vals_out.size == k * n_traj and vals_out.flags.c_contiguous
+        vp = _ptr(vals_out)
+    else:
+        vp = C.c_void_p(vals_out_ptr) if vals_out_ptr else None
+    _check(lib().nt_run_batch(ctx, arr, k, seed, traj_begin, n_traj, tau, vp, _ptr(cnt), _ptr(p)))
+    return cnt, p
 
 
 def nt_sweep(ctx, circ, rates: Sequence[float], seed: int, n_traj: int, tau: float) -> np.ndarray:

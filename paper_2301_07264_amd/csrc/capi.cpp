@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "engine.hpp"
 
@@ -191,6 +192,31 @@ nt_status nt_run(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_
     cx.run(*c->impl, seed, traj_begin, n_traj, tau, fid_out, &cnt, (p_out && !fidc) ? &sum : nullptr);
     if (count_out) *count_out = cnt;
     if (p_out) *p_out = fidc ? (double)cnt / (double)n_traj : sum / (double)n_traj;
+  });
+}
+
+nt_status nt_run_batch(nt_ctx *ctx, const nt_circuit *const *circuits, int n_circ, uint64_t seed,
+                       uint64_t traj_begin, uint64_t n_traj, double tau, double *vals_out, uint64_t *count_out,
+                       double *p_out) {
+  if (!ctx) return fail(NT_ERR_INVALID_ARG, "ctx is NULL");
+  if (n_circ <= 0 || !circuits) return fail(NT_ERR_INVALID_ARG, "need n_circ > 0 circuits");
+  for (int i = 0; i < n_circ; ++i) {
+    nt_status s = check_run_args(ctx, circuits[i], tau);
+    if (s) return s;
+  }
+  if (n_traj == 0) return fail(NT_ERR_INVALID_ARG, "n_traj must be > 0");
+  if ((uint64_t)n_circ * n_traj > ((uint64_t)1 << 32)) return fail(NT_ERR_INVALID_ARG, "n_circ * n_traj too large");
+  return guard([&] {
+    nt::Ctx &cx = *ctx->impl;
+    std::vector<const nt::Circuit *> cs(n_circ);
+    for (int i = 0; i < n_circ; ++i) cs[i] = circuits[i]->impl;
+    std::vector<uint64_t> cnt(n_circ);
+    std::vector<double> sum(n_circ);
+    const bool fidc = cx.crit == NT_CRIT_FIDELITY;
+    cx.run_batch(cs, seed, traj_begin, n_traj, tau, vals_out, cnt.data(), (p_out && !fidc) ? sum.data() : nullptr);
+    if (count_out) std::memcpy(count_out, cnt.data(), n_circ * sizeof(uint64_t));
+    if (p_out)
+      for (int i = 0; i < n_circ; ++i) p_out[i] = fidc ? (double)cnt[i] / (double)n_traj : sum[i] / (double)n_traj;
   });
 }
 

@@ -42,6 +42,8 @@ bool is_device_pointer(const void *p) {
 DevBuf::~DevBuf() { release(); }
 
 void DevBuf::release() {
+  // queued work may still read the buffer
+  if (p) (void)hipDeviceSynchronize();
   if (p) (void)hipFree(p);
   p = nullptr;
   bytes = 0;
@@ -165,10 +167,13 @@ static void upload_ops(DevPlan &dp, const std::vector<int32_t> &code, const std:
 DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
   auto key = std::make_pair(c.serial, pr);
   auto it = plans.find(key);
-  if (it != plans.end()) return *it->second;
-  // keep at most a few plans (each may hold a reference state)
-  if (plans.size() >= 4) plans.clear();
+  if (it != plans.end()) {
+    it->second->last_use = ++use_clock;
+    return *it->second;
+  }
+  evict_plans();
   auto dp = std::make_unique<DevPlan>();
+  dp->last_use = ++use_clock;
   dp->prec = pr;
   int L, R, cfix;
   plan_for_precision(c, pr, &L, &R, &cfix);
@@ -291,6 +296,25 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
   DevPlan &ref = *dp;
   plans.emplace(key, std::move(dp));
   return ref;
+}
+
+// Drop least-recently-used plans (and their reference states and
+// checkpoints) until one more fits under the count and byte budgets; plans
+// pinned by a batched run stay.
+void Ctx::evict_plans() {
+  for (;;) {
+    size_t bytes = 0;
+    auto victim = plans.end();
+    for (auto it = plans.begin(); it != plans.end(); ++it) {
+      bytes += it->second->footprint();
+      if (it->second->pins == 0 && (victim == plans.end() || it->second->last_use < victim->second->last_use))
+        victim = it;
+    }
+    if (plans.size() < max_plans && bytes <= plan_budget) return;
+    if (victim == plans.end()) return;
+    sync();   // its buffers may still be read by queued work
+    plans.erase(victim);
+  }
 }
 
 uint64_t Ctx::batch_size(const Circuit &c, const DevPlan &dp, uint64_t n_traj) {
@@ -450,6 +474,7 @@ void Ctx::ensure_reference(const Circuit &c, DevPlan &dp) {
   timing = was;
   check_hip(ntk::launch_norm_final(dp.ref_partials.as<double>(), (int)ntiles, dp.nref.as<double>(), stream),
             "k_norm_final launch");
+  check_hip(hipMemcpyAsync(&dp.nref_host, dp.nref.p, sizeof(double), hipMemcpyDeviceToHost, stream), "copy norm");
   sync();
   dp.ref_ready = true;
 }
@@ -946,6 +971,220 @@ void Ctx::reference_state(const Circuit &c, void *out, int64_t len) {
   check_hip(hipMemcpyAsync(out, dp.ref.p, bytes, is_device_pointer(out) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                            stream), "copy reference");
   sync();
+}
+
+}  // namespace nt
+
+namespace nt {
+
+// Batched Monte Carlo over many circuits.  Circuits whose plan is one pass
+// over one tile (n <= tile width) are grouped by tile shape; each group runs
+// as one sampling launch, one gate-pass launch and one finalize launch per
+// trajectory chunk, with per-circuit plan pointers in a descriptor table.
+// Larger circuits run their usual pass sequence back to back on the stream,
+// with no host synchronization between circuits.
+void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint64_t t0, uint64_t n, double tau,
+                    double *vals_out, uint64_t *counts_out, double *sums_out) {
+  check_hip(hipSetDevice(device), "hipSetDevice");
+  const size_t nc = cs.size();
+  for (const Circuit *c : cs) check_target(*c);
+  const Thresholds th = make_thresholds(px, py, pz);
+  const bool dev_out = is_device_pointer(vals_out);
+  bvals.ensure(nc * n * sizeof(double));
+  bcounts.ensure(nc * sizeof(uint64_t));
+  check_hip(hipMemsetAsync(bcounts.p, 0, nc * sizeof(uint64_t), stream), "hipMemsetAsync");
+  double *vals_dev = dev_out ? vals_out : bvals.as<double>();
+  const bool c64 = prec == NT_C64;
+
+  size_t i0 = 0;
+  while (i0 < nc) {
+    // a window of circuits whose plans and reference states are held together
+    std::vector<DevPlan *> dps;
+    size_t bytes = 0, i1 = i0;
+    while (i1 < nc) {
+      DevPlan &dp = plan_for(*cs[i1], prec);
+      ++dp.pins;
+      dps.push_back(&dp);
+      ensure_reference(*cs[i1], dp);
+      if (crit == NT_CRIT_HEAVY) heavy_median(*cs[i1], dp);
+      bytes += dp.footprint();
+      ++i1;
+      if (bytes > plan_budget / 2) break;
+    }
+    struct Unpin {
+      std::vector<DevPlan *> &v;
+      ~Unpin() { for (DevPlan *d : v) --d->pins; }
+    } unpin{dps};
+
+    // group the one-pass, one-tile circuits by tile shape
+    std::map<std::pair<int, int>, std::vector<size_t>> groups;   // (L, R) -> window slots
+    std::vector<size_t> big;
+    for (size_t k = 0; k < dps.size(); ++k) {
+      const Plan &P = dps[k]->plan;
+      if (P.passes.size() == 1 && P.L == cs[i0 + k]->n) groups[{P.L, P.R}].push_back(k);
+      else big.push_back(k);
+    }
+    // descriptor tables of every group, uploaded once for the window
+    std::vector<ntk::MultiItem<float>> mf;
+    std::vector<ntk::MultiItem<double>> md;
+    std::vector<ntk::SampleItem> si;
+    std::vector<int32_t> imap;
+    std::vector<double> nref;
+    std::vector<size_t> gbase;
+    for (auto &g : groups) {
+      gbase.push_back(si.size());
+      for (size_t k : g.second) {
+        DevPlan &dp = *dps[k];
+        const Circuit &c = *cs[i0 + k];
+        const Pass &ps = dp.plan.passes[0];
+        ntk::MultiItem<float> a;
+        ntk::MultiItem<double> b;
+        std::memset(&a, 0, sizeof a);
+        std::memset(&b, 0, sizeof b);
+        a.ops = static_cast<const ntk::DevOp<float> *>(dp.ops.p);
+        b.ops = static_cast<const ntk::DevOp<double> *>(dp.ops.p);
+        a.segs = b.segs = static_cast<const ntk::DevSeg *>(dp.segs.p);
+        a.pass = b.pass = static_cast<const ntk::DevPass *>(dp.passes.p);
+        a.ref = static_cast<const ntk::cx<float> *>(dp.ref.p);
+        b.ref = static_cast<const ntk::cx<double> *>(dp.ref.p);
+        a.seg_begin = b.seg_begin = ps.seg_begin;
+        a.seg_end = b.seg_end = ps.seg_end;
+        a.op_begin = b.op_begin = ps.op_begin;
+        a.heavy_med = b.heavy_med = dp.heavy_med;
+        mf.push_back(a);
+        md.push_back(b);
+        ntk::SampleItem s;
+        std::memset(&s, 0, sizeof s);
+        s.cid = c.cid;
+        s.order = dp.app_order.as<int32_t>();
+        s.tag = dp.app_tag.as<uint32_t>();
+        s.S = (int32_t)c.S;
+        si.push_back(s);
+        imap.push_back((int32_t)(i0 + k));
+        nref.push_back(dp.nref_host);
+      }
+    }
+    if (!si.empty()) {
+      const size_t ni = si.size();
+      multi_items.ensure(ni * (c64 ? sizeof(ntk::MultiItem<float>) : sizeof(ntk::MultiItem<double>)));
+      sample_items.ensure(ni * sizeof(ntk::SampleItem));
+      item_map.ensure(ni * sizeof(int32_t));
+      multi_nref.ensure(ni * sizeof(double));
+      if (c64)
+        check_hip(hipMemcpyAsync(multi_items.p, mf.data(), ni * sizeof(ntk::MultiItem<float>), hipMemcpyHostToDevice,
+                                 stream), "upload batch tables");
+      else
+        check_hip(hipMemcpyAsync(multi_items.p, md.data(), ni * sizeof(ntk::MultiItem<double>),
+                                 hipMemcpyHostToDevice, stream), "upload batch tables");
+      check_hip(hipMemcpyAsync(sample_items.p, si.data(), ni * sizeof(ntk::SampleItem), hipMemcpyHostToDevice, stream),
+                "upload batch tables");
+      check_hip(hipMemcpyAsync(item_map.p, imap.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice, stream),
+                "upload batch tables");
+      check_hip(hipMemcpyAsync(multi_nref.p, nref.data(), ni * sizeof(double), hipMemcpyHostToDevice, stream),
+                "upload batch tables");
+    }
+    size_t gi = 0;
+    for (auto &g : groups) {
+      const int L = g.first.first, R = g.first.second;
+      const size_t base = gbase[gi++];
+      const size_t ng = g.second.size();
+      int64_t smax = 1;
+      for (size_t k : g.second) smax = std::max<int64_t>(smax, cs[i0 + k]->S);
+      // trajectories per circuit per launch: bounded work-group count and event memory
+      uint64_t bc = std::min<uint64_t>(n, std::max<uint64_t>(1, ((uint64_t)1 << 20) / ng));
+      bc = std::min<uint64_t>(bc, std::max<uint64_t>(1, (((uint64_t)512 << 20) / (4 * (uint64_t)smax)) / ng));
+      for (uint64_t off = 0; off < n; off += bc) {
+        const int per = (int)std::min<uint64_t>(bc, n - off);
+        const int items = (int)(ng * (size_t)per);
+        events.ensure((size_t)items * smax * 4);
+        ev_count.ensure((size_t)items * 4);
+        partials.ensure((size_t)items * ntk::NPART * sizeof(double));
+        ntk::SampleArgs sa;
+        std::memset(&sa, 0, sizeof sa);
+        sa.seed = seed;
+        sa.t0 = t0 + off;
+        sa.t_fire = th.t_fire;
+        sa.c_x = th.c_x;
+        sa.c_xy = th.c_xy;
+        sa.always = th.always;
+        sa.B = items;
+        sa.ev_stride = (int)smax;
+        sa.events = events.as<uint32_t>();
+        sa.ev_count = ev_count.as<int32_t>();
+        sa.multi = sample_items.as<ntk::SampleItem>() + base;
+        sa.per_item = per;
+        check_hip(ntk::launch_sample(sa, stream), "k_sample launch");
+        const int nthreads = 1 << (L - R);
+        if (c64) {
+          ntk::PassArgs<float> a;
+          std::memset(&a, 0, sizeof a);
+          a.events = events.as<uint32_t>();
+          a.ev_count = ev_count.as<int32_t>();
+          a.partials = partials.as<double>();
+          a.ev_stride = (int)smax;
+          a.B = items;
+          a.L = L;
+          a.flags = ntk::PF_SCORE;
+          a.crit = crit;
+          a.target = (uint32_t)target;
+          a.multi = multi_items.as<ntk::MultiItem<float>>() + base;
+          a.per_item = per;
+          check_hip(ntk::launch_pass<float>(a, R, nthreads, stream), "k_pass launch");
+        } else {
+          ntk::PassArgs<double> a;
+          std::memset(&a, 0, sizeof a);
+          a.events = events.as<uint32_t>();
+          a.ev_count = ev_count.as<int32_t>();
+          a.partials = partials.as<double>();
+          a.ev_stride = (int)smax;
+          a.B = items;
+          a.L = L;
+          a.flags = ntk::PF_SCORE;
+          a.crit = crit;
+          a.target = (uint32_t)target;
+          a.multi = multi_items.as<ntk::MultiItem<double>>() + base;
+          a.per_item = per;
+          check_hip(ntk::launch_pass<double>(a, R, nthreads, stream), "k_pass launch");
+        }
+        check_hip(ntk::launch_finalize_multi(partials.as<double>(), 1, items, multi_nref.as<double>() + base, per,
+                                             item_map.as<int32_t>() + base, (int64_t)n, (int64_t)off, crit, tau,
+                                             vals_dev, bcounts.as<uint64_t>(), stream),
+                  "k_finalize launch");
+      }
+    }
+    for (size_t k : big) {
+      const Circuit &c = *cs[i0 + k];
+      DevPlan &dp = *dps[k];
+      const uint64_t bs = batch_size(c, dp, n);
+      for (uint64_t off = 0; off < n; off += bs) {
+        const int B = (int)std::min<uint64_t>(bs, n - off);
+        simulate_batch(c, dp, seed, t0 + off, B, 0, tau, vals_dev + (i0 + k) * n + off,
+                       bcounts.as<uint64_t>() + (i0 + k), th);
+      }
+    }
+    sync();   // host tables of this window go out of scope
+    i0 = i1;
+  }
+  std::vector<double> hv;
+  double *host_vals = nullptr;
+  if (vals_out && !dev_out) host_vals = vals_out;
+  else if (sums_out) {
+    hv.resize(nc * n);
+    host_vals = hv.data();
+  }
+  if (host_vals)
+    check_hip(hipMemcpyAsync(host_vals, vals_dev, nc * n * sizeof(double), hipMemcpyDeviceToHost, stream),
+              "copy values");
+  std::vector<uint64_t> hc(nc);
+  check_hip(hipMemcpyAsync(hc.data(), bcounts.p, nc * sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "copy counts");
+  sync();
+  if (counts_out) std::memcpy(counts_out, hc.data(), nc * sizeof(uint64_t));
+  if (sums_out)
+    for (size_t i = 0; i < nc; ++i) {
+      double s = 0;
+      for (uint64_t j = 0; j < n; ++j) s += host_vals[i * n + j];
+      sums_out[i] = s;
+    }
 }
 
 }  // namespace nt

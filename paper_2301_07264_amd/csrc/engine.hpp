@@ -32,12 +32,16 @@ struct DevPlan {
   DevBuf ckpt;                 // error-free state before passes 1..np-1
   DevBuf ckpt_partials, nref_pass;   // norms of the error-free state after each pass
   bool ckpt_ready = false;
+  double nref_host = 0;        // <R|R>, copied once the reference is built
   double heavy_med = 0;        // median of the error-free probabilities (heavy criterion)
   bool med_ready = false;
   // criterion value of the error-free state, keyed by (criterion, target)
   std::map<std::pair<int, uint64_t>, double> ref_value;
   std::vector<int> pass_of_op;
   std::vector<double> pass_flops_per_amp;   // algorithmic flops per amplitude, per pass
+  uint64_t last_use = 0;       // plan cache: least recently used goes first
+  int pins = 0;                // > 0 while a batched run holds it
+  size_t footprint() const { return ref.bytes + ckpt.bytes + ckpt_partials.bytes + ref_partials.bytes; }
 };
 
 // Arguments of one run of all passes over a batch (engine.cpp).
@@ -72,6 +76,12 @@ struct Ctx {
   int crit = 0;                // NT_CRIT_*
   uint64_t target = 0;         // basis state of NT_CRIT_TARGET_PROB
   std::map<std::pair<uint64_t, int>, std::unique_ptr<DevPlan>> plans;
+  uint64_t use_clock = 0;
+  size_t plan_budget = (size_t)24 << 30;   // device bytes held by cached plans
+  size_t max_plans = 4096;
+  void evict_plans();
+  // batched runs: per-launch descriptor tables and per-circuit results
+  DevBuf multi_items, sample_items, item_map, multi_nref, bvals, bcounts;
   DevBuf states, events, ev_count, partials, fid, count, frames, tmp, tlist, start, end, firstlast, hist;
   // timing
   bool timing = false;
@@ -104,6 +114,12 @@ struct Ctx {
   // Success probability of n trajectories: the fraction with F >= tau for
   // the fidelity criterion, the mean measurement probability otherwise.
   double success(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau);
+  // Many circuits, trajectories [t0, t0 + n) of each: values [n_circ][n]
+  // (host or device, may be NULL), success counts and value sums per
+  // circuit (host, may be NULL).  Single-pass circuits of one tile shape
+  // share launches; the values equal those of run() on each circuit.
+  void run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint64_t t0, uint64_t n, double tau,
+                 double *vals_out, uint64_t *counts_out, double *sums_out);
   // Criterion fields of a scoring run (computes the heavy-set median once).
   void criterion_args(const Circuit &c, DevPlan &dp, PassRun &r);
   double heavy_median(const Circuit &c, DevPlan &dp);

@@ -57,19 +57,31 @@ __global__ void __launch_bounds__(256) k_sample(const SampleArgs a) {
   const int lane = threadIdx.x & 63;
   const int b = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (b >= a.B) return;                       // whole wavefront leaves together
-  const uint64_t t = a.tlist ? a.tlist[b] : a.t0 + (uint64_t)b;
+  uint64_t t = a.tlist ? a.tlist[b] : a.t0 + (uint64_t)b;
+  uint64_t cid = a.cid;
+  int S = a.S;
+  const int32_t *order = a.order;
+  const uint32_t *tag = a.tag;
+  if (a.multi) {
+    const SampleItem &m = a.multi[b / a.per_item];
+    t = a.t0 + (uint64_t)(b % a.per_item);
+    cid = m.cid;
+    S = m.S;
+    order = m.order;
+    tag = m.tag;
+  }
   uint32_t *ev = a.events + (size_t)b * a.ev_stride;
   int base = 0;
-  for (int k0 = 0; k0 < a.S; k0 += 64) {
+  for (int k0 = 0; k0 < S; k0 += 64) {
     const int k = k0 + lane;
     bool fire = false;
     uint32_t code = 0;
-    if (k < a.S) {
+    if (k < S) {
       uint64_t w0, w1;
-      philox4x64_10((uint64_t)(uint32_t)a.order[k], t, 0, 0, a.seed, a.cid, w0, w1);
+      philox4x64_10((uint64_t)(uint32_t)order[k], t, 0, 0, a.seed, cid, w0, w1);
       fire = (a.always & 1u) || (w0 < a.t_fire);
       uint32_t pa = ((a.always & 2u) || w1 < a.c_x) ? 1u : (((a.always & 4u) || w1 < a.c_xy) ? 2u : 3u);
-      code = a.tag[k] | pa;
+      code = tag[k] | pa;
     }
     const uint64_t mask = __ballot(fire);
     const int pos = base + (int)__popcll(mask & ((1ull << lane) - 1ull));
@@ -451,8 +463,24 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   if (a.end && a.pass_index > a.end[b]) return;
   const bool score_here = a.end ? (a.end[b] == a.pass_index) : ((a.flags & PF_SCORE) != 0);
   const cx<T> *refp = a.end ? a.ref_here : a.ref;
+  const DevOp<T> *ops = a.ops;
+  const DevSeg *segs = a.segs;
+  const DevPass *passp = a.pass;
+  int seg_begin = a.seg_begin, seg_end = a.seg_end, op_begin = a.op_begin;
+  double heavy_med = a.heavy_med;
+  if (a.multi) {
+    const MultiItem<T> &m = a.multi[b / a.per_item];
+    ops = m.ops;
+    segs = m.segs;
+    passp = m.pass;
+    refp = m.ref;
+    seg_begin = m.seg_begin;
+    seg_end = m.seg_end;
+    op_begin = m.op_begin;
+    heavy_med = m.heavy_med;
+  }
 
-  const DevPass &ps = *a.pass;
+  const DevPass &ps = *passp;
   uint32_t tilebase = 0;
   for (int i = 0; i < a.ntile_bits; ++i) tilebase |= ((tile >> i) & 1u) << ps.nlq[i];
   cx<T> *st = a.state + (uint64_t)b * a.state_stride;
@@ -506,7 +534,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   uint32_t next_e = 0, next_op = 0xffffffffu;
   while (ep < ne) {
     next_e = __builtin_amdgcn_readfirstlane(ev[ep]);
-    if ((int)(next_e >> 8) >= a.op_begin) break;
+    if ((int)(next_e >> 8) >= op_begin) break;
     frame_apply(next_e, fx, fz, fc);
     ++ep;
   }
@@ -524,10 +552,10 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     }
   };
 
-  for (int s = a.seg_begin; s < a.seg_end; ++s) {
-    const DevSeg &sg = a.segs[s];
+  for (int s = seg_begin; s < seg_end; ++s) {
+    const DevSeg &sg = segs[s];
     if (sg.kind == SEG_KIND_QUAD) {
-      apply_quad_lds<T>(a.ops[sg.op_begin], lds, a.L, fx, fz);
+      apply_quad_lds<T>(ops[sg.op_begin], lds, a.L, fx, fz);
       take_events(sg.op_begin);
       __syncthreads();
       continue;
@@ -555,10 +583,10 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
 #pragma unroll
     for (int r = 0; r < NS; ++r) v[r] = slot(r);
     if (sg.op_begin < sg.op_end) {
-      OpLite<T> cur = load_lite(a.ops, sg.op_begin);
+      OpLite<T> cur = load_lite(ops, sg.op_begin);
       for (int o = sg.op_begin; o < sg.op_end; ++o) {
         OpLite<T> nxt = cur;
-        if (o + 1 < sg.op_end) nxt = load_lite(a.ops, o + 1);   // next op's loads in flight
+        if (o + 1 < sg.op_end) nxt = load_lite(ops, o + 1);   // next op's loads in flight
         apply_reg_op<R, T>(cur, v, gb, fx, fz);
         take_events(o);
         cur = nxt;
@@ -576,6 +604,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   if (score_here) {
     double ovr = 0.0, ovi = 0.0, nrm = 0.0, mass = 0.0;
     const uint32_t tgt = a.target ^ fx;   // psi[target] = +-s[target ^ x]
+    const bool want_t = a.crit == CRIT_TARGET, want_h = a.crit == CRIT_HEAVY;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const uint32_t g = tilebase | dlo | dhi(k);
@@ -591,12 +620,9 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
       ovi = __dadd_rn(ovi, __fma_rn(-ri, sr, __dmul_rn(rr, si)));
       const double ps = __fma_rn(si, si, __dmul_rn(sr, sr));
       nrm = __dadd_rn(nrm, ps);
-      if (a.crit == CRIT_TARGET) {
-        if (g == tgt) mass = __dadd_rn(mass, ps);
-      } else if (a.crit == CRIT_HEAVY) {
-        // heavy iff the error-free probability of index g ^ x exceeds the median
-        if (__fma_rn(ri, ri, __dmul_rn(rr, rr)) > a.heavy_med) mass = __dadd_rn(mass, ps);
-      }
+      // heavy iff the error-free probability of index g ^ x exceeds the median
+      const bool in = want_t ? (g == tgt) : (want_h && __fma_rn(ri, ri, __dmul_rn(rr, rr)) > heavy_med);
+      mass = __dadd_rn(mass, in ? ps : 0.0);
     }
     double part[NPART] = {ovr, ovi, nrm, mass};
     block_reduce(part, a.partials + ((size_t)b * ntiles + tile) * NPART, smem_raw);
@@ -665,9 +691,12 @@ DEV double sum_partials(const double *p, int ntiles, int comp, double *red) {
   return s;
 }
 
+// Entry b of a batched launch (per_item > 0) is trajectory b % per_item of
+// circuit slot b / per_item.
 __global__ void __launch_bounds__(256) k_finalize(const double *partials, int ntiles, const double *nref,
-                                                  const int32_t *end, int crit, double tau, double *fid,
-                                                  uint64_t *count) {
+                                                  const int32_t *end, int per_item, const int32_t *item_map,
+                                                  int64_t out_stride, int64_t out_off, int crit, double tau,
+                                                  double *fid, uint64_t *count) {
   __shared__ double red[4];
   const int b = blockIdx.x;
   const double *p = partials + (size_t)b * ntiles * NPART;
@@ -676,23 +705,43 @@ __global__ void __launch_bounds__(256) k_finalize(const double *partials, int nt
   const double nrm = sum_partials(p, ntiles, 2, red);
   const double mass = sum_partials(p, ntiles, 3, red);
   if (threadIdx.x == 0) {
+    int slot = 0;
+    int64_t out = b;
+    uint64_t *cnt = count;
+    if (per_item > 0) {
+      slot = b / per_item;
+      const int64_t ci = item_map[slot];
+      out = ci * out_stride + out_off + (b % per_item);
+      cnt = count + ci;
+    }
     double v;
     if (crit == CRIT_FIDELITY) {
       const double num = __fma_rn(ovi, ovi, __dmul_rn(ovr, ovr));
-      const double nr = end ? nref[end[b]] : nref[0];
+      const double nr = per_item > 0 ? nref[slot] : (end ? nref[end[b]] : nref[0]);
       v = __ddiv_rn(num, __dmul_rn(nr, nrm));
     } else {
       v = __ddiv_rn(mass, nrm);
     }
-    fid[b] = v;
-    if (v >= tau) atomicAdd((unsigned long long *)count, 1ull);
+    fid[out] = v;
+    if (v >= tau) atomicAdd((unsigned long long *)cnt, 1ull);
   }
 }
 
 hipError_t launch_finalize(const double *partials, int ntiles, int B, const double *nref, const int32_t *end,
                            int crit, double tau, double *fid, uint64_t *count, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3(B), dim3(256), 0, s, partials, ntiles, nref, end, crit, tau, fid, count);
+  hipLaunchKernelGGL(k_finalize, dim3(B), dim3(256), 0, s, partials, ntiles, nref, end, 0, (const int32_t *)nullptr,
+                     (int64_t)0, (int64_t)0, crit, tau, fid, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_multi(const double *partials, int ntiles, int B, const double *nref, int per_item,
+                                 const int32_t *item_map, int64_t out_stride, int64_t out_off, int crit, double tau,
+                                 double *fid, uint64_t *count, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  if (per_item <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_finalize, dim3(B), dim3(256), 0, s, partials, ntiles, nref, (const int32_t *)nullptr,
+                     per_item, item_map, out_stride, out_off, crit, tau, fid, count);
   return hipGetLastError();
 }
 

@@ -74,6 +74,18 @@ enum : int32_t {
   PF_NORM = 8,    // norm partials only (reference run)
 };
 
+// One circuit of a batched launch over many circuits that share a tile
+// shape: its plan, reference state and heavy-set median.
+template <typename T>
+struct MultiItem {
+  const DevOp<T> *ops;
+  const DevSeg *segs;
+  const DevPass *pass;
+  const cx<T> *ref;
+  int32_t seg_begin, seg_end, op_begin, pad;
+  double heavy_med;
+};
+
 template <typename T>
 struct PassArgs {
   const DevPass *pass;     // this pass's tile layout (device memory)
@@ -107,6 +119,19 @@ struct PassArgs {
   int32_t crit;            // CRIT_*
   uint32_t target;         // CRIT_TARGET: basis state
   double heavy_med;        // CRIT_HEAVY: median of the error-free probabilities
+  // Batched circuits (single-pass plans only): work-group b belongs to
+  // circuit slot b / per_item, whose ops / segs / pass / ref / seg range /
+  // median replace the fields above.  NULL: one circuit.
+  const MultiItem<T> *multi;
+  int32_t per_item;
+};
+
+// One circuit of a batched sampling launch.
+struct SampleItem {
+  uint64_t cid;
+  const int32_t *order;
+  const uint32_t *tag;
+  int32_t S, pad;
 };
 
 struct SampleArgs {
@@ -119,6 +144,11 @@ struct SampleArgs {
   const uint32_t *tag;     // event code without the Pauli bits, per position
   uint32_t *events;
   int32_t *ev_count;
+  // Batched circuits: trajectory slot b is trajectory t0 + b % per_item of
+  // circuit slot b / per_item, whose key, site count and tables replace
+  // cid / S / order / tag.  NULL: one circuit.
+  const SampleItem *multi;
+  int32_t per_item;
 };
 
 // Launch wrappers (kernels.hip).
@@ -129,6 +159,13 @@ hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, hipStream_t s)
 // end[b].
 hipError_t launch_finalize(const double *partials, int ntiles, int B, const double *nref, const int32_t *end,
                            int crit, double tau, double *fid, uint64_t *count, hipStream_t s);
+// Batched circuits: entry b is trajectory j = b % per_item of circuit slot
+// k = b / per_item, batch circuit item_map[k]: reference norm nref[k], value
+// to fid[item_map[k] * out_stride + out_off + j], success counted in
+// count[item_map[k]].
+hipError_t launch_finalize_multi(const double *partials, int ntiles, int B, const double *nref, int per_item,
+                                 const int32_t *item_map, int64_t out_stride, int64_t out_off, int crit, double tau,
+                                 double *fid, uint64_t *count, hipStream_t s);
 // Histogram (65536 bins) of bits [shift, shift+16) of the FP64 probability
 // |a_k|^2 of every amplitude whose bits above shift+16 equal `prefix`.
 template <typename T>

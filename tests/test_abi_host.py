@@ -85,6 +85,8 @@ def test_null_handles(P):
     assert L.nt_set_error_model(None, 0.1, 0, 0) == P.NT_ERR_INVALID_ARG
     assert L.nt_set_precision(None, 1) == P.NT_ERR_INVALID_ARG
     assert L.nt_run(None, None, 0, 0, 1, 0.9, None, None, None) == P.NT_ERR_INVALID_ARG
+    assert L.nt_run_batch(None, None, 1, 0, 0, 1, 0.9, None, None, None) == P.NT_ERR_INVALID_ARG
+    assert L.nt_set_criterion(None, 0, 0) == P.NT_ERR_INVALID_ARG
     assert L.nt_circuit_info(None, None, None, None) == P.NT_ERR_INVALID_ARG
     L.nt_destroy(None)
     L.nt_circuit_free(None)

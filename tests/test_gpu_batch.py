@@ -1,0 +1,152 @@
+"""GPU tests of the batched multi-circuit run (many independent instances of
+different sizes in shared launches).
+
+  * values are bit-identical to running each circuit alone (the batch only
+    changes which launch a trajectory runs in, never its arithmetic);
+  * against the CPU oracle, on the batched workload's first 32 instances
+    (n in 10..20, 336..2592 gates, circuit id = instance seed): every
+    instance with n <= 16 at trajectories [0, 8), and the n = 17, 18 ones at
+    [0, 2); fidelities within 1e-12 (c128) / 2e-5 (c64), equal success
+    counts outside the margin of the precision's fidelity error around tau.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TAU = 0.9
+P_ERR = 1e-3
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2301_07264_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    c = P.nt_create(0)
+    yield c
+    P.nt_destroy(c)
+
+
+def _load_batch(P, seeds):
+    circs = [W.config2(s) for s in seeds]
+    hs = []
+    for s, c in zip(seeds, circs):
+        h = P.nt_circuit_load(None, c)
+        P.nt_circuit_set_id(h, s)
+        hs.append(h)
+    return circs, hs
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_batch_equals_single_runs(P, ctx, prec):
+    pr = P.NT_C64 if prec == "c64" else P.NT_C128
+    seeds = list(range(24))
+    circs, hs = _load_batch(P, seeds)
+    hs_rep = hs + [hs[3], hs[11]]          # a handle may repeat
+    P.nt_set_precision(ctx, pr)
+    P.nt_set_error_model(ctx, 0.01 / 3, 0.01 / 3, 0.01 / 3)
+    N = 24
+    _say(f"batch vs single: {len(hs_rep)} circuits, prec={prec}")
+    vals = np.zeros((len(hs_rep), N))
+    cnt, pb = P.nt_run_batch(ctx, hs_rep, 5, 3, N, TAU, vals)
+    for i, h in enumerate(hs_rep):
+        f = np.zeros(N)
+        c1, p1 = P.nt_run(ctx, h, 5, 3, N, TAU, f)
+        np.testing.assert_array_equal(vals[i].view(np.uint64), f.view(np.uint64))
+        assert cnt[i] == c1 and pb[i] == p1
+    for h in hs:
+        P.nt_circuit_free(h)
+
+
+def test_batch_device_output_and_criteria(P, ctx):
+    import torch
+    seeds = [11, 14, 23, 27, 30, 6, 9]
+    circs, hs = _load_batch(P, seeds)
+    P.nt_set_precision(ctx, P.NT_C64)
+    P.nt_set_error_model(ctx, 0.02 / 3, 0.02 / 3, 0.02 / 3)
+    N = 40
+    for crit in (P.NT_CRIT_FIDELITY, P.NT_CRIT_HEAVY):
+        _say(f"batch device output: crit={crit}")
+        P.nt_set_criterion(ctx, crit, 0)
+        d = torch.zeros(len(hs), N, dtype=torch.float64, device="cuda:0")
+        cnt, pb = P.nt_run_batch(ctx, hs, 1, 0, N, 0.5, vals_out_ptr=d.data_ptr())
+        torch.cuda.synchronize()
+        got = d.cpu().numpy()
+        for i, h in enumerate(hs):
+            f = np.zeros(N)
+            c1, p1 = P.nt_run(ctx, h, 1, 0, N, 0.5, f)
+            np.testing.assert_array_equal(got[i].view(np.uint64), f.view(np.uint64))
+            assert cnt[i] == c1 and pb[i] == p1
+    P.nt_set_criterion(ctx, P.NT_CRIT_FIDELITY, 0)
+    for h in hs:
+        P.nt_circuit_free(h)
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle_subset(orc):
+    if not _ORACLE_CACHE:
+        for s in range(32):
+            c = W.config2(s)
+            if c.n <= 16:
+                nt = 8
+            elif c.n <= 18:
+                nt = 2
+            else:
+                continue
+            fid, _ = orc.run(c, P_ERR / 3, P_ERR / 3, P_ERR / 3, 0, 0, nt, TAU, cid=s)
+            _ORACLE_CACHE[s] = fid
+    return _ORACLE_CACHE
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_batch_vs_oracle_subset(P, ctx, orc, prec):
+    pr = P.NT_C64 if prec == "c64" else P.NT_C128
+    ftol = 2e-5 if prec == "c64" else 1e-12
+    _say(f"batch vs oracle: computing oracle subset (prec={prec})")
+    ref = _oracle_subset(orc)
+    seeds = sorted(ref)
+    circs, hs = _load_batch(P, seeds)
+    P.nt_set_precision(ctx, pr)
+    P.nt_set_error_model(ctx, P_ERR / 3, P_ERR / 3, P_ERR / 3)
+    N = 8
+    _say(f"batch vs oracle: {len(seeds)} circuits on the GPU")
+    vals = np.zeros((len(hs), N))
+    cnt, _ = P.nt_run_batch(ctx, hs, 0, 0, N, TAU, vals)
+    for i, s in enumerate(seeds):
+        fo = ref[s]
+        k = len(fo)
+        assert np.abs(vals[i, :k] - fo).max() <= ftol, (s, circs[i].n)
+        margin = np.abs(fo - TAU) < ftol
+        assert int(((vals[i, :k] >= TAU) != (fo >= TAU))[~margin].sum()) == 0
+        if k == N:
+            assert cnt[i] == int((vals[i] >= TAU).sum())
+    for h in hs:
+        P.nt_circuit_free(h)
+
+
+def test_batch_error_paths(P, ctx):
+    with pytest.raises(P.NtError) as e:
+        P.nt_run_batch(ctx, [], 0, 0, 4, TAU)
+    assert e.value.status == P.NT_ERR_INVALID_ARG
+    c = W.config2(0)
+    h = P.nt_circuit_load(None, c)
+    with pytest.raises(P.NtError) as e:
+        P.nt_run_batch(ctx, [h], 0, 0, 0, TAU)
+    assert e.value.status == P.NT_ERR_INVALID_ARG
+    P.nt_circuit_free(h)
