@@ -8,6 +8,9 @@ S = 3047 error sites), complex64 amplitudes with FP64 overlaps / norms /
 counts, uniform Pauli error rate cycling over the 13 rates 10^(-5 + j/4).
 --workload qaoa3reg30: the 30-qubit alternating-layer circuit on a random
 3-regular graph (G = 330, S = 510, 8 GiB complex64 state), rates 10^(-5+j/3).
+--workload batch512: 512 independent random-layer instances (n uniform in
+10..20, 10..100 layers, circuit id = instance seed), 256 trajectories each at
+p = 1e-3, all in one batched call per step.
 One step = one batch of B trajectories through the whole path: Philox
 error-site sampling, every gate pass, fused fidelity scoring and the success
 count.  Inputs (circuit plan and reference state) are resident in HBM before
@@ -39,7 +42,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["ghz_qft_layers24", "qaoa3reg30"], default="ghz_qft_layers24")
+    ap.add_argument("--workload", choices=["ghz_qft_layers24", "qaoa3reg30", "batch512"], default="ghz_qft_layers24")
     ap.add_argument("--batch", type=int, default=0, help="trajectories per step (0: 32 for 24 qubits, 4 for 30)")
     ap.add_argument("--prec", choices=["c64", "c128"], default="c64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -75,6 +78,8 @@ def main():
     import workloads as W
 
     P.lib()
+    if args.workload == "batch512":
+        return bench_batch(args, P, W)
     if args.workload == "ghz_qft_layers24":
         circ = W.config1()
         rates = W.rates_config1()
@@ -242,6 +247,92 @@ def main():
     }
     print(json.dumps(out), flush=True)
     P.nt_circuit_free(h)
+    P.nt_destroy(ctx)
+
+
+def bench_batch(args, P, W):
+    """Batched uneven instances: one nt_run_batch call over all 512 circuits
+    per step (inputs resident: plans and reference states built before the
+    timed region)."""
+    import numpy as np
+    import torch
+
+    n_circ, N, p, tau = 512, 256, 1e-3, 0.9
+    circs = [W.config2(s) for s in range(n_circ)]
+    prec = P.NT_C64 if args.prec == "c64" else P.NT_C128
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    ctx = P.nt_create(0, stream.cuda_stream)
+    P.nt_set_precision(ctx, prec)
+    hs = []
+    for s, c in enumerate(circs):
+        h = P.nt_circuit_load(ctx, c)
+        P.nt_circuit_set_id(h, s)
+        hs.append(h)
+    P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+    vals = torch.empty(n_circ, N, dtype=torch.float64, device="cuda:0")
+    P.nt_run_batch(ctx, hs, 0, 0, 1, tau)          # plans + reference states
+    for _ in range(args.warmup):
+        P.nt_run_batch(ctx, hs, 0, 0, N, tau, vals_out_ptr=vals.data_ptr())
+    torch.cuda.synchronize()
+    P.nt_timing_enable(ctx, True)
+    P.nt_timing_reset(ctx)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    succ = 0
+    e0.record(stream)
+    for k in range(args.steps):
+        cnt, _ = P.nt_run_batch(ctx, hs, 0, k * N, N, tau, vals_out_ptr=vals.data_ptr())
+        succ += int(cnt.sum())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    launches, pass_ms, pass_bytes, pass_updates, pass_flops = P.nt_timing_read(ctx)
+    P.nt_timing_enable(ctx, False)
+    updates = float(args.steps) * N * sum(c.G * (1 << c.n) for c in circs)
+    value = updates / (ms / 1e3)
+    achieved_tf = pass_flops / (pass_ms / 1e3) / 1e12
+    achieved_gbs = pass_bytes / (pass_ms / 1e3) / 1e9
+    alu_view = {"bound": "alu", "achieved": achieved_tf, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved_tf / ALU_PEAK_TFLOPS, "traffic": None}
+    hbm_view = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None}
+    roofline = dict(alu_view if alu_view["frac"] >= hbm_view["frac"] else hbm_view)
+    roofline.update({"kernel": "k_pass (all launch shapes, time-weighted)", "launches": launches,
+                     "avg_launch_ms": pass_ms / max(launches, 1),
+                     "pass_kernel_share_of_step": pass_ms / ms if ms > 0 else None,
+                     "hbm_view": hbm_view, "alu_view": alu_view})
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = [(s, c) for s, c in enumerate(circs) if c.n <= 15][:6]
+        t0 = time.perf_counter()
+        upd = 0
+        threads = 0
+        for s, c in sample:
+            _, _, threads = oracle.run(c, p / 3, p / 3, p / 3, 0, 0, 4, tau, cid=s, return_threads=True)
+            upd += 5 * c.G * (1 << c.n)
+        dt = time.perf_counter() - t0
+        cpu = {"value": upd / dt, "unit": "amplitude-updates/s", "cores": threads, "kind": "oracle",
+               "sample": f"instances {[s for s, _ in sample]} (n <= 15), error-free reference + 4 trajectories "
+                         f"each, FP64, one trajectory per thread, {dt:.1f} s wall"}
+    ns = [c.n for c in circs]
+    out = {
+        "metric": "trajectory amplitude-updates/s (% HBM peak); time-to-tolerable-error-rate ±0.01",
+        "value": value, "unit": "amplitude-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": "512 random-layer instances, n 10..20, 10..100 layers, 256 trajectories each, "
+                               "p=1e-3, one batched call per step",
+                   "circuits": n_circ, "trajectories_per_circuit": N, "n_min": min(ns), "n_max": max(ns),
+                   "gates_total": sum(c.G for c in circs), "amplitudes": args.prec,
+                   "parallelism": "single GPU, circuits x trajectories"},
+        "roofline": roofline, "cpu_baseline": cpu, "successes": succ,
+        "trajectories": args.steps * N * n_circ,
+    }
+    print(json.dumps(out), flush=True)
+    for h in hs:
+        P.nt_circuit_free(h)
     P.nt_destroy(ctx)
 
 

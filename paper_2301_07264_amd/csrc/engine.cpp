@@ -391,7 +391,9 @@ static void run_passes(Ctx &cx, const Circuit &c, DevPlan &dp, ntk::cx<T> *state
     a.events = r.events;
     a.ev_count = r.ev_count;
     a.partials = r.partials;
-    a.frame_out = (p == np - 1) ? r.frames : nullptr;
+    // frames double-buffered by pass parity
+    a.frame_out = r.frames ? r.frames + (size_t)(p & 1) * 4 * r.B : nullptr;
+    a.frame_in = (r.frames && p > 0) ? r.frames + (size_t)((p - 1) & 1) * 4 * r.B : nullptr;
     a.state_stride = dim;
     a.ev_stride = r.ev_stride;
     a.B = Bp;
@@ -488,7 +490,7 @@ void Ctx::simulate_batch(const Circuit &c, DevPlan &dp, uint64_t seed, uint64_t 
   events.ensure((size_t)B * S * 4);
   ev_count.ensure((size_t)B * 4);
   partials.ensure((size_t)B * ntiles * ntk::NPART * sizeof(double));
-  frames.ensure((size_t)B * 4 * sizeof(uint32_t));
+  frames.ensure((size_t)2 * B * 4 * sizeof(uint32_t));
   const bool need_states = P.passes.size() > 1 || mode == 1;
   if (need_states) states.ensure((size_t)B * dim * amp_bytes(dp.prec));
 
@@ -694,7 +696,7 @@ static void run_entries(Ctx &cx, const Circuit &c, DevPlan &dp, int B, int ev_st
   const size_t dim = (size_t)1 << c.n;
   const size_t ntiles = (size_t)1 << (c.n - P.L);
   cx.partials.ensure((size_t)B * ntiles * ntk::NPART * sizeof(double));
-  cx.frames.ensure((size_t)B * 4 * sizeof(uint32_t));
+  cx.frames.ensure((size_t)2 * B * 4 * sizeof(uint32_t));
   cx.fid.ensure((size_t)B * sizeof(double));
   cx.count.ensure(sizeof(uint64_t));
   cx.start.ensure((size_t)B * sizeof(int32_t));
@@ -944,6 +946,8 @@ void Ctx::final_state(const Circuit &c, uint64_t seed, uint64_t traj, void *out,
   ensure_reference(c, dp);
   const Thresholds th = make_thresholds(px, py, pz);
   simulate_batch(c, dp, seed, traj, 1, 1, 0.0, nullptr, nullptr, th);
+  // frames of a batch of one, double-buffered by pass parity
+  const uint32_t *last_frame = frames.as<uint32_t>() + (size_t)((dp.plan.passes.size() - 1) & 1) * 4;
   const size_t bytes = dim * amp_bytes(prec);
   const bool dev_out = is_device_pointer(out);
   void *dst = out;
@@ -953,10 +957,10 @@ void Ctx::final_state(const Circuit &c, uint64_t seed, uint64_t traj, void *out,
   }
   if (prec == NT_C64)
     check_hip(ntk::launch_unframe<float>(states.as<ntk::cx<float>>(), static_cast<ntk::cx<float> *>(dst), dim,
-                                         frames.as<uint32_t>(), stream), "k_unframe launch");
+                                         last_frame, stream), "k_unframe launch");
   else
     check_hip(ntk::launch_unframe<double>(states.as<ntk::cx<double>>(), static_cast<ntk::cx<double> *>(dst), dim,
-                                          frames.as<uint32_t>(), stream), "k_unframe launch");
+                                          last_frame, stream), "k_unframe launch");
   if (!dev_out) check_hip(hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, stream), "copy state");
   sync();
 }
@@ -1115,6 +1119,12 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
         sa.per_item = per;
         check_hip(ntk::launch_sample(sa, stream), "k_sample launch");
         const int nthreads = 1 << (L - R);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timing) {
+          e0 = take_event(ev_pool);
+          e1 = take_event(ev_pool);
+          check_hip(hipEventRecord(e0, stream), "hipEventRecord");
+        }
         if (c64) {
           ntk::PassArgs<float> a;
           std::memset(&a, 0, sizeof a);
@@ -1145,6 +1155,22 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
           a.multi = multi_items.as<ntk::MultiItem<double>>() + base;
           a.per_item = per;
           check_hip(ntk::launch_pass<double>(a, R, nthreads, stream), "k_pass launch");
+        }
+        if (timing) {
+          // a scoring pass over one tile reads the reference once per trajectory
+          check_hip(hipEventRecord(e1, stream), "hipEventRecord");
+          double by = 0, up = 0, fl = 0;
+          for (size_t k : g.second) {
+            const double dim = (double)((uint64_t)1 << cs[i0 + k]->n);
+            by += dim * (double)amp_bytes(prec);
+            up += dim * (double)dps[k]->plan.ops.size();
+            fl += dim * (dps[k]->pass_flops_per_amp[0] + 8.0);
+          }
+          ev_pending.emplace_back(e0, e1);
+          ev_bytes.push_back(by * per);
+          ev_updates.push_back(up * per);
+          ev_flops.push_back(fl * per);
+          if (ev_pending.size() >= 2048) timing_flush();
         }
         check_hip(ntk::launch_finalize_multi(partials.as<double>(), 1, items, multi_nref.as<double>() + base, per,
                                              item_map.as<int32_t>() + base, (int64_t)n, (int64_t)off, crit, tau,

@@ -177,77 +177,67 @@ DEV void frame_apply(uint32_t e, uint32_t &fx, uint32_t &fz, uint32_t &fc) {
 
 // general complex 2x2: 16 FMA per pair
 template <int B, int R, typename T>
-DEV void g1_apply(cx<T> (&v)[1 << R], cx<T> m00, cx<T> m01, cx<T> m10, cx<T> m11) {
+DEV void g1_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> m00, cx<T> m01, cx<T> m10, cx<T> m11) {
 #pragma unroll
   for (int r = 0; r < (1 << R); ++r) {
     if (r & (1 << B)) continue;
     const cx<T> x = v[r], y = v[r | (1 << B)];
-    v[r] = mac2(m00, x, m01, y);
-    v[r | (1 << B)] = mac2(m10, x, m11, y);
+    w[r] = mac2(m00, x, m01, y);
+    w[r | (1 << B)] = mac2(m10, x, m11, y);
   }
 }
 
 // real 2x2 (H, RY, X, and their frame conjugates): 8 FMA per pair
 template <int B, int R, typename T>
-DEV void g1r_apply(cx<T> (&v)[1 << R], T m00, T m01, T m10, T m11) {
+DEV void g1r_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], T m00, T m01, T m10, T m11) {
 #pragma unroll
   for (int r = 0; r < (1 << R); ++r) {
     if (r & (1 << B)) continue;
     const cx<T> x = v[r], y = v[r | (1 << B)];
-    v[r] = cx<T>{fmat(m01, y.x, m00 * x.x), fmat(m01, y.y, m00 * x.y)};
-    v[r | (1 << B)] = cx<T>{fmat(m11, y.x, m10 * x.x), fmat(m11, y.y, m10 * x.y)};
+    w[r] = cx<T>{fmat(m01, y.x, m00 * x.x), fmat(m01, y.y, m00 * x.y)};
+    w[r | (1 << B)] = cx<T>{fmat(m11, y.x, m10 * x.x), fmat(m11, y.y, m10 * x.y)};
   }
 }
 
 // [[c, i w], [i w, c]] with c, w real (RX(t): c = cos t/2, w = -sin t/2; a
 // Z in the frame flips w, an X leaves it): 8 FMA per pair
 template <int B, int R, typename T>
-DEV void g1x_apply(cx<T> (&v)[1 << R], T c, T w) {
+DEV void g1x_apply(const cx<T> (&v)[1 << R], cx<T> (&o)[1 << R], T c, T w) {
 #pragma unroll
   for (int r = 0; r < (1 << R); ++r) {
     if (r & (1 << B)) continue;
     const cx<T> x = v[r], y = v[r | (1 << B)];
-    v[r] = cx<T>{fmat(-w, y.y, c * x.x), fmat(w, y.x, c * x.y)};
-    v[r | (1 << B)] = cx<T>{fmat(-w, x.y, c * y.x), fmat(w, x.x, c * y.y)};
+    o[r] = cx<T>{fmat(-w, y.y, c * x.x), fmat(w, y.x, c * x.y)};
+    o[r | (1 << B)] = cx<T>{fmat(-w, x.y, c * y.x), fmat(w, x.x, c * y.y)};
   }
 }
 
-// Controlled +-X on register bit B (a CNOT conjugated by the frame: the
-// target's X part leaves X unchanged, its Z part flips the sign).
-template <typename T> struct SignBits;
-template <> struct SignBits<float> {
-  using U = uint32_t;
-  static DEV float flip(float v, U s) { return __uint_as_float(__float_as_uint(v) ^ s); }
-  static constexpr U sign = 0x80000000u;
-};
-template <> struct SignBits<double> {
-  using U = uint64_t;
-  static DEV double flip(double v, U s) {
-    return __longlong_as_double((long long)((uint64_t)__double_as_longlong(v) ^ s));
-  }
-  static constexpr U sign = 0x8000000000000000ull;
-};
-
-// take_lane: control condition for a control outside the registers (per
-// lane); cmask: register bit of the control (0 if none); creg: whether a set
-// register control bit satisfies the control value (uniform).
+// Controlled X on register bit B: a conditional swap of each register pair.
+// (The frame's Z on the target, which would turn X into -X, is moved into the
+// frame by the caller.)  take_lane: control condition for a control outside
+// the registers (per lane); cmask: register bit of the control (0 if none);
+// creg: whether a set register control bit satisfies the control value
+// (uniform).
 template <int B, int R, typename T>
-DEV void cx_apply(cx<T> (&v)[1 << R], bool neg, bool take_lane, uint32_t cmask, bool creg) {
-  using SB = SignBits<T>;
-  const typename SB::U sbit = neg ? SB::sign : 0;
+DEV void cx_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], bool take_lane, uint32_t cmask, bool creg) {
+  if (cmask) {
+    // control in the registers: the swap of each pair is uniform (a set
+    // control bit satisfies the control iff creg; a clear one iff !creg)
 #pragma unroll
-  for (int r = 0; r < (1 << R); ++r) {
-    if (r & (1 << B)) continue;
-    const cx<T> x = v[r], y = v[r | (1 << B)];
-    const bool take = ((uint32_t)r & cmask) ? creg : take_lane;
-    if (neg) {
-      const cx<T> ny{SB::flip(y.x, sbit), SB::flip(y.y, sbit)};
-      const cx<T> nx{SB::flip(x.x, sbit), SB::flip(x.y, sbit)};
-      v[r] = take ? ny : x;
-      v[r | (1 << B)] = take ? nx : y;
-    } else {
-      v[r] = take ? y : x;
-      v[r | (1 << B)] = take ? x : y;
+    for (int r = 0; r < (1 << R); ++r) {
+      if (r & (1 << B)) continue;
+      const cx<T> x = v[r], y = v[r | (1 << B)];
+      const bool take = (((uint32_t)r & cmask) != 0u) == creg;
+      w[r] = take ? y : x;
+      w[r | (1 << B)] = take ? x : y;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < (1 << R); ++r) {
+      if (r & (1 << B)) continue;
+      const cx<T> x = v[r], y = v[r | (1 << B)];
+      w[r] = take_lane ? y : x;
+      w[r | (1 << B)] = take_lane ? x : y;
     }
   }
 }
@@ -288,40 +278,49 @@ DEV cx<T> perm4(const OpLite<T> &h, int i, uint32_t xm) {
 // Diagonal on one qubit: a uniform phase per slot when the qubit is a
 // register qubit, one phase per lane otherwise.
 template <int R, typename T>
-DEV void d1_apply(cx<T> (&v)[1 << R], cx<T> d0, cx<T> d1, uint32_t lane, uint32_t am) {
+DEV void d1_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> d0, cx<T> d1, uint32_t lane, uint32_t am) {
   if (am) {
 #pragma unroll
-    for (int r = 0; r < (1 << R); ++r) v[r] = cmul(((uint32_t)r & am) ? d1 : d0, v[r]);
+    for (int r = 0; r < (1 << R); ++r) w[r] = cmul(((uint32_t)r & am) ? d1 : d0, v[r]);
   } else {
     const cx<T> d = lane ? d1 : d0;
 #pragma unroll
-    for (int r = 0; r < (1 << R); ++r) v[r] = cmul(d, v[r]);
+    for (int r = 0; r < (1 << R); ++r) w[r] = cmul(d, v[r]);
   }
 }
 
 // Diagonal on two qubits, entries d[b_a + 2 b_b].
 template <int R, typename T>
-DEV void d2_apply(cx<T> (&v)[1 << R], cx<T> d0, cx<T> d1, cx<T> d2, cx<T> d3, uint32_t la, uint32_t lb,
+DEV void d2_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> d0, cx<T> d1, cx<T> d2, cx<T> d3, uint32_t la, uint32_t lb,
                   uint32_t am, uint32_t bm) {
   if (!am && !bm) {
     const cx<T> d = lb ? (la ? d3 : d2) : (la ? d1 : d0);
 #pragma unroll
-    for (int r = 0; r < (1 << R); ++r) v[r] = cmul(d, v[r]);
+    for (int r = 0; r < (1 << R); ++r) w[r] = cmul(d, v[r]);
   } else if (am && bm) {
 #pragma unroll
     for (int r = 0; r < (1 << R); ++r) {
       const bool ba = ((uint32_t)r & am) != 0, bb = ((uint32_t)r & bm) != 0;
-      v[r] = cmul(bb ? (ba ? d3 : d2) : (ba ? d1 : d0), v[r]);
+      w[r] = cmul(bb ? (ba ? d3 : d2) : (ba ? d1 : d0), v[r]);
     }
   } else if (am) {
     const cx<T> p0 = lb ? d2 : d0, p1 = lb ? d3 : d1;   // by the register bit of qa
 #pragma unroll
-    for (int r = 0; r < (1 << R); ++r) v[r] = cmul(((uint32_t)r & am) ? p1 : p0, v[r]);
+    for (int r = 0; r < (1 << R); ++r) w[r] = cmul(((uint32_t)r & am) ? p1 : p0, v[r]);
   } else {
     const cx<T> p0 = la ? d1 : d0, p1 = la ? d3 : d2;   // by the register bit of qb
 #pragma unroll
-    for (int r = 0; r < (1 << R); ++r) v[r] = cmul(((uint32_t)r & bm) ? p1 : p0, v[r]);
+    for (int r = 0; r < (1 << R); ++r) w[r] = cmul(((uint32_t)r & bm) ? p1 : p0, v[r]);
   }
+}
+
+// A frame Z on the target of a CNOT (control value cv after the frame's X)
+// turns the conjugated op into C(-X) = (+-Z_c) CX; the +-Z_c is absorbed into
+// the frame instead of being applied: z_c ^= 1, and a factor -1 (i^2) when
+// cv = 0.  Exact, and keeps the register work a plain conditional swap.
+DEV void cx_frame(uint32_t za, uint32_t qc, uint32_t cv, uint32_t &fz, uint32_t &fc) {
+  fz = __builtin_amdgcn_readfirstlane(fz ^ (za << qc));
+  fc = __builtin_amdgcn_readfirstlane(fc + (za & (cv ^ 1u)) * 2u);
 }
 
 // Apply one register-segment op, conjugated by the current Pauli frame, to
@@ -330,7 +329,8 @@ DEV void d2_apply(cx<T> (&v)[1 << R], cx<T> d0, cx<T> d1, cx<T> d2, cx<T> d3, ui
 // mask(q) is the register bit holding q (0 if none).  Conjugation by X^x Z^z of a 2x2
 // M gives entries (i, j) = (-1)^{z(i+j)} M[i^x][j^x].
 template <int R, typename T>
-DEV void apply_reg_op(const OpLite<T> &op, cx<T> (&v)[1 << R], uint32_t gb, uint32_t fx, uint32_t fz) {
+DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], uint32_t gb,
+                      uint32_t fx, uint32_t &fz, uint32_t &fc) {
   const int code = op.code;
   const uint32_t qa = (uint32_t)op.qa;
   const uint32_t xa = (fx >> qa) & 1u, za = (fz >> qa) & 1u;
@@ -350,16 +350,19 @@ DEV void apply_reg_op(const OpLite<T> &op, cx<T> (&v)[1 << R], uint32_t gb, uint
   switch (code) {
 #define NT_G1(b)                                                                          \
   case OPK_G1 * 4 + b:                                                                    \
-    if constexpr (b < R) g1_apply<b, R>(v, c00, c01, c10, c11);                           \
+    if constexpr (b < R) g1_apply<b, R>(v, w, c00, c01, c10, c11);                        \
     break;                                                                                \
   case OPK_G1R * 4 + b:                                                                   \
-    if constexpr (b < R) g1r_apply<b, R>(v, c00.x, c01.x, c10.x, c11.x);                  \
+    if constexpr (b < R) g1r_apply<b, R>(v, w, c00.x, c01.x, c10.x, c11.x);               \
     break;                                                                                \
   case OPK_G1X * 4 + b:                                                                   \
-    if constexpr (b < R) g1x_apply<b, R>(v, m00.x, za ? -m01.y : m01.y);                  \
+    if constexpr (b < R) g1x_apply<b, R>(v, w, m00.x, za ? -m01.y : m01.y);               \
     break;                                                                                \
   case OPK_CX * 4 + b:                                                                    \
-    if constexpr (b < R) cx_apply<b, R>(v, za != 0u, ((gb >> qc) & 1u) == cv, bm, cv == 1u); \
+    if constexpr (b < R) {                                                                \
+      cx_apply<b, R>(v, w, ((gb >> qc) & 1u) == cv, bm, cv == 1u);                        \
+      cx_frame(za, qc, cv, fz, fc);                                                       \
+    }                                                                                     \
     break;
     NT_G1(0)
     NT_G1(1)
@@ -367,17 +370,19 @@ DEV void apply_reg_op(const OpLite<T> &op, cx<T> (&v)[1 << R], uint32_t gb, uint
     NT_G1(3)
 #undef NT_G1
     case OPK_D1 * 4: {
-      d1_apply<R>(v, xa ? m01 : m00, xa ? m00 : m01, (gb >> qa) & 1u, am);
+      d1_apply<R>(v, w, xa ? m01 : m00, xa ? m00 : m01, (gb >> qa) & 1u, am);
       break;
     }
     case OPK_D2 * 4: {
       const uint32_t qb = (uint32_t)op.qb;
       const uint32_t xm = xa | (((fx >> qb) & 1u) << 1);
-      d2_apply<R>(v, perm4(op, 0, xm), perm4(op, 1, xm), perm4(op, 2, xm), perm4(op, 3, xm), (gb >> qa) & 1u,
+      d2_apply<R>(v, w, perm4(op, 0, xm), perm4(op, 1, xm), perm4(op, 2, xm), perm4(op, 3, xm), (gb >> qa) & 1u,
                   (gb >> qb) & 1u, am, bm);
       break;
     }
     default:
+#pragma unroll
+      for (int r = 0; r < (1 << R); ++r) w[r] = v[r];
       break;
   }
 }
@@ -525,18 +530,26 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   }
   __syncthreads();
 
-  // Pauli frame at the start of this pass; next_op is the op index of the
-  // trajectory's next error event (~0 when there is none).
+  // Pauli frame at the start of this pass: carried from the previous pass,
+  // or (first pass of the trajectory) the identity with every earlier error
+  // applied.  next_op is the op index of the trajectory's next error event
+  // (~0 when there is none).
   const uint32_t *ev = a.events + (size_t)b * a.ev_stride;
   const int ne = __builtin_amdgcn_readfirstlane(a.ev_count[b]);
+  const bool carried = a.frame_in != nullptr && my_start < a.pass_index;
   int ep = 0;
   uint32_t fx = 0, fz = 0, fc = 0;
   uint32_t next_e = 0, next_op = 0xffffffffu;
   while (ep < ne) {
     next_e = __builtin_amdgcn_readfirstlane(ev[ep]);
     if ((int)(next_e >> 8) >= op_begin) break;
-    frame_apply(next_e, fx, fz, fc);
+    if (!carried) frame_apply(next_e, fx, fz, fc);
     ++ep;
+  }
+  if (carried) {
+    fx = __builtin_amdgcn_readfirstlane(a.frame_in[4 * b + 0]);
+    fz = __builtin_amdgcn_readfirstlane(a.frame_in[4 * b + 1]);
+    fc = __builtin_amdgcn_readfirstlane(a.frame_in[4 * b + 2]);
   }
   if (ep < ne) next_op = next_e >> 8;
   auto take_events = [&](int o) {
@@ -579,17 +592,29 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
         if ((r >> bb) & 1) u ^= sbit[bb];
       return *reinterpret_cast<cx<T> *>(smem_raw + (sjb ^ u));
     };
-    cx<T> v[NS];
+    // Two register banks, ops alternating between them (v -> w -> v), so no
+    // op has to copy its results back into the registers it read.
+    cx<T> v[NS], w[NS];
 #pragma unroll
     for (int r = 0; r < NS; ++r) v[r] = slot(r);
-    if (sg.op_begin < sg.op_end) {
-      OpLite<T> cur = load_lite(ops, sg.op_begin);
-      for (int o = sg.op_begin; o < sg.op_end; ++o) {
-        OpLite<T> nxt = cur;
-        if (o + 1 < sg.op_end) nxt = load_lite(ops, o + 1);   // next op's loads in flight
-        apply_reg_op<R, T>(cur, v, gb, fx, fz);
+    int o = sg.op_begin;
+    if (o < sg.op_end) {
+      OpLite<T> cur = load_lite(ops, o);
+      for (; o + 1 < sg.op_end; o += 2) {
+        OpLite<T> nxt = load_lite(ops, o + 1);   // next op's loads in flight
+        apply_reg_op<R, T>(cur, v, w, gb, fx, fz, fc);
         take_events(o);
         cur = nxt;
+        if (o + 2 < sg.op_end) nxt = load_lite(ops, o + 2);
+        apply_reg_op<R, T>(cur, w, v, gb, fx, fz, fc);
+        take_events(o + 1);
+        cur = nxt;
+      }
+      if (o < sg.op_end) {
+        apply_reg_op<R, T>(cur, v, w, gb, fx, fz, fc);
+        take_events(o);
+#pragma unroll
+        for (int r = 0; r < NS; ++r) v[r] = w[r];
       }
     }
 #pragma unroll

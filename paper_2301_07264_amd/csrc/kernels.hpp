@@ -96,7 +96,12 @@ struct PassArgs {
   const uint32_t *events;  // per trajectory, sorted by op: (op << 8) | (qubit << 2) | pauli
   const int32_t *ev_count;
   double *partials;        // [B][ntiles][NPART]
-  uint32_t *frame_out;     // [B][4]: final Pauli frame x-mask, z-mask, phase
+  // Pauli frame (x-mask, z-mask, phase) per trajectory, [B][4]: written at
+  // the end of the pass, read at the start of the next one.  The frame is
+  // not a function of the errors alone (a CNOT moves a frame Z from its
+  // target to its control), so it is carried from pass to pass.
+  uint32_t *frame_out;
+  const uint32_t *frame_in;
   uint64_t state_stride;
   int32_t ev_stride;
   int32_t B;
