@@ -36,6 +36,23 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # instructions (kept off on the test machines), and the same for FP64.
 ALU_PEAK_TFLOPS = 78.6
 
+# HBM bytes per gate-pass launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# (calibrated against a device copy), per workload, valid for the kernel
+# source they were taken on (profiles/hbm_traffic_*.md).
+MEASURED_TRAFFIC = {
+    ("ghz_qft_layers24", "c64", 32): {
+        "bytes_per_launch": 8.413e9,
+        "kernel_sha256": "7d8c5f61a92733fe528522641912181f1a867adc391d0dec644d232cfa7242a0",
+    },
+}
+
+
+def kernel_sha256():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2301_07264_amd", "csrc", "kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -149,6 +166,10 @@ def main():
     if args.traffic and os.path.exists(args.traffic):
         with open(args.traffic) as f:
             traffic = json.load(f).get("bytes_per_launch")
+    else:
+        m = MEASURED_TRAFFIC.get((args.workload, args.prec, B))
+        if m and m["kernel_sha256"] == kernel_sha256():
+            traffic = m["bytes_per_launch"]
 
     ttr = None
     if args.ttr:

@@ -1,0 +1,83 @@
+"""GPU parity at full size on the 30-qubit alternating-layer workload
+(3-regular graph, 4 rounds, G = 330, S = 510; 8 GiB complex64 states)
+against stored CPU-oracle values (tests/golden/config4_oracle.json, written
+by tests/golden/make_config4_golden.py, which calls only the oracle).
+
+Checked, in the launch configuration the benchmark uses (complex64, FP64
+reductions): the error-free state and the final states of the stored
+trajectories at 1024 fixed random indices, the fired error sites of those
+trajectories (bit-exact), and their fidelities.  A sample of 1024 of the 2^30
+amplitudes estimates the state's L2 error as ||d_sample|| * sqrt(2^30 / 1024);
+the bar is the complex64 state bar, 1e-5.
+
+The circuit commutes with the global bit flip and starts in its +1 sector, so
+a single Z or Y error sends the state to the orthogonal sector: those stored
+fidelities are 0 up to rounding (~1e-35).
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = os.path.join(HERE, "golden", "config4_oracle.json")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gold():
+    with open(GOLD) as f:
+        return json.load(f)
+
+
+def test_config4_full_size_vs_oracle(gold):
+    import paper_2301_07264_amd as P
+    P.lib()
+    c = W.config4()
+    assert (c.n, c.G, c.S) == (gold["n"], gold["G"], gold["S"])
+    idx = np.asarray(gold["indices"], np.int64)
+    scale = math.sqrt((1 << c.n) / len(idx))
+    ctx = P.nt_create(0)
+    h = P.nt_circuit_load(ctx, c)
+    try:
+        P.nt_set_precision(ctx, P.NT_C64)
+        _say("config4 golden: reference state (2^30 amplitudes, complex64)")
+        ref = P.nt_reference_state(ctx, h, P.NT_C64)
+        want = np.asarray(gold["reference"]["re"]) + 1j * np.asarray(gold["reference"]["im"])
+        got = ref[idx].astype(np.complex128)
+        d = np.linalg.norm(got - want) * scale
+        _say(f"  reference: estimated L2 {d:.3e}")
+        assert d <= 1e-5
+        del ref
+        for tr in gold["trajectories"]:
+            p, t = tr["p"], tr["t"]
+            _say(f"config4 golden: p={p} t={t} sites={tr['sites']}")
+            P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+            off, sites, paulis = P.nt_sample_sites(ctx, h, 0, t, 1)
+            k = int(off[1])
+            assert sites[:k].tolist() == tr["sites"]
+            assert paulis[:k].tolist() == tr["paulis"]
+            fid = np.zeros(1)
+            P.nt_run(ctx, h, 0, t, 1, 0.9, fid)
+            assert abs(fid[0] - tr["F"]) <= 2e-5
+            psi = P.nt_final_state(ctx, h, 0, t, P.NT_C64)
+            want = np.asarray(tr["re"]) + 1j * np.asarray(tr["im"])
+            got = psi[idx].astype(np.complex128)
+            del psi
+            d = np.linalg.norm(got - want) * scale
+            _say(f"  estimated L2 {d:.3e}, F {fid[0]:.3e} (oracle {tr['F']:.3e})")
+            assert d <= 1e-5
+    finally:
+        P.nt_circuit_free(h)
+        P.nt_destroy(ctx)
