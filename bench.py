@@ -331,11 +331,11 @@ def bench_batch(args, P, W):
         upd = 0
         threads = 0
         for s, c in sample:
-            _, _, threads = oracle.run(c, p / 3, p / 3, p / 3, 0, 0, 4, tau, cid=s, return_threads=True)
-            upd += 5 * c.G * (1 << c.n)
+            _, _, threads = oracle.run(c, p / 3, p / 3, p / 3, 0, 0, 96, tau, cid=s, return_threads=True)
+            upd += 97 * c.G * (1 << c.n)
         dt = time.perf_counter() - t0
         cpu = {"value": upd / dt, "unit": "amplitude-updates/s", "cores": threads, "kind": "oracle",
-               "sample": f"instances {[s for s, _ in sample]} (n <= 15), error-free reference + 4 trajectories "
+               "sample": f"instances {[s for s, _ in sample]} (n <= 15), error-free reference + 96 trajectories "
                          f"each, FP64, one trajectory per thread, {dt:.1f} s wall"}
     ns = [c.n for c in circs]
     out = {
