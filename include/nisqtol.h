@@ -188,7 +188,10 @@ nt_status nt_run(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_
  * different sizes): for each circuit i, trajectories [traj_begin,
  * traj_begin + n_traj) under the context's error model, precision and
  * criterion, with Philox key (seed, circuit id of circuits[i]).  Values are
- * bit-identical to nt_run on each circuit alone (short-cuts are not applied).
+ * bit-identical to nt_run on each circuit alone under the same settings
+ * (short-cuts included: zero-fired trajectories of the shared launches are
+ * not simulated under the fidelity criterion; larger circuits take the
+ * short-cut path of nt_run).
  * Circuits whose plan is a single pass over one tile share launches (one
  * work-group per trajectory, per-circuit plan tables); larger ones run back
  * to back without host synchronization.
@@ -265,6 +268,58 @@ nt_status nt_eq5(double P_target, const double P_e[3], double P_R, double units,
  * [0, n_traj).  *method: 0 = exhaustive + Eq. 4, 1 = Monte Carlo. */
 nt_status nt_success_probability(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t n_traj, double tau,
                                  double *P, int *method);
+
+/* ---- learned surrogate of the success curve ---------------------------------- */
+
+/* A graph neural network over a circuit's gate graph predicts the success
+ * probability (fidelity criterion) at the 13 rates 10^(-5 + j/4), j = 0..12,
+ * trained on Monte Carlo labels; the tolerable-rate search uses it to bracket
+ * the rate (the Monte Carlo search then runs inside the bracket, with the
+ * full bracket as fallback, so the surrogate never decides the result).
+ * Graph: one node per gate, an edge between consecutive gates on a qubit.
+ * Node features (32): one-hot kind (17), sin/cos of up to three angles (6),
+ * ASAP layer / depth, arity - 1, n / 16, 1, zero padding.  Globals: n / 16,
+ * G / 2048, S / 4096, 1.  Network: input layer 32 -> 64 (ReLU); 3 layers
+ * H' = ReLU(H Ws + mean_nbr(H) Wn + b); mean pool; [pool, globals] (68) ->
+ * 64 (ReLU) -> 13 (sigmoid); loss: mean squared error.  Dense products use
+ * bf16 MFMA with FP32 accumulation ("exact" = 0) or plain FP32 ("exact" = 1,
+ * for gradient checks).  Deterministic: fixed-order reductions, no
+ * floating-point atomics.  One model per context; the model uses the
+ * context's device and stream. */
+typedef struct nt_gnn nt_gnn;
+nt_status nt_gnn_create(nt_ctx *ctx, uint64_t seed, nt_gnn **out);
+void nt_gnn_destroy(nt_gnn *m);
+/* Host-only graph of a circuit.  Pass NULL buffers to query the sizes:
+ * *n_nodes = G, *n_edges = entries of col.  x: [n_nodes][32], row_ptr:
+ * [n_nodes + 1], col: neighbour indices, glob: [4]. */
+nt_status nt_gnn_graph(const nt_circuit *c, float *x, int32_t *row_ptr, int32_t *col, float *glob, int64_t *n_nodes,
+                       int64_t *n_edges);
+/* Flat parameter vector (FP32): W_in [32][64], b_in [64]; per layer
+ * Ws [64][64], Wn [64][64], b [64]; W_h1 [68][64], b_h1 [64]; W_h2 [64][13],
+ * b_h2 [13] (row-major, input index first).  out NULL: *len = size. */
+nt_status nt_gnn_params(nt_gnn *m, float *out, int64_t *len);
+nt_status nt_gnn_set_params(nt_gnn *m, const float *in, int64_t len);
+/* Training set: circuits and labels [n][13] (host; NULL for none). */
+nt_status nt_gnn_set_data(nt_gnn *m, const nt_circuit *const *circuits, int n, const float *labels);
+/* Loss and gradient (host, length of the parameter vector) over training
+ * graphs [g0, g1). */
+nt_status nt_gnn_loss_grad(nt_gnn *m, int g0, int g1, int exact, double *loss, float *grad);
+/* Adam (beta 0.9 / 0.999, eps 1e-8) over mini-batches of batch_graphs
+ * consecutive graphs, batch order shuffled per epoch (seeded);
+ * loss_out[epochs] (host, may be NULL): mean training loss per epoch. */
+nt_status nt_gnn_train(nt_gnn *m, int epochs, int batch_graphs, double lr, uint64_t seed, double *loss_out);
+/* Predicted success probabilities, out [n][13] (host). */
+nt_status nt_gnn_predict(nt_gnn *m, const nt_circuit *const *circuits, int n, int exact, float *out);
+
+/* Tolerable rate with the surrogate's bracket: from the predicted curve, the
+ * grid interval where it crosses P_target widened by one grid step on each
+ * side (the whole grid [1e-5, 1e-2] when it does not cross); then
+ * nt_tolerable_rate inside it, and over [1e-5, 1e-2] if that bracket turns
+ * out not to hold the target.  bracket_out (may be NULL): the bracket the
+ * search ended in.  *n_probes counts every Monte Carlo evaluation. */
+nt_status nt_tolerable_rate_guided(nt_ctx *ctx, const nt_circuit *c, nt_gnn *m, double P_target, double tol,
+                                   uint64_t seed, uint64_t n_traj, double tau, double *p_star, int *n_probes,
+                                   double bracket_out[2]);
 
 /* ---- parity and debug exports ---------------------------------------------- */
 

@@ -47,7 +47,11 @@ EXPORTED = [
     "nt_timing_reset", "nt_timing_read", "nt_last_error", "nt_version",
     "nt_set_shortcuts", "nt_exhaustive", "nt_eq4", "nt_eq5", "nt_success_probability",
     "nt_set_criterion", "nt_run_batch",
+    "nt_gnn_create", "nt_gnn_destroy", "nt_gnn_graph", "nt_gnn_params", "nt_gnn_set_params",
+    "nt_gnn_set_data", "nt_gnn_loss_grad", "nt_gnn_train", "nt_gnn_predict", "nt_tolerable_rate_guided",
 ]
+
+GNN_RATES = [10.0 ** (-5.0 + j / 4.0) for j in range(13)]
 
 NT_CRIT_FIDELITY = 0
 NT_CRIT_TARGET_PROB = 1
@@ -114,6 +118,16 @@ def lib() -> C.CDLL:
         "nt_set_shortcuts": ([P, i32], i32),
         "nt_set_criterion": ([P, i32, u64], i32),
         "nt_run_batch": ([P, P, i32, u64, u64, u64, dbl, P, P, P], i32),
+        "nt_gnn_create": ([P, u64, PP], i32),
+        "nt_gnn_destroy": ([P], None),
+        "nt_gnn_graph": ([P, P, P, P, P, P, P], i32),
+        "nt_gnn_params": ([P, P, P], i32),
+        "nt_gnn_set_params": ([P, P, i64], i32),
+        "nt_gnn_set_data": ([P, P, i32, P], i32),
+        "nt_gnn_loss_grad": ([P, i32, i32, i32, P, P], i32),
+        "nt_gnn_train": ([P, i32, i32, dbl, u64, P], i32),
+        "nt_gnn_predict": ([P, P, i32, i32, P], i32),
+        "nt_tolerable_rate_guided": ([P, P, P, dbl, dbl, u64, u64, dbl, P, P, P], i32),
         "nt_exhaustive": ([P, P, dbl, P, P, P], i32),
         "nt_eq4": ([P, dbl, P, P], i32),
         "nt_eq5": ([dbl, P, dbl, dbl, P], i32),
@@ -392,3 +406,83 @@ def nt_timing_read(ctx):
     ms, by, up, fl = C.c_double(), C.c_double(), C.c_double(), C.c_double()
     _check(lib().nt_timing_read(ctx, C.byref(n), C.byref(ms), C.byref(by), C.byref(up), C.byref(fl)))
     return n.value, ms.value, by.value, up.value, fl.value
+
+
+# ---- learned surrogate ------------------------------------------------------------
+
+def _handles(circs):
+    return (C.c_void_p * len(circs))(*[C.c_void_p(h.value if isinstance(h, C.c_void_p) else h) for h in circs])
+
+
+def nt_gnn_create(ctx, seed: int = 0) -> C.c_void_p:
+    m = C.c_void_p()
+    _check(lib().nt_gnn_create(ctx, seed, C.byref(m)))
+    return m
+
+
+def nt_gnn_destroy(m) -> None:
+    lib().nt_gnn_destroy(m)
+
+
+def nt_gnn_graph(circ):
+    """Host graph of a circuit: (x[G, 32], row_ptr[G+1], col[E], glob[4])."""
+    nn = C.c_int64()
+    ne = C.c_int64()
+    _check(lib().nt_gnn_graph(circ, None, None, None, None, C.byref(nn), C.byref(ne)))
+    x = np.zeros((nn.value, 32), np.float32)
+    rp = np.zeros(nn.value + 1, np.int32)
+    col = np.zeros(max(ne.value, 1), np.int32)
+    glob = np.zeros(4, np.float32)
+    _check(lib().nt_gnn_graph(circ, _ptr(x), _ptr(rp), _ptr(col), _ptr(glob), C.byref(nn), C.byref(ne)))
+    return x, rp, col[:ne.value], glob
+
+
+def nt_gnn_params(m) -> np.ndarray:
+    n = C.c_int64()
+    _check(lib().nt_gnn_params(m, None, C.byref(n)))
+    out = np.zeros(n.value, np.float32)
+    _check(lib().nt_gnn_params(m, _ptr(out), C.byref(n)))
+    return out
+
+
+def nt_gnn_set_params(m, params) -> None:
+    p = np.ascontiguousarray(params, np.float32)
+    _check(lib().nt_gnn_set_params(m, _ptr(p), p.size))
+
+
+def nt_gnn_set_data(m, circs, labels=None) -> None:
+    lab = None if labels is None else np.ascontiguousarray(labels, np.float32)
+    if lab is not None:
+        assert lab.shape == (len(circs), 13)
+    _check(lib().nt_gnn_set_data(m, _handles(circs), len(circs), _ptr(lab)))
+
+
+def nt_gnn_loss_grad(m, g0: int, g1: int, exact: bool):
+    loss = C.c_double()
+    n = C.c_int64()
+    _check(lib().nt_gnn_params(m, None, C.byref(n)))
+    grad = np.zeros(n.value, np.float32)
+    _check(lib().nt_gnn_loss_grad(m, g0, g1, int(exact), C.byref(loss), _ptr(grad)))
+    return loss.value, grad
+
+
+def nt_gnn_train(m, epochs: int, batch_graphs: int, lr: float, seed: int = 0) -> np.ndarray:
+    out = np.zeros(max(epochs, 1), np.float64)
+    _check(lib().nt_gnn_train(m, epochs, batch_graphs, lr, seed, _ptr(out)))
+    return out[:epochs]
+
+
+def nt_gnn_predict(m, circs, exact: bool = False) -> np.ndarray:
+    out = np.zeros((len(circs), 13), np.float32)
+    _check(lib().nt_gnn_predict(m, _handles(circs), len(circs), int(exact), _ptr(out)))
+    return out
+
+
+def nt_tolerable_rate_guided(ctx, circ, m, P_target: float, tol: float, seed: int, n_traj: int, tau: float):
+    """Returns (p_star, n_probes, (p_lo, p_hi))."""
+    p = C.c_double()
+    k = C.c_int()
+    br = np.zeros(2, np.float64)
+    _check(lib().nt_tolerable_rate_guided(ctx, circ, m, P_target, tol, seed, n_traj, tau, C.byref(p), C.byref(k),
+                                          _ptr(br)))
+    return p.value, k.value, (float(br[0]), float(br[1]))

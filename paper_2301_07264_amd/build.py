@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnisqtol.so")
 
-SOURCES = ["kernels.hip", "circuit.cpp", "plan.cpp", "engine.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "gnn.hip", "circuit.cpp", "plan.cpp", "engine.cpp", "gnn_model.cpp", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

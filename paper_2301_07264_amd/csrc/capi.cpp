@@ -1,18 +1,24 @@
 // C ABI of libnisqtol (declared in include/nisqtol.h).  Every entry point
 // validates its arguments, converts internal errors into nt_status codes and
 // records a thread-local message; no exception crosses the boundary.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
 
 #include "engine.hpp"
+#include "gnn_model.hpp"
 
 struct nt_ctx {
   nt::Ctx *impl;
 };
 struct nt_circuit {
   nt::Circuit *impl;
+};
+struct nt_gnn {
+  nt_ctx *ctx;
+  gnn::Model *impl;
 };
 
 namespace {
@@ -42,6 +48,8 @@ nt_status guard(F &&f) {
 }
 
 bool valid_prob(double p) { return std::isfinite(p) && p >= 0.0 && p <= 1.0; }
+
+void check_hip_entry(nt_ctx *ctx) { nt::check_hip(hipSetDevice(ctx->impl->device), "hipSetDevice"); }
 
 }  // namespace
 
@@ -435,6 +443,160 @@ nt_status nt_timing_read(nt_ctx *ctx, int64_t *n_launches, double *ms_total, dou
     if (updates_total) *updates_total = cx.t_updates;
     if (flops_total) *flops_total = cx.t_flops;
   });
+}
+
+
+nt_status nt_gnn_create(nt_ctx *ctx, uint64_t seed, nt_gnn **out) {
+  if (!ctx || !out) return fail(NT_ERR_INVALID_ARG, "ctx / out is NULL");
+  *out = nullptr;
+  return guard([&] {
+    check_hip_entry(ctx);
+    auto *m = new nt_gnn{ctx, new gnn::Model(ctx->impl, seed)};
+    *out = m;
+  });
+}
+
+void nt_gnn_destroy(nt_gnn *m) {
+  if (!m) return;
+  (void)hipSetDevice(m->ctx->impl->device);
+  delete m->impl;
+  delete m;
+}
+
+nt_status nt_gnn_graph(const nt_circuit *c, float *x, int32_t *row_ptr, int32_t *col, float *glob, int64_t *n_nodes,
+                       int64_t *n_edges) {
+  if (!c || !n_nodes || !n_edges) return fail(NT_ERR_INVALID_ARG, "NULL argument");
+  return guard([&] {
+    const gnn::Graph g = gnn::build_graph(*c->impl);
+    *n_nodes = g.n_nodes;
+    *n_edges = (int64_t)g.col.size();
+    if (x) std::memcpy(x, g.x.data(), g.x.size() * sizeof(float));
+    if (row_ptr) std::memcpy(row_ptr, g.row_ptr.data(), g.row_ptr.size() * sizeof(int32_t));
+    if (col && !g.col.empty()) std::memcpy(col, g.col.data(), g.col.size() * sizeof(int32_t));
+    if (glob) std::memcpy(glob, g.glob, sizeof g.glob);
+  });
+}
+
+nt_status nt_gnn_params(nt_gnn *m, float *out, int64_t *len) {
+  if (!m || !len) return fail(NT_ERR_INVALID_ARG, "NULL argument");
+  return guard([&] {
+    *len = (int64_t)m->impl->lay.total;
+    if (out) {
+      check_hip_entry(m->ctx);
+      nt::check_hip(hipMemcpy(out, m->impl->params.p, m->impl->lay.total * 4, hipMemcpyDeviceToHost), "copy params");
+    }
+  });
+}
+
+nt_status nt_gnn_set_params(nt_gnn *m, const float *in, int64_t len) {
+  if (!m || !in) return fail(NT_ERR_INVALID_ARG, "NULL argument");
+  if (len != (int64_t)m->impl->lay.total) return fail(NT_ERR_INVALID_ARG, "parameter vector has the wrong length");
+  return guard([&] {
+    check_hip_entry(m->ctx);
+    nt::check_hip(hipMemcpy(m->impl->params.p, in, (size_t)len * 4, hipMemcpyHostToDevice), "copy params");
+  });
+}
+
+static std::vector<gnn::Graph> graphs_of(const nt_circuit *const *cs, int n) {
+  std::vector<gnn::Graph> gs;
+  gs.reserve(n);
+  for (int i = 0; i < n; ++i) {
+    if (!cs[i]) throw nt::Error(NT_ERR_INVALID_ARG, "circuit is NULL");
+    gs.push_back(gnn::build_graph(*cs[i]->impl));
+    if (gs.back().n_nodes == 0) throw nt::Error(NT_ERR_INVALID_ARG, "circuit without gates");
+  }
+  return gs;
+}
+
+nt_status nt_gnn_set_data(nt_gnn *m, const nt_circuit *const *circuits, int n, const float *labels) {
+  if (!m || !circuits || n <= 0) return fail(NT_ERR_INVALID_ARG, "need n > 0 circuits");
+  return guard([&] {
+    check_hip_entry(m->ctx);
+    const std::vector<gnn::Graph> gs = graphs_of(circuits, n);
+    m->impl->data.upload(gs, labels, m->ctx->impl->stream);
+  });
+}
+
+nt_status nt_gnn_loss_grad(nt_gnn *m, int g0, int g1, int exact, double *loss, float *grad) {
+  if (!m) return fail(NT_ERR_INVALID_ARG, "model is NULL");
+  if (g0 < 0 || g1 <= g0 || g1 > m->impl->data.n_graphs) return fail(NT_ERR_INVALID_ARG, "bad graph range");
+  return guard([&] {
+    check_hip_entry(m->ctx);
+    const double l = m->impl->loss_backward(m->impl->data, g0, g1, exact == 0);
+    if (loss) *loss = l;
+    if (grad)
+      nt::check_hip(hipMemcpy(grad, m->impl->grads.p, m->impl->lay.total * 4, hipMemcpyDeviceToHost), "copy grads");
+  });
+}
+
+nt_status nt_gnn_train(nt_gnn *m, int epochs, int batch_graphs, double lr, uint64_t seed, double *loss_out) {
+  if (!m) return fail(NT_ERR_INVALID_ARG, "model is NULL");
+  if (epochs < 0 || batch_graphs <= 0 || !(lr > 0)) return fail(NT_ERR_INVALID_ARG, "bad training settings");
+  if (m->impl->data.n_graphs == 0 || !m->impl->data.has_labels) return fail(NT_ERR_INVALID_ARG, "no labelled data");
+  return guard([&] {
+    check_hip_entry(m->ctx);
+    for (int e = 0; e < epochs; ++e) {
+      const double l = m->impl->train_epoch(batch_graphs, lr, seed + (uint64_t)e * 0x9E3779B97F4A7C15ull);
+      if (loss_out) loss_out[e] = l;
+    }
+  });
+}
+
+nt_status nt_gnn_predict(nt_gnn *m, const nt_circuit *const *circuits, int n, int exact, float *out) {
+  if (!m || !circuits || n <= 0 || !out) return fail(NT_ERR_INVALID_ARG, "NULL argument or n <= 0");
+  return guard([&] {
+    check_hip_entry(m->ctx);
+    gnn::Dataset ds;
+    ds.upload(graphs_of(circuits, n), nullptr, m->ctx->impl->stream);
+    const int chunk = 256;
+    for (int g0 = 0; g0 < n; g0 += chunk) {
+      const int g1 = std::min(n, g0 + chunk);
+      m->impl->forward(ds, g0, g1, exact == 0);
+      nt::check_hip(hipMemcpyAsync(out + (size_t)g0 * gnn::OUT, m->impl->v.p, (size_t)(g1 - g0) * gnn::OUT * 4,
+                                   hipMemcpyDeviceToHost, m->ctx->impl->stream), "copy predictions");
+      nt::check_hip(hipStreamSynchronize(m->ctx->impl->stream), "hipStreamSynchronize");
+    }
+  });
+}
+
+nt_status nt_tolerable_rate_guided(nt_ctx *ctx, const nt_circuit *c, nt_gnn *m, double P_target, double tol,
+                                   uint64_t seed, uint64_t n_traj, double tau, double *p_star, int *n_probes,
+                                   double bracket_out[2]) {
+  nt_status s = check_run_args(ctx, c, tau);
+  if (s) return s;
+  if (!m || !p_star) return fail(NT_ERR_INVALID_ARG, "model / p_star is NULL");
+  float pred[gnn::OUT];
+  s = nt_gnn_predict(m, &c, 1, 0, pred);
+  if (s) return s;
+  const double grid_lo = gnn::output_rate(0), grid_hi = gnn::output_rate(gnn::OUT - 1);
+  // first grid interval [j, j + 1] where the predicted curve falls through P_target
+  int j = -1;
+  for (int k = 0; k + 1 < gnn::OUT; ++k)
+    if (pred[k] >= P_target && pred[k + 1] < P_target) {
+      j = k;
+      break;
+    }
+  double lo = grid_lo, hi = grid_hi;
+  if (j >= 0) {
+    lo = gnn::output_rate(std::max(0, j - 1));
+    hi = gnn::output_rate(std::min(gnn::OUT - 1, j + 2));
+  }
+  int probes = 0, pr = 0;
+  s = nt_tolerable_rate(ctx, c, P_target, tol, lo, hi, seed, n_traj, tau, p_star, &pr);
+  probes += pr;
+  if (s == NT_ERR_NOT_BRACKETED && (lo > grid_lo || hi < grid_hi)) {
+    lo = grid_lo;
+    hi = grid_hi;
+    pr = 0;
+    s = nt_tolerable_rate(ctx, c, P_target, tol, lo, hi, seed, n_traj, tau, p_star, &pr);
+    probes += pr;
+  }
+  if (n_probes) *n_probes = probes;
+  if (bracket_out) {
+    bracket_out[0] = lo;
+    bracket_out[1] = hi;
+  }
+  return s;
 }
 
 }  // extern "C"

@@ -27,7 +27,7 @@ int kind_from_name(const std::string &s) {
   return -1;
 }
 
-static int num_params(int kind) {
+int kind_nparam(int kind) {
   switch (kind) {
     case NT_RX: case NT_RY: case NT_RZ: case NT_CP: case NT_RZZ: return 1;
     case NT_U: return 3;
@@ -118,7 +118,7 @@ static void validate_and_fill(Circuit *c, int n, const nt_gate *gates, int64_t G
       throw Error(NT_ERR_INVALID_ARG, "gate " + std::to_string(g) + ": duplicate qubits");
     if ((in.kind == NT_U1Q || in.kind == NT_U2Q) && !in.matrix)
       throw Error(NT_ERR_INVALID_ARG, "gate " + std::to_string(g) + ": matrix required");
-    for (int j = 0; j < num_params(in.kind); ++j)
+    for (int j = 0; j < kind_nparam(in.kind); ++j)
       if (!std::isfinite(in.param[j]))
         throw Error(NT_ERR_INVALID_ARG, "gate " + std::to_string(g) + ": non-finite angle");
     hg.kind = in.kind;
@@ -198,7 +198,7 @@ Circuit *load_circuit_text(const char *path) {
       if (rest.size() != want) throw Error(NT_ERR_INVALID_ARG, "line " + std::to_string(lineno) + ": bad matrix size");
       mats.push_back(rest);
     } else {
-      if ((int)rest.size() != num_params(kind))
+      if ((int)rest.size() != kind_nparam(kind))
         throw Error(NT_ERR_INVALID_ARG, "line " + std::to_string(lineno) + ": wrong number of angles");
       for (size_t j = 0; j < rest.size(); ++j) g.param[j] = rest[j];
       mats.emplace_back();

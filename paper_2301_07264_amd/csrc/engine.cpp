@@ -999,6 +999,10 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
   check_hip(hipMemsetAsync(bcounts.p, 0, nc * sizeof(uint64_t), stream), "hipMemsetAsync");
   double *vals_dev = dev_out ? vals_out : bvals.as<double>();
   const bool c64 = prec == NT_C64;
+  // zero-fired trajectories of one-tile circuits are not simulated (fidelity
+  // criterion: F = 1 exactly either way)
+  const int skip0 = ((shortcuts & SC_ZERO_FIRED) && crit == NT_CRIT_FIDELITY) ? ntk::PF_SKIP0 : 0;
+  std::vector<uint64_t> host_counts(nc, 0);
 
   size_t i0 = 0;
   while (i0 < nc) {
@@ -1055,6 +1059,7 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
         a.seg_end = b.seg_end = ps.seg_end;
         a.op_begin = b.op_begin = ps.op_begin;
         a.heavy_med = b.heavy_med = dp.heavy_med;
+        a.nref = b.nref = dp.nref_host;
         mf.push_back(a);
         md.push_back(b);
         ntk::SampleItem s;
@@ -1134,7 +1139,7 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
           a.ev_stride = (int)smax;
           a.B = items;
           a.L = L;
-          a.flags = ntk::PF_SCORE;
+          a.flags = ntk::PF_SCORE | skip0;
           a.crit = crit;
           a.target = (uint32_t)target;
           a.multi = multi_items.as<ntk::MultiItem<float>>() + base;
@@ -1149,7 +1154,7 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
           a.ev_stride = (int)smax;
           a.B = items;
           a.L = L;
-          a.flags = ntk::PF_SCORE;
+          a.flags = ntk::PF_SCORE | skip0;
           a.crit = crit;
           a.target = (uint32_t)target;
           a.multi = multi_items.as<ntk::MultiItem<double>>() + base;
@@ -1181,6 +1186,13 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
     for (size_t k : big) {
       const Circuit &c = *cs[i0 + k];
       DevPlan &dp = *dps[k];
+      if (shortcuts) {
+        // the short-cut path of a single run (synchronizes per chunk)
+        uint64_t cnt = 0;
+        run_shortcut(c, seed, t0, n, tau, vals_dev + (i0 + k) * n, &cnt, nullptr);
+        host_counts[i0 + k] = cnt;
+        continue;
+      }
       const uint64_t bs = batch_size(c, dp, n);
       for (uint64_t off = 0; off < n; off += bs) {
         const int B = (int)std::min<uint64_t>(bs, n - off);
@@ -1204,6 +1216,7 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
   std::vector<uint64_t> hc(nc);
   check_hip(hipMemcpyAsync(hc.data(), bcounts.p, nc * sizeof(uint64_t), hipMemcpyDeviceToHost, stream), "copy counts");
   sync();
+  for (size_t i = 0; i < nc; ++i) hc[i] += host_counts[i];
   if (counts_out) std::memcpy(counts_out, hc.data(), nc * sizeof(uint64_t));
   if (sums_out)
     for (size_t i = 0; i < nc; ++i) {

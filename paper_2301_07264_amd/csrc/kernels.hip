@@ -475,6 +475,17 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   double heavy_med = a.heavy_med;
   if (a.multi) {
     const MultiItem<T> &m = a.multi[b / a.per_item];
+    if ((a.flags & PF_SKIP0) && a.ev_count[b] == 0) {
+      // F = <R|R>^2 / (<R|R> <R|R>) = 1 exactly, as for the simulated state
+      if (threadIdx.x == 0) {
+        double *pt = a.partials + (size_t)b * NPART;
+        pt[0] = m.nref;
+        pt[1] = 0.0;
+        pt[2] = m.nref;
+        pt[3] = 0.0;
+      }
+      return;
+    }
     ops = m.ops;
     segs = m.segs;
     passp = m.pass;

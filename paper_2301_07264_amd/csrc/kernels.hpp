@@ -72,6 +72,8 @@ enum : int32_t {
   PF_SCORE = 2,   // overlap with the reference + norm (FP64 partials); no store
   PF_STORE = 4,   // write the tile back (always unless PF_SCORE)
   PF_NORM = 8,    // norm partials only (reference run)
+  PF_SKIP0 = 16,  // batched fidelity scoring: a trajectory without errors is
+                  // the reference itself; its partials are (<R|R>, 0, <R|R>, 0)
 };
 
 // One circuit of a batched launch over many circuits that share a tile
@@ -84,6 +86,7 @@ struct MultiItem {
   const cx<T> *ref;
   int32_t seg_begin, seg_end, op_begin, pad;
   double heavy_med;
+  double nref;             // <R|R>
 };
 
 template <typename T>

@@ -92,6 +92,7 @@ struct Circuit {
 // circuit.cpp
 void gate_matrix(int kind, const double *param, const double *umat, cd *m);
 int kind_arity(int kind);
+int kind_nparam(int kind);   // number of angles the kind takes
 const char *kind_name(int kind);
 int kind_from_name(const std::string &s);
 Circuit *load_circuit(int n, const nt_gate *gates, int64_t G);

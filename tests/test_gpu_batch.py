@@ -150,3 +150,27 @@ def test_batch_error_paths(P, ctx):
         P.nt_run_batch(ctx, [h], 0, 0, 0, TAU)
     assert e.value.status == P.NT_ERR_INVALID_ARG
     P.nt_circuit_free(h)
+
+
+@pytest.mark.parametrize("flags", [1, 3])
+def test_batch_with_shortcuts(P, ctx, flags):
+    """Zero-fired trajectories are skipped in the shared launches, larger
+    circuits take the short-cut path; values stay bit-identical to the plain
+    batched run."""
+    seeds = [0, 6, 11, 14, 21, 23, 27, 30]
+    circs, hs = _load_batch(P, seeds)
+    P.nt_set_precision(ctx, P.NT_C64)
+    P.nt_set_error_model(ctx, 1e-3 / 3, 1e-3 / 3, 1e-3 / 3)
+    N = 64
+    _say(f"batch with short-cuts {flags}")
+    base = np.zeros((len(hs), N))
+    P.nt_set_shortcuts(ctx, 0)
+    c0, p0 = P.nt_run_batch(ctx, hs, 2, 0, N, TAU, base)
+    P.nt_set_shortcuts(ctx, flags)
+    vals = np.zeros((len(hs), N))
+    c1, p1 = P.nt_run_batch(ctx, hs, 2, 0, N, TAU, vals)
+    P.nt_set_shortcuts(ctx, 0)
+    np.testing.assert_array_equal(vals.view(np.uint64), base.view(np.uint64))
+    np.testing.assert_array_equal(c1, c0)
+    for h in hs:
+        P.nt_circuit_free(h)
