@@ -651,6 +651,11 @@ bool Ctx::ensure_checkpoints(const Circuit &c, DevPlan &dp) {
   ensure_reference(c, dp);
   const int np = (int)dp.plan.passes.size();
   if (np <= 1) {
+    // no checkpoints; the per-pass reference norm of the single pass is <R|R>
+    dp.nref_pass.ensure(sizeof(double));
+    check_hip(hipMemcpyAsync(dp.nref_pass.p, dp.nref.p, sizeof(double), hipMemcpyDeviceToDevice, stream),
+              "copy norm");
+    sync();
     dp.ckpt_ready = true;
     return true;
   }
@@ -756,7 +761,8 @@ void Ctx::run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n,
   const bool have_ckpt = (shortcuts & (SC_CHECKPOINT | SC_LAST_ERROR)) && ensure_checkpoints(c, dp);
   // The measurement-probability criteria are not invariant under the
   // error-free suffix of the circuit: no early scoring for them.
-  const bool early_end = have_ckpt && (shortcuts & SC_LAST_ERROR) && crit == NT_CRIT_FIDELITY;
+  const bool early_end = have_ckpt && (shortcuts & SC_LAST_ERROR) && crit == NT_CRIT_FIDELITY &&
+                         dp.plan.passes.size() > 1;
   const double v_ref = (shortcuts & SC_ZERO_FIRED) ? reference_value(c, dp, tau) : 0.0;
   const Thresholds th = make_thresholds(px, py, pz);
   const int S = (int)std::max<int64_t>(c.S, 1);

@@ -416,3 +416,33 @@ def test_last_error_shortcut(P, ctx, prec):
         margin = np.abs(base - TAU) < ftol
         assert int(((f >= TAU) != (base >= TAU))[~margin].sum()) == 0
     P.nt_circuit_free(h)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_shortcuts_single_pass_plans(P, ctx, prec):
+    """Short-cuts on circuits whose plan is one pass (n <= tile width): the
+    last-error short-cut reduces to scoring at the only pass."""
+    pr = P.NT_C64 if prec == "c64" else P.NT_C128
+    ftol = 2e-5 if prec == "c64" else 1e-12
+    P.nt_set_precision(ctx, pr)
+    for c in (W.config0(), W.config3_circuit(100003), _all_gates_circuit(11, 3, 5)):
+        h = _load(P, c)
+        npass, _, _ = P.nt_plan_info(h, pr)
+        assert npass == 1
+        for p in (1e-3, 3e-2):
+            P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+            N = 64
+            base = np.zeros(N)
+            P.nt_set_shortcuts(ctx, 0)
+            c0, _ = P.nt_run(ctx, h, 2, 0, N, TAU, base)
+            for flags in (3, 7):
+                _say(f"single-pass short-cuts: n={c.n} p={p} flags={flags} prec={prec}")
+                P.nt_set_shortcuts(ctx, flags)
+                f = np.zeros(N)
+                c1, _ = P.nt_run(ctx, h, 2, 0, N, TAU, f)
+                if flags == 3:
+                    np.testing.assert_array_equal(f.view(np.uint64), base.view(np.uint64))
+                else:
+                    assert np.abs(f - base).max() <= ftol
+        P.nt_set_shortcuts(ctx, 0)
+        P.nt_circuit_free(h)
