@@ -118,3 +118,67 @@ def test_gnn_training_lowers_loss_and_repeats(P, ctx):
     np.testing.assert_array_equal(l0, l1)
     for h in hs:
         P.nt_circuit_free(h)
+
+
+def test_labels_match_oracle_sweep(P, ctx, orc):
+    """Labels are the library's batched Monte Carlo success probabilities;
+    spot-check them against the oracle's sweep (complex128: equal counts)."""
+    from paper_2301_07264_amd import surrogate as SG
+    circs = [W.config3_circuit(s) for s in (300, 301, 302, 303)]
+    circs = [c for c in circs if c.n <= 12][:3]
+    hs = [P.nt_circuit_load(None, c) for c in circs]
+    P.nt_set_precision(ctx, P.NT_C128)
+    N = 96
+    _say("surrogate labels vs oracle sweep")
+    lab = SG.make_labels(ctx, hs, N, seed=4)
+    for i, c in enumerate(circs):
+        want = orc.sweep(c, P.GNN_RATES, 4, N, 0.9, cid=i)
+        np.testing.assert_allclose(lab[i], want, rtol=0, atol=1e-6)
+    P.nt_set_precision(ctx, P.NT_C64)
+    for h in hs:
+        P.nt_circuit_free(h)
+
+
+def test_surrogate_bracket_saves_probes(P, ctx):
+    """Trained on Monte Carlo labels, the surrogate predicts held-out curves
+    well and its bracket needs fewer Monte Carlo probes than the whole grid,
+    reaching the same tolerance."""
+    from paper_2301_07264_amd import surrogate as SG
+    P.nt_set_precision(ctx, P.NT_C64)
+    train_c = [W.config3_circuit(s) for s in range(512)]
+    held_c = [W.config3_circuit(100000 + s) for s in range(48)]
+    th = [P.nt_circuit_load(None, c) for c in train_c]
+    hh = [P.nt_circuit_load(None, c) for c in held_c]
+    _say("surrogate gain: labels")
+    lab_tr = SG.make_labels(ctx, th, 256, seed=1)
+    lab_ho = SG.make_labels(ctx, hh, 256, seed=1)
+    _say("surrogate gain: training")
+    m, losses = SG.train(ctx, th, lab_tr, epochs=60)
+    assert losses[-1] < 0.2 * losses[0]
+    pred = P.nt_gnn_predict(m, hh)
+    mse = float(((pred - lab_ho) ** 2).mean())
+    base = float(((lab_tr.mean(0)[None, :] - lab_ho) ** 2).mean())
+    _say(f"  held-out mse {mse:.3g} vs {base:.3g} for the training mean")
+    assert mse < 0.1 * base
+    ev = [i for i in range(len(hh)) if lab_ho[i, 0] >= 0.66 > lab_ho[i, -1]][:6]
+    assert len(ev) >= 4
+    full, guided = [], []
+    P.nt_set_shortcuts(ctx, 7)
+    for i in ev:
+        _say(f"surrogate gain: searches on held-out circuit {i}")
+        p_f, k_f = P.nt_tolerable_rate(ctx, hh[i], 0.66, 0.01, SG.GRID_LO, SG.GRID_HI, 3, 1024, 0.9)
+        p_g, k_g, br = P.nt_tolerable_rate_guided(ctx, hh[i], m, 0.66, 0.01, 3, 1024, 0.9)
+        # both searches stop on the same criterion over the same trajectories:
+        # the success probability at their rates is within the tolerance
+        for p in (p_f, p_g):
+            P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+            _, Pm = P.nt_run(ctx, hh[i], 3, 0, 1024, 0.9)
+            assert abs(Pm - 0.66) <= 0.01 + 1e-12
+        full.append(k_f)
+        guided.append(k_g)
+    P.nt_set_shortcuts(ctx, 0)
+    _say(f"  probes: whole grid {np.mean(full):.2f}, surrogate bracket {np.mean(guided):.2f}")
+    assert np.mean(guided) < np.mean(full)
+    P.nt_gnn_destroy(m)
+    for h in th + hh:
+        P.nt_circuit_free(h)
