@@ -145,9 +145,7 @@ nt_status nt_plan_info(const nt_circuit *c, int prec, int *n_passes, int *n_segm
   if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
   if (prec != NT_C64 && prec != NT_C128) return fail(NT_ERR_INVALID_ARG, "precision must be NT_C64 or NT_C128");
   return guard([&] {
-    int L, R, cfix;
-    nt::plan_for_precision(*c->impl, prec, &L, &R, &cfix);
-    nt::Plan P = nt::make_plan(*c->impl, L, R, cfix);
+    nt::Plan P = nt::choose_plan(*c->impl, prec);
     if (n_passes) *n_passes = (int)P.passes.size();
     if (n_segments) *n_segments = (int)P.segs.size();
     if (tile_qubits) *tile_qubits = P.L;
@@ -159,9 +157,7 @@ nt_status nt_plan_export(const nt_circuit *c, int prec, int32_t *op_gate, int32_
   if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
   if (prec != NT_C64 && prec != NT_C128) return fail(NT_ERR_INVALID_ARG, "precision must be NT_C64 or NT_C128");
   return guard([&] {
-    int L, R, cfix;
-    nt::plan_for_precision(*c->impl, prec, &L, &R, &cfix);
-    nt::Plan P = nt::make_plan(*c->impl, L, R, cfix);
+    nt::Plan P = nt::choose_plan(*c->impl, prec);
     for (size_t p = 0; p < P.passes.size(); ++p) {
       const nt::Pass &ps = P.passes[p];
       if (pass_local_mask) pass_local_mask[p] = ps.local_mask;

@@ -175,10 +175,9 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
   auto dp = std::make_unique<DevPlan>();
   dp->last_use = ++use_clock;
   dp->prec = pr;
-  int L, R, cfix;
-  plan_for_precision(c, pr, &L, &R, &cfix);
-  dp->plan = make_plan(c, L, R, cfix);
+  dp->plan = choose_plan(c, pr);
   const Plan &P = dp->plan;
+  const int L = P.L, R = P.R;
   dp->nthreads = 1 << (L - R);
   const int SW = pr == NT_C64 ? 4 : 3;
   // Algorithmic flops per amplitude of each op class (complex multiply 6,
@@ -211,7 +210,7 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
     std::vector<int> loc, nl;
     for (int q = 0; q < c.n; ++q) ((ps.local_mask >> q) & 1 ? loc : nl).push_back(q);
     if ((int)loc.size() != L) throw Error(NT_ERR_UNSUPPORTED, "internal: tile size mismatch");
-    for (int q = 0; q < cfix; ++q)
+    for (int q = 0; q < P.cfix; ++q)
       if (loc[q] != q) throw Error(NT_ERR_UNSUPPORTED, "internal: low qubits not local");
     for (size_t i = 0; i < loc.size(); ++i) dpass[p].locq[i] = (uint8_t)loc[i];
     for (size_t i = 0; i < nl.size(); ++i) dpass[p].nlq[i] = (uint8_t)nl[i];

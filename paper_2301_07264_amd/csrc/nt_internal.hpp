@@ -102,6 +102,8 @@ std::vector<HostOp> classify(const Circuit &c);
 // plan.cpp
 Plan make_plan(const Circuit &c, int max_tile_qubits, int max_reg, int cfix);
 void plan_for_precision(const Circuit &c, int prec, int *L, int *R, int *cfix);
+// The plan the library runs for a precision (tile shape chosen per circuit).
+Plan choose_plan(const Circuit &c, int prec);
 
 // sampling thresholds (host, FP64)
 struct Thresholds {
