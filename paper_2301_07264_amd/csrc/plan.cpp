@@ -133,6 +133,32 @@ uint64_t choose_set(Sched &s, uint64_t base, uint64_t pool, int k, int mode = 0)
   return set;
 }
 
+// Local improvement of a pass's local set: exchange one chosen qubit (not
+// in `fixed`) for one outside the set while that lets more ops be scheduled.
+uint64_t improve_set(Sched &s, uint64_t set, uint64_t fixed, uint64_t pool) {
+  int cur = s.drain(set, nullptr);
+  for (int round = 0; round < 64; ++round) {
+    int best = cur;
+    uint64_t best_set = set;
+    for (int qi = 0; qi < s.n; ++qi) {
+      if (!((set >> qi) & 1) || ((fixed >> qi) & 1)) continue;
+      for (int qo = 0; qo < s.n; ++qo) {
+        if (!((pool >> qo) & 1) || ((set >> qo) & 1)) continue;
+        const uint64_t t = (set & ~(1ull << qi)) | (1ull << qo);
+        const int c = s.drain(t, nullptr);
+        if (c > best) {
+          best = c;
+          best_set = t;
+        }
+      }
+    }
+    if (best_set == set) break;
+    set = best_set;
+    cur = best;
+  }
+  return set;
+}
+
 }  // namespace
 
 void plan_for_precision(const Circuit &c, int prec, int *L, int *R, int *cfix) {
@@ -189,7 +215,7 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix) {
     pass_mask.push_back(all & ((1ull << L) - 1));
   }
   while (!top.finished()) {
-    uint64_t lset = (L >= n) ? all : choose_set(top, fixed, all, L);
+    uint64_t lset = (L >= n) ? all : improve_set(top, choose_set(top, fixed, all, L), fixed, all);
     std::vector<int> sched;
     top.drain(lset, &sched);
     if (sched.empty()) throw Error(NT_ERR_UNSUPPORTED, "planner made no progress");
