@@ -41,8 +41,9 @@ ALU_PEAK_TFLOPS = 78.6
 # source they were taken on (profiles/hbm_traffic_*.md).
 MEASURED_TRAFFIC = {
     ("ghz_qft_layers24", "c64", 32): {
-        "bytes_per_launch": 8.413e9,
-        "kernel_sha256": "7d8c5f61a92733fe528522641912181f1a867adc391d0dec644d232cfa7242a0",
+        "bytes_per_launch": 8.417e9,
+        "passes": 43,
+        "kernel_sha256": "0bb2d2d87dfa41b2bc2ee778fe715ea03dd47510e94e293df55497d21242f741",
     },
 }
 
@@ -176,7 +177,7 @@ def main():
             traffic = json.load(f).get("bytes_per_launch")
     else:
         m = MEASURED_TRAFFIC.get((args.workload, args.prec, B))
-        if m and m["kernel_sha256"] == kernel_sha256():
+        if m and m["kernel_sha256"] == kernel_sha256() and m["passes"] == n_pass:
             traffic = m["bytes_per_launch"]
 
     ttr = None

@@ -135,8 +135,8 @@ uint64_t choose_set(Sched &s, uint64_t base, uint64_t pool, int k, int mode = 0)
 
 // Local improvement of a pass's local set: exchange one chosen qubit (not
 // in `fixed`) for one outside the set while that lets more ops be scheduled.
-uint64_t improve_set(Sched &s, uint64_t set, uint64_t fixed, uint64_t pool) {
-  int cur = s.drain(set, nullptr);
+uint64_t improve_set(Sched &s, uint64_t set, uint64_t fixed, uint64_t pool, int mode = 0) {
+  int cur = s.drain(set, nullptr, mode);
   for (int round = 0; round < 64; ++round) {
     int best = cur;
     uint64_t best_set = set;
@@ -145,7 +145,7 @@ uint64_t improve_set(Sched &s, uint64_t set, uint64_t fixed, uint64_t pool) {
       for (int qo = 0; qo < s.n; ++qo) {
         if (!((pool >> qo) & 1) || ((set >> qo) & 1)) continue;
         const uint64_t t = (set & ~(1ull << qi)) | (1ull << qo);
-        const int c = s.drain(t, nullptr);
+        const int c = s.drain(t, nullptr, mode);
         if (c > best) {
           best = c;
           best_set = t;
@@ -252,7 +252,7 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix) {
         P.segs.push_back(sg);
         continue;
       }
-      uint64_t rset = choose_set(in, 0, ps.local_mask, R, 1);
+      uint64_t rset = improve_set(in, choose_set(in, 0, ps.local_mask, R, 1), 0, ps.local_mask, 1);
       std::vector<int> sched;
       in.drain(rset, &sched, 1);
       if (sched.empty()) throw Error(NT_ERR_UNSUPPORTED, "segment planner made no progress");
