@@ -134,6 +134,24 @@ nt_status nt_circuit_info(const nt_circuit *c, int *n, int64_t *G, int64_t *S);
  * draw independent errors. */
 nt_status nt_circuit_set_id(nt_circuit *c, uint64_t circuit_id);
 
+/* Tile width (qubits per work-group tile) of the circuit's plan at precision
+ * `prec`: 0 = automatic (a fixed cost model of the pass count; complex64
+ * takes 2^12-amplitude tiles when their predicted pass cost is at least 5%
+ * lower than 2^13), else a width in [min(n, 10), min(n, 13)] (complex64) or
+ * [min(n, 10), min(n, 12)] (complex128).  The tile width changes which
+ * commuting gates a pass groups, so results change at rounding level only;
+ * with a fixed width they are reproducible.  NT_ERR_INVALID_ARG outside the
+ * range. */
+nt_status nt_circuit_set_tile(nt_circuit *c, int prec, int tile_qubits);
+
+/* Autotuner: runs n_traj trajectories (seed, current error model) with each
+ * allowed tile width from the largest down to two below it, keeps the
+ * fastest as the circuit's tile width (nt_circuit_set_tile) and returns it.
+ * ms_out (may be NULL): milliseconds per candidate, in the order tried
+ * (up to 3 entries). */
+nt_status nt_autotune(nt_ctx *ctx, nt_circuit *c, uint64_t seed, uint64_t n_traj, int *tile_out,
+                      double *ms_out);
+
 /* Host-only view of the gate-pass plan used for precision `prec`: number of
  * HBM passes over a state vector per trajectory, LDS segments, and the
  * local-tile width in qubits. */

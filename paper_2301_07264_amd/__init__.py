@@ -49,6 +49,7 @@ EXPORTED = [
     "nt_set_criterion", "nt_run_batch",
     "nt_gnn_create", "nt_gnn_destroy", "nt_gnn_graph", "nt_gnn_params", "nt_gnn_set_params",
     "nt_gnn_set_data", "nt_gnn_loss_grad", "nt_gnn_train", "nt_gnn_predict", "nt_tolerable_rate_guided",
+    "nt_circuit_set_tile", "nt_autotune",
 ]
 
 GNN_RATES = [10.0 ** (-5.0 + j / 4.0) for j in range(13)]
@@ -128,6 +129,8 @@ def lib() -> C.CDLL:
         "nt_gnn_train": ([P, i32, i32, dbl, u64, P], i32),
         "nt_gnn_predict": ([P, P, i32, i32, P], i32),
         "nt_tolerable_rate_guided": ([P, P, P, dbl, dbl, u64, u64, dbl, P, P, P], i32),
+        "nt_circuit_set_tile": ([P, i32, i32], i32),
+        "nt_autotune": ([P, P, u64, u64, P, P], i32),
         "nt_exhaustive": ([P, P, dbl, P, P, P], i32),
         "nt_eq4": ([P, dbl, P, P], i32),
         "nt_eq5": ([dbl, P, dbl, dbl, P], i32),
@@ -486,3 +489,15 @@ def nt_tolerable_rate_guided(ctx, circ, m, P_target: float, tol: float, seed: in
     _check(lib().nt_tolerable_rate_guided(ctx, circ, m, P_target, tol, seed, n_traj, tau, C.byref(p), C.byref(k),
                                           _ptr(br)))
     return p.value, k.value, (float(br[0]), float(br[1]))
+
+
+def nt_circuit_set_tile(circ, prec: int, tile_qubits: int) -> None:
+    _check(lib().nt_circuit_set_tile(circ, prec, tile_qubits))
+
+
+def nt_autotune(ctx, circ, seed: int, n_traj: int):
+    """Returns (chosen tile width, milliseconds per candidate)."""
+    t = C.c_int()
+    ms = np.zeros(3, np.float64)
+    _check(lib().nt_autotune(ctx, circ, seed, n_traj, C.byref(t), _ptr(ms)))
+    return t.value, ms

@@ -2,6 +2,7 @@
 // validates its arguments, converts internal errors into nt_status codes and
 // records a thread-local message; no exception crosses the boundary.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -138,6 +139,55 @@ nt_status nt_circuit_set_id(nt_circuit *c, uint64_t cid) {
   if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
   c->impl->cid = cid;
   g_last_error.clear();
+  return NT_OK;
+}
+
+static nt_status check_run_args(nt_ctx *ctx, const nt_circuit *c, double tau);
+
+nt_status nt_circuit_set_tile(nt_circuit *c, int prec, int tile_qubits) {
+  if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
+  if (prec != NT_C64 && prec != NT_C128) return fail(NT_ERR_INVALID_ARG, "precision must be NT_C64 or NT_C128");
+  int lo = 0, hi = 0;
+  nt::tile_range(*c->impl, prec, &lo, &hi);
+  if (tile_qubits != 0 && (tile_qubits < lo || tile_qubits > hi))
+    return fail(NT_ERR_INVALID_ARG, "tile width outside [" + std::to_string(lo) + ", " + std::to_string(hi) + "]");
+  c->impl->tile_override[prec == NT_C64 ? 1 : 2] = tile_qubits;
+  g_last_error.clear();
+  return NT_OK;
+}
+
+nt_status nt_autotune(nt_ctx *ctx, nt_circuit *c, uint64_t seed, uint64_t n_traj, int *tile_out, double *ms_out) {
+  nt_status s = check_run_args(ctx, c, 0.9);
+  if (s) return s;
+  if (n_traj == 0) return fail(NT_ERR_INVALID_ARG, "n_traj must be > 0");
+  const int slot = ctx->impl->prec == NT_C64 ? 1 : 2;
+  const int saved = c->impl->tile_override[slot];
+  int best = 0;
+  nt_status st = guard([&] {
+    nt::Ctx &cx = *ctx->impl;
+    int lo = 0, hi = 0;
+    nt::tile_range(*c->impl, cx.prec, &lo, &hi);
+    double best_ms = 0;
+    int k = 0;
+    for (int L = hi; L >= std::max(lo, hi - 2); --L, ++k) {
+      c->impl->tile_override[slot] = L;
+      cx.run(*c->impl, seed, 0, std::min<uint64_t>(n_traj, 4), 0.9, nullptr, nullptr);   // plan, reference, warm-up
+      const auto t0 = std::chrono::steady_clock::now();
+      cx.run(*c->impl, seed, 0, n_traj, 0.9, nullptr, nullptr);
+      const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (ms_out) ms_out[k] = ms;
+      if (best == 0 || ms < best_ms) {
+        best = L;
+        best_ms = ms;
+      }
+    }
+    c->impl->tile_override[slot] = best;
+  });
+  if (st) {
+    c->impl->tile_override[slot] = saved;
+    return st;
+  }
+  if (tile_out) *tile_out = best;
   return NT_OK;
 }
 

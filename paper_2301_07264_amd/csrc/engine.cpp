@@ -165,7 +165,8 @@ static void upload_ops(DevPlan &dp, const std::vector<int32_t> &code, const std:
 }
 
 DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
-  auto key = std::make_pair(c.serial, pr);
+  // the tile override is part of the key: changing it builds a new plan
+  auto key = std::make_pair(c.serial, pr + 16 * c.tile_override[pr == NT_C64 ? 1 : 2]);
   auto it = plans.find(key);
   if (it != plans.end()) {
     it->second->last_use = ++use_clock;

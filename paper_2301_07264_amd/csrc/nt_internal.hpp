@@ -87,6 +87,7 @@ struct Circuit {
   int64_t S = 0;
   uint64_t cid = 0;
   uint64_t serial = 0;                  // unique per loaded circuit
+  int tile_override[3] = {0, 0, 0};     // per precision (NT_C64, NT_C128): tile qubits, 0 = automatic
 };
 
 // circuit.cpp
@@ -102,8 +103,11 @@ std::vector<HostOp> classify(const Circuit &c);
 // plan.cpp
 Plan make_plan(const Circuit &c, int max_tile_qubits, int max_reg, int cfix);
 void plan_for_precision(const Circuit &c, int prec, int *L, int *R, int *cfix);
-// The plan the library runs for a precision (tile shape chosen per circuit).
+// The plan the library runs for a precision (tile shape chosen per circuit,
+// or the circuit's override).
 Plan choose_plan(const Circuit &c, int prec);
+// Range of tile widths a precision allows for a circuit: [lo, hi].
+void tile_range(const Circuit &c, int prec, int *lo, int *hi);
 
 // sampling thresholds (host, FP64)
 struct Thresholds {

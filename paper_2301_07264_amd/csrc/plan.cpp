@@ -178,9 +178,22 @@ void plan_for_precision(const Circuit &c, int prec, int *L, int *R, int *cfix) {
 // tile has fewer local qubits, so it can need more passes; it is taken when
 // its predicted pass cost is at least 5% lower.  Deterministic (a function of
 // the circuit), so results stay a function of the inputs.
+void tile_range(const Circuit &c, int prec, int *lo, int *hi) {
+  int L, R, cfix;
+  plan_for_precision(c, prec, &L, &R, &cfix);
+  *hi = L;
+  *lo = std::min(L, 10);   // 2^(L - 4) >= 64 threads per work-group
+}
+
 Plan choose_plan(const Circuit &c, int prec) {
   int L, R, cfix;
   plan_for_precision(c, prec, &L, &R, &cfix);
+  const int ov = c.tile_override[prec == NT_C64 ? 1 : 2];
+  if (ov > 0) {
+    const int Lo = std::min(ov, L);
+    const int Ro = std::max(2, std::min(4, Lo - 6));
+    return make_plan(c, Lo, std::min(Ro, Lo), cfix);
+  }
   Plan p = make_plan(c, L, R, cfix);
   if (prec == NT_C64 && L == 13 && p.passes.size() > 1) {
     const int L2 = 12, R2 = std::max(2, std::min(4, L2 - 6));

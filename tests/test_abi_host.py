@@ -179,3 +179,27 @@ def test_workload_sizes():
     assert (W.config1().G, W.config1().S) == (2136, 3047)
     assert (W.config4().G, W.config4().S) == (330, 510)
     assert len(W.rates_config1()) == 13 and abs(W.rates_config1()[-1] - 1e-2) < 1e-15
+
+
+def test_tile_override_host(P):
+    c = W.config1(n=20, layers=4)
+    h = P.nt_circuit_load(None, c)
+    _, _, L0 = P.nt_plan_info(h, P.NT_C64)
+    assert L0 in (12, 13)
+    for L in (10, 11, 12, 13):
+        P.nt_circuit_set_tile(h, P.NT_C64, L)
+        npass, nseg, Lp = P.nt_plan_info(h, P.NT_C64)
+        assert Lp == L and npass >= 1
+    with pytest.raises(P.NtError):
+        P.nt_circuit_set_tile(h, P.NT_C64, 14)
+    with pytest.raises(P.NtError):
+        P.nt_circuit_set_tile(h, P.NT_C128, 13)
+    with pytest.raises(P.NtError):
+        P.nt_circuit_set_tile(h, P.NT_C64, 9)
+    P.nt_circuit_set_tile(h, P.NT_C64, 0)
+    assert P.nt_plan_info(h, P.NT_C64)[2] == L0
+    P.nt_circuit_free(h)
+    small = P.nt_circuit_load(None, W.config0())          # n = 8: the only width is 8
+    P.nt_circuit_set_tile(small, P.NT_C64, 8)
+    assert P.nt_plan_info(small, P.NT_C64)[2] == 8
+    P.nt_circuit_free(small)

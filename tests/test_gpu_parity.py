@@ -446,3 +446,35 @@ def test_shortcuts_single_pass_plans(P, ctx, prec):
                     assert np.abs(f - base).max() <= ftol
         P.nt_set_shortcuts(ctx, 0)
         P.nt_circuit_free(h)
+
+
+def test_tile_widths_and_autotune(P, ctx, orc):
+    """Every allowed tile width gives the oracle's fidelities (to the
+    precision's bar); the autotuner picks one of the candidates it timed and
+    runs are reproducible under the chosen width."""
+    c = W.random_layers(17, 8, np.random.default_rng(77))
+    h = _load(P, c)
+    P.nt_set_precision(ctx, P.NT_C64)
+    p = 0.02
+    P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+    N = 8
+    want, _ = orc.run(c, p / 3, p / 3, p / 3, 6, 0, N, TAU)
+    for L in (10, 11, 12, 13):
+        _say(f"tile width {L}")
+        P.nt_circuit_set_tile(h, P.NT_C64, L)
+        assert P.nt_plan_info(h, P.NT_C64)[2] == L
+        f = np.zeros(N)
+        P.nt_run(ctx, h, 6, 0, N, TAU, f)
+        assert np.abs(f - want).max() <= 2e-5
+    P.nt_circuit_set_tile(h, P.NT_C64, 0)
+    _say("autotune")
+    L, ms = P.nt_autotune(ctx, h, 1, 64)
+    assert L in (11, 12, 13) and np.all(ms > 0)
+    assert P.nt_plan_info(h, P.NT_C64)[2] == L
+    a = np.zeros(N)
+    b = np.zeros(N)
+    P.nt_run(ctx, h, 6, 0, N, TAU, a)
+    P.nt_run(ctx, h, 6, 0, N, TAU, b)
+    np.testing.assert_array_equal(a.view(np.uint64), b.view(np.uint64))
+    assert np.abs(a - want).max() <= 2e-5
+    P.nt_circuit_free(h)
