@@ -244,6 +244,10 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
             rb = __builtin_ctz((unsigned)am);
           }
           code[o] = op_code(h, rb);
+          // diagonal ops with exactly one register qubit: body specialized on its bit
+          if (h.cls == OPC_D1 && am) code[o] = ntk::OPK_D1R * 4 + __builtin_ctz((unsigned)am);
+          if (h.cls == OPC_D2 && am && !bm) code[o] = ntk::OPK_D2A * 4 + __builtin_ctz((unsigned)am);
+          if (h.cls == OPC_D2 && bm && !am) code[o] = ntk::OPK_D2B * 4 + __builtin_ctz((unsigned)bm);
         } else {
           throw Error(NT_ERR_UNSUPPORTED, "internal: dense 2q op in a register segment");
         }

@@ -275,6 +275,14 @@ DEV cx<T> perm4(const OpLite<T> &h, int i, uint32_t xm) {
   return xm == 0u ? e0 : (xm == 1u ? e1 : (xm == 2u ? e2 : e3));
 }
 
+// Diagonal whose phase is p1 on the slots with register bit B set and p0
+// on the others (B known at compile time: no per-slot selects).
+template <int B, int R, typename T>
+DEV void diag_bit(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> p0, cx<T> p1) {
+#pragma unroll
+  for (int r = 0; r < (1 << R); ++r) w[r] = cmul(((r >> B) & 1) ? p1 : p0, v[r]);
+}
+
 // Diagonal on one qubit: a uniform phase per slot when the qubit is a
 // register qubit, one phase per lane otherwise.
 template <int R, typename T>
@@ -369,6 +377,33 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
     NT_G1(2)
     NT_G1(3)
 #undef NT_G1
+    // Diagonal ops with one register qubit at bit b.  Under the frame the
+    // phase of index g is D(g ^ x): the frame's X flips index bits, so it
+    // swaps the two phases of a slot group instead of permuting entries.
+#define NT_D(b)                                                                           \
+  case OPK_D1R * 4 + b:                                                                   \
+    if constexpr (b < R) diag_bit<b, R>(v, w, xa ? m01 : m00, xa ? m00 : m01);            \
+    break;                                                                                \
+  case OPK_D2A * 4 + b:                                                                   \
+    if constexpr (b < R) {                                                                \
+      const uint32_t t = ((gb >> qc) & 1u) ^ ((fx >> qc) & 1u);                           \
+      const cx<T> lo = t ? m10 : m00, hi = t ? m11 : m01;                                 \
+      diag_bit<b, R>(v, w, xa ? hi : lo, xa ? lo : hi);                                   \
+    }                                                                                     \
+    break;                                                                                \
+  case OPK_D2B * 4 + b:                                                                   \
+    if constexpr (b < R) {                                                                \
+      const uint32_t t = ((gb >> qa) & 1u) ^ xa;                                          \
+      const uint32_t xb = (fx >> qc) & 1u;                                                \
+      const cx<T> lo = t ? m01 : m00, hi = t ? m11 : m10;                                 \
+      diag_bit<b, R>(v, w, xb ? hi : lo, xb ? lo : hi);                                   \
+    }                                                                                     \
+    break;
+    NT_D(0)
+    NT_D(1)
+    NT_D(2)
+    NT_D(3)
+#undef NT_D
     case OPK_D1 * 4: {
       d1_apply<R>(v, w, xa ? m01 : m00, xa ? m00 : m01, (gb >> qa) & 1u, am);
       break;

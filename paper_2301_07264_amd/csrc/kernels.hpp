@@ -25,16 +25,20 @@ struct DevOp {
   T m[32];
 };
 
-// Op dispatch codes: kind * 4 + register bit (kinds with a register target)
-// or kind * 4 (diagonal kinds).  G2 ops live in quad segments.
+// Op dispatch codes: kind * 4 + register bit (kinds with a register
+// qubit) or kind * 4 (diagonal kinds without one).  G2 ops live in quad
+// segments.
 enum : int32_t {
   OPK_G1 = 0,   // general complex 2x2, m = 4 entries
   OPK_G1R = 1,  // real 2x2 (imaginary parts zero)
   OPK_G1X = 2,  // [[c, -i s], [-i s, c]]: m00 = c, m01 = -i s
   OPK_CX = 3,   // controlled X: qa target, qb control
-  OPK_D1 = 4,   // diagonal (d0, d1) on qa
-  OPK_D2 = 5,   // diagonal (d0..d3) on local index b_qa + 2 b_qb
+  OPK_D1 = 4,   // diagonal (d0, d1) on qa, qa not a register qubit
+  OPK_D2 = 5,   // diagonal (d0..d3) on local index b_qa + 2 b_qb: both or neither in registers
   OPK_G2 = 6,   // dense 4x4 (quad segment)
+  OPK_D2A = 7,  // diagonal on two qubits, qa in register bit b, qb not
+  OPK_D2B = 8,  // diagonal on two qubits, qb in register bit b, qa not
+  OPK_D1R = 9,  // diagonal on one qubit, qa in register bit b
 };
 
 // One register segment: which local bits / global qubits the thread's
