@@ -646,21 +646,22 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     int o = sg.op_begin;
     if (o < sg.op_end) {
       OpLite<T> cur = load_lite(ops, o);
-      for (; o + 1 < sg.op_end; o += 2) {
-        OpLite<T> nxt = load_lite(ops, o + 1);   // next op's loads in flight
+      for (; o < sg.op_end; o += 2) {
+        OpLite<T> nxt = cur;
+        if (o + 1 < sg.op_end) nxt = load_lite(ops, o + 1);   // next op's loads in flight
         apply_reg_op<R, T>(cur, v, w, gb, fx, fz, fc);
         take_events(o);
-        cur = nxt;
-        if (o + 2 < sg.op_end) nxt = load_lite(ops, o + 2);
-        apply_reg_op<R, T>(cur, w, v, gb, fx, fz, fc);
-        take_events(o + 1);
-        cur = nxt;
-      }
-      if (o < sg.op_end) {
-        apply_reg_op<R, T>(cur, v, w, gb, fx, fz, fc);
-        take_events(o);
+        if (o + 1 < sg.op_end) {
+          cur = nxt;
+          if (o + 2 < sg.op_end) nxt = load_lite(ops, o + 2);
+          apply_reg_op<R, T>(cur, w, v, gb, fx, fz, fc);
+          take_events(o + 1);
+          cur = nxt;
+        } else {
+          // odd op count: the last result is in w
 #pragma unroll
-        for (int r = 0; r < NS; ++r) v[r] = w[r];
+          for (int r = 0; r < NS; ++r) v[r] = w[r];
+        }
       }
     }
 #pragma unroll
