@@ -41,9 +41,14 @@ ALU_PEAK_TFLOPS = 78.6
 # source they were taken on (profiles/hbm_traffic_*.md).
 MEASURED_TRAFFIC = {
     ("ghz_qft_layers24", "c64", 32): {
-        "bytes_per_launch": 8.417e9,
+        "bytes_per_launch": 8.418e9,
         "passes": 43,
-        "kernel_sha256": "0bb2d2d87dfa41b2bc2ee778fe715ea03dd47510e94e293df55497d21242f741",
+        "kernel_sha256": "d06523af38e650aa45e015cac6b7301791867b0a36d30ffc3f211bb856c40576",
+    },
+    ("qaoa3reg30", "c64", 4): {
+        "bytes_per_launch": 6.560e10,
+        "passes": 11,
+        "kernel_sha256": "d06523af38e650aa45e015cac6b7301791867b0a36d30ffc3f211bb856c40576",
     },
 }
 
