@@ -28,6 +28,17 @@ namespace ntk {
 
 #define DEV __device__ __forceinline__
 
+// Plan tables, error events and the previous pass's frames are never written
+// while a pass kernel runs.  Reading them through the constant address space
+// lets the compiler turn uniform loads into scalar loads, so op headers,
+// matrix entries and frame bits stay in SGPRs and the frame conjugation of an
+// op is scalar work instead of vector selects.
+#define NT_CONST __attribute__((address_space(4)))
+template <typename X>
+DEV const NT_CONST X *cptr(const X *p) {
+  return (const NT_CONST X *)p;
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).
 
@@ -138,7 +149,7 @@ DEV cx<T> cneg(cx<T> v) {
 
 // Matrix entry i of an op (uniform address).
 template <typename T>
-DEV cx<T> ment(const DevOp<T> &op, uint32_t i) {
+DEV cx<T> ment(const NT_CONST DevOp<T> &op, uint32_t i) {
   return cx<T>{op.m[2 * i], op.m[2 * i + 1]};
 }
 
@@ -252,7 +263,7 @@ struct OpLite {
 
 template <typename T>
 DEV OpLite<T> load_lite(const DevOp<T> *ops, int o) {
-  const DevOp<T> &op = ops[o];
+  const NT_CONST DevOp<T> &op = cptr(ops)[o];
   OpLite<T> h;
   h.code = op.cls;
   h.qa = op.qa;
@@ -425,7 +436,7 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
 // Dense two-qubit op applied directly to the tile in LDS (quad segment).
 // rsel holds the tile-local bit positions of qa (bits 0..3) and qb (4..7).
 template <typename T>
-DEV void apply_quad_lds(const DevOp<T> &op, cx<T> *lds, int L, uint32_t fx, uint32_t fz) {
+DEV void apply_quad_lds(const NT_CONST DevOp<T> &op, cx<T> *lds, int L, uint32_t fx, uint32_t fz) {
   const uint32_t qa = (uint32_t)op.qa, qb = (uint32_t)op.qb;
   const uint32_t pa = (uint32_t)op.rsel & 15u, pb = ((uint32_t)op.rsel >> 4) & 15u;
   const uint32_t xm = ((fx >> qa) & 1u) | (((fx >> qb) & 1u) << 1);
@@ -500,8 +511,8 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   const int b = (int)(blockIdx.x % (uint32_t)a.B);
   const uint32_t tile = blockIdx.x / (uint32_t)a.B;
   // trajectories already scored at an earlier pass have nothing to do
-  if (a.end && a.pass_index > a.end[b]) return;
-  const bool score_here = a.end ? (a.end[b] == a.pass_index) : ((a.flags & PF_SCORE) != 0);
+  if (a.end && a.pass_index > cptr(a.end)[b]) return;
+  const bool score_here = a.end ? (cptr(a.end)[b] == a.pass_index) : ((a.flags & PF_SCORE) != 0);
   const cx<T> *refp = a.end ? a.ref_here : a.ref;
   const DevOp<T> *ops = a.ops;
   const DevSeg *segs = a.segs;
@@ -509,8 +520,8 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   int seg_begin = a.seg_begin, seg_end = a.seg_end, op_begin = a.op_begin;
   double heavy_med = a.heavy_med;
   if (a.multi) {
-    const MultiItem<T> &m = a.multi[b / a.per_item];
-    if ((a.flags & PF_SKIP0) && a.ev_count[b] == 0) {
+    const NT_CONST MultiItem<T> &m = cptr(a.multi)[b / a.per_item];
+    if ((a.flags & PF_SKIP0) && cptr(a.ev_count)[b] == 0) {
       // F = <R|R>^2 / (<R|R> <R|R>) = 1 exactly, as for the simulated state
       if (threadIdx.x == 0) {
         double *pt = a.partials + (size_t)b * NPART;
@@ -531,7 +542,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     heavy_med = m.heavy_med;
   }
 
-  const DevPass &ps = *passp;
+  const NT_CONST DevPass &ps = *cptr(passp);
   uint32_t tilebase = 0;
   for (int i = 0; i < a.ntile_bits; ++i) tilebase |= ((tile >> i) & 1u) << ps.nlq[i];
   cx<T> *st = a.state + (uint64_t)b * a.state_stride;
@@ -559,7 +570,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   const cx<T> *sp = st + (tilebase | dlo);   // dhi(k) bits are disjoint from tilebase | dlo
 
   // Load the tile (coalesced: thread-id bits are the low local bits).
-  const int my_start = a.start ? a.start[b] : 0;
+  const int my_start = a.start ? cptr(a.start)[b] : 0;
   if (my_start == a.pass_index && a.pass_index == 0) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
@@ -580,8 +591,8 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   // or (first pass of the trajectory) the identity with every earlier error
   // applied.  next_op is the op index of the trajectory's next error event
   // (~0 when there is none).
-  const uint32_t *ev = a.events + (size_t)b * a.ev_stride;
-  const int ne = __builtin_amdgcn_readfirstlane(a.ev_count[b]);
+  const NT_CONST uint32_t *ev = cptr(a.events + (size_t)b * a.ev_stride);
+  const int ne = __builtin_amdgcn_readfirstlane(cptr(a.ev_count)[b]);
   const bool carried = a.frame_in != nullptr && my_start < a.pass_index;
   int ep = 0;
   uint32_t fx = 0, fz = 0, fc = 0;
@@ -593,9 +604,10 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     ++ep;
   }
   if (carried) {
-    fx = __builtin_amdgcn_readfirstlane(a.frame_in[4 * b + 0]);
-    fz = __builtin_amdgcn_readfirstlane(a.frame_in[4 * b + 1]);
-    fc = __builtin_amdgcn_readfirstlane(a.frame_in[4 * b + 2]);
+    const NT_CONST uint32_t *fin = cptr(a.frame_in + 4 * b);
+    fx = __builtin_amdgcn_readfirstlane(fin[0]);
+    fz = __builtin_amdgcn_readfirstlane(fin[1]);
+    fc = __builtin_amdgcn_readfirstlane(fin[2]);
   }
   if (ep < ne) next_op = next_e >> 8;
   auto take_events = [&](int o) {
@@ -612,9 +624,9 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   };
 
   for (int s = seg_begin; s < seg_end; ++s) {
-    const DevSeg &sg = segs[s];
+    const NT_CONST DevSeg &sg = cptr(segs)[s];
     if (sg.kind == SEG_KIND_QUAD) {
-      apply_quad_lds<T>(ops[sg.op_begin], lds, a.L, fx, fz);
+      apply_quad_lds<T>(cptr(ops)[sg.op_begin], lds, a.L, fx, fz);
       take_events(sg.op_begin);
       __syncthreads();
       continue;
