@@ -248,6 +248,13 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
           if (h.cls == OPC_D1 && am) code[o] = ntk::OPK_D1R * 4 + __builtin_ctz((unsigned)am);
           if (h.cls == OPC_D2 && am && !bm) code[o] = ntk::OPK_D2A * 4 + __builtin_ctz((unsigned)am);
           if (h.cls == OPC_D2 && bm && !am) code[o] = ntk::OPK_D2B * 4 + __builtin_ctz((unsigned)bm);
+          if (h.cls == OPC_D2 && am && bm) {
+            const int lo = __builtin_ctz((unsigned)(am < bm ? am : bm)), hi = __builtin_ctz((unsigned)(am < bm ? bm : am));
+            int k = 0;
+            while (k < 6 && !(ntk::D2RR_PAIRS[k][0] == lo && ntk::D2RR_PAIRS[k][1] == hi)) ++k;
+            if (k == 6) throw Error(NT_ERR_UNSUPPORTED, "internal: register-bit pair out of range");
+            code[o] = ntk::OPK_D2RR * 4 + k;
+          }
         } else {
           throw Error(NT_ERR_UNSUPPORTED, "internal: dense 2q op in a register segment");
         }

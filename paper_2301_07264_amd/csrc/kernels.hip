@@ -147,6 +147,21 @@ DEV cx<T> cneg(cx<T> v) {
   return cx<T>{-v.x, -v.y};
 }
 
+// Copy a uniform value into a VGPR.  On gfx950 a VALU instruction that reads
+// an SGPR operand issues at most every 4 cycles per SIMD, while FP32
+// arithmetic on VGPR operands alone can issue about twice as fast; a gate
+// body's 64-128 FMAs all read the same few matrix entries, so one move per
+// entry pays for itself many times over.
+template <typename T>
+DEV T vpin(T x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+template <typename T>
+DEV cx<T> vpin(cx<T> x) {
+  return cx<T>{vpin(x.x), vpin(x.y)};
+}
+
 // Matrix entry i of an op (uniform address).
 template <typename T>
 DEV cx<T> ment(const NT_CONST DevOp<T> &op, uint32_t i) {
@@ -223,33 +238,42 @@ DEV void g1x_apply(const cx<T> (&v)[1 << R], cx<T> (&o)[1 << R], T c, T w) {
   }
 }
 
-// Controlled X on register bit B: a conditional swap of each register pair.
-// (The frame's Z on the target, which would turn X into -X, is moved into the
-// frame by the caller.)  take_lane: control condition for a control outside
-// the registers (per lane); cmask: register bit of the control (0 if none);
-// creg: whether a set register control bit satisfies the control value
-// (uniform).
+// Controlled X on register bit B, control value 1 (the caller moves the
+// frame's effect on the control value into the frame): a swap of each
+// register pair whose control bit is set.  With the control in the
+// registers (register bit C) the swap pattern is known at compile time and
+// the op is a plain register permutation; with the control outside them
+// the swap is a per-lane select.
+template <int B, int C, int R, typename T>
+DEV void cx_perm(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R]) {
+#pragma unroll
+  for (int r = 0; r < (1 << R); ++r) w[r] = ((r >> C) & 1) ? v[r ^ (1 << B)] : v[r];
+}
+
 template <int B, int R, typename T>
-DEV void cx_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], bool take_lane, uint32_t cmask, bool creg) {
-  if (cmask) {
-    // control in the registers: the swap of each pair is uniform (a set
-    // control bit satisfies the control iff creg; a clear one iff !creg)
+DEV void cx_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], bool take_lane, uint32_t cmask) {
+  switch (cmask) {
+    case 1u:
+      if constexpr (B != 0) { cx_perm<B, 0, R>(v, w); return; }
+      break;
+    case 2u:
+      if constexpr (B != 1 && R > 1) { cx_perm<B, 1, R>(v, w); return; }
+      break;
+    case 4u:
+      if constexpr (B != 2 && R > 2) { cx_perm<B, 2, R>(v, w); return; }
+      break;
+    case 8u:
+      if constexpr (B != 3 && R > 3) { cx_perm<B, 3, R>(v, w); return; }
+      break;
+    default:
+      break;
+  }
 #pragma unroll
-    for (int r = 0; r < (1 << R); ++r) {
-      if (r & (1 << B)) continue;
-      const cx<T> x = v[r], y = v[r | (1 << B)];
-      const bool take = (((uint32_t)r & cmask) != 0u) == creg;
-      w[r] = take ? y : x;
-      w[r | (1 << B)] = take ? x : y;
-    }
-  } else {
-#pragma unroll
-    for (int r = 0; r < (1 << R); ++r) {
-      if (r & (1 << B)) continue;
-      const cx<T> x = v[r], y = v[r | (1 << B)];
-      w[r] = take_lane ? y : x;
-      w[r | (1 << B)] = take_lane ? x : y;
-    }
+  for (int r = 0; r < (1 << R); ++r) {
+    if (r & (1 << B)) continue;
+    const cx<T> x = v[r], y = v[r | (1 << B)];
+    w[r] = take_lane ? y : x;
+    w[r | (1 << B)] = take_lane ? x : y;
   }
 }
 
@@ -294,52 +318,45 @@ DEV void diag_bit(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> p0, cx<T> 
   for (int r = 0; r < (1 << R); ++r) w[r] = cmul(((r >> B) & 1) ? p1 : p0, v[r]);
 }
 
-// Diagonal on one qubit: a uniform phase per slot when the qubit is a
-// register qubit, one phase per lane otherwise.
+// Diagonal on one qubit outside the registers: one phase per lane.
 template <int R, typename T>
-DEV void d1_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> d0, cx<T> d1, uint32_t lane, uint32_t am) {
-  if (am) {
+DEV void d1_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> d0, cx<T> d1, uint32_t lane) {
+  const cx<T> d = lane ? d1 : d0;
 #pragma unroll
-    for (int r = 0; r < (1 << R); ++r) w[r] = cmul(((uint32_t)r & am) ? d1 : d0, v[r]);
-  } else {
-    const cx<T> d = lane ? d1 : d0;
+  for (int r = 0; r < (1 << R); ++r) w[r] = cmul(d, v[r]);
+}
+
+// Diagonal on two qubits outside the registers: one phase per lane, entries
+// d[b_a + 2 b_b].
+template <int R, typename T>
+DEV void d2_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> d0, cx<T> d1, cx<T> d2, cx<T> d3, uint32_t la,
+                  uint32_t lb) {
+  const cx<T> d = lb ? (la ? d3 : d2) : (la ? d1 : d0);
 #pragma unroll
-    for (int r = 0; r < (1 << R); ++r) w[r] = cmul(d, v[r]);
+  for (int r = 0; r < (1 << R); ++r) w[r] = cmul(d, v[r]);
+}
+
+// Diagonal on register bits LO < HI: slot r takes p[b_LO + 2 b_HI] (known at
+// compile time, so no per-slot selects).
+template <int LO, int HI, int R, typename T>
+DEV void diag2(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> p0, cx<T> p1, cx<T> p2, cx<T> p3) {
+#pragma unroll
+  for (int r = 0; r < (1 << R); ++r) {
+    const int i = ((r >> LO) & 1) | (((r >> HI) & 1) << 1);
+    w[r] = cmul(i == 0 ? p0 : (i == 1 ? p1 : (i == 2 ? p2 : p3)), v[r]);
   }
 }
 
-// Diagonal on two qubits, entries d[b_a + 2 b_b].
-template <int R, typename T>
-DEV void d2_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> d0, cx<T> d1, cx<T> d2, cx<T> d3, uint32_t la, uint32_t lb,
-                  uint32_t am, uint32_t bm) {
-  if (!am && !bm) {
-    const cx<T> d = lb ? (la ? d3 : d2) : (la ? d1 : d0);
-#pragma unroll
-    for (int r = 0; r < (1 << R); ++r) w[r] = cmul(d, v[r]);
-  } else if (am && bm) {
-#pragma unroll
-    for (int r = 0; r < (1 << R); ++r) {
-      const bool ba = ((uint32_t)r & am) != 0, bb = ((uint32_t)r & bm) != 0;
-      w[r] = cmul(bb ? (ba ? d3 : d2) : (ba ? d1 : d0), v[r]);
-    }
-  } else if (am) {
-    const cx<T> p0 = lb ? d2 : d0, p1 = lb ? d3 : d1;   // by the register bit of qa
-#pragma unroll
-    for (int r = 0; r < (1 << R); ++r) w[r] = cmul(((uint32_t)r & am) ? p1 : p0, v[r]);
-  } else {
-    const cx<T> p0 = la ? d1 : d0, p1 = la ? d3 : d2;   // by the register bit of qb
-#pragma unroll
-    for (int r = 0; r < (1 << R); ++r) w[r] = cmul(((uint32_t)r & bm) ? p1 : p0, v[r]);
-  }
-}
-
-// A frame Z on the target of a CNOT (control value cv after the frame's X)
-// turns the conjugated op into C(-X) = (+-Z_c) CX; the +-Z_c is absorbed into
-// the frame instead of being applied: z_c ^= 1, and a factor -1 (i^2) when
-// cv = 0.  Exact, and keeps the register work a plain conditional swap.
-DEV void cx_frame(uint32_t za, uint32_t qc, uint32_t cv, uint32_t &fz, uint32_t &fc) {
-  fz = __builtin_amdgcn_readfirstlane(fz ^ (za << qc));
-  fc = __builtin_amdgcn_readfirstlane(fc + (za & (cv ^ 1u)) * 2u);
+// Frame update of a CNOT (control qc, target qt).  Conjugated by the frame,
+// the CNOT becomes (+-Z_c)^{z_t} CX_cv: the frame's X on the control sets the
+// control value cv, its Z on the target turns X into -X = (+-Z_c) X (sign +
+// for cv = 1).  The register work is always CX_1, since CX_0 = X_t CX_1, and
+// both factors around it move into the frame: F <- F (+-Z_c)^{z_t} X_t^{1-cv}.
+// Working out the products: z_c ^= z_t, x_t ^= 1 - cv, and the phase is
+// unchanged (the -1 of -Z_c is cancelled by commuting X_t past Z_t).
+DEV void cx_frame(uint32_t zt, uint32_t qc, uint32_t qt, uint32_t cv, uint32_t &fx, uint32_t &fz) {
+  fz = __builtin_amdgcn_readfirstlane(fz ^ (zt << qc));
+  fx = __builtin_amdgcn_readfirstlane(fx ^ ((cv ^ 1u) << qt));
 }
 
 // Apply one register-segment op, conjugated by the current Pauli frame, to
@@ -349,7 +366,7 @@ DEV void cx_frame(uint32_t za, uint32_t qc, uint32_t cv, uint32_t &fz, uint32_t 
 // M gives entries (i, j) = (-1)^{z(i+j)} M[i^x][j^x].
 template <int R, typename T>
 DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], uint32_t gb,
-                      uint32_t fx, uint32_t &fz, uint32_t &fc) {
+                      uint32_t &fx, uint32_t &fz, uint32_t &fc) {
   const int code = op.code;
   const uint32_t qa = (uint32_t)op.qa;
   const uint32_t xa = (fx >> qa) & 1u, za = (fz >> qa) & 1u;
@@ -369,18 +386,19 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
   switch (code) {
 #define NT_G1(b)                                                                          \
   case OPK_G1 * 4 + b:                                                                    \
-    if constexpr (b < R) g1_apply<b, R>(v, w, c00, c01, c10, c11);                        \
+    if constexpr (b < R) g1_apply<b, R>(v, w, vpin(c00), vpin(c01), vpin(c10), vpin(c11));\
     break;                                                                                \
   case OPK_G1R * 4 + b:                                                                   \
-    if constexpr (b < R) g1r_apply<b, R>(v, w, c00.x, c01.x, c10.x, c11.x);               \
+    if constexpr (b < R)                                                                  \
+      g1r_apply<b, R>(v, w, vpin(c00.x), vpin(c01.x), vpin(c10.x), vpin(c11.x));          \
     break;                                                                                \
   case OPK_G1X * 4 + b:                                                                   \
-    if constexpr (b < R) g1x_apply<b, R>(v, w, m00.x, za ? -m01.y : m01.y);               \
+    if constexpr (b < R) g1x_apply<b, R>(v, w, vpin(m00.x), vpin(za ? -m01.y : m01.y));   \
     break;                                                                                \
   case OPK_CX * 4 + b:                                                                    \
     if constexpr (b < R) {                                                                \
-      cx_apply<b, R>(v, w, ((gb >> qc) & 1u) == cv, bm, cv == 1u);                        \
-      cx_frame(za, qc, cv, fz, fc);                                                       \
+      cx_apply<b, R>(v, w, ((gb >> qc) & 1u) != 0u, bm);                                  \
+      cx_frame(za, qc, qa, cv, fx, fz);                                                   \
     }                                                                                     \
     break;
     NT_G1(0)
@@ -393,7 +411,7 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
     // swaps the two phases of a slot group instead of permuting entries.
 #define NT_D(b)                                                                           \
   case OPK_D1R * 4 + b:                                                                   \
-    if constexpr (b < R) diag_bit<b, R>(v, w, xa ? m01 : m00, xa ? m00 : m01);            \
+    if constexpr (b < R) diag_bit<b, R>(v, w, vpin(xa ? m01 : m00), vpin(xa ? m00 : m01));\
     break;                                                                                \
   case OPK_D2A * 4 + b:                                                                   \
     if constexpr (b < R) {                                                                \
@@ -416,16 +434,37 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
     NT_D(3)
 #undef NT_D
     case OPK_D1 * 4: {
-      d1_apply<R>(v, w, xa ? m01 : m00, xa ? m00 : m01, (gb >> qa) & 1u, am);
+      d1_apply<R>(v, w, xa ? m01 : m00, xa ? m00 : m01, (gb >> qa) & 1u);
       break;
     }
     case OPK_D2 * 4: {
-      const uint32_t qb = (uint32_t)op.qb;
-      const uint32_t xm = xa | (((fx >> qb) & 1u) << 1);
+      const uint32_t xm = xa | (((fx >> qc) & 1u) << 1);
       d2_apply<R>(v, w, perm4(op, 0, xm), perm4(op, 1, xm), perm4(op, 2, xm), perm4(op, 3, xm), (gb >> qa) & 1u,
-                  (gb >> qb) & 1u, am, bm);
+                  (gb >> qc) & 1u);
       break;
     }
+    // Both qubits in the registers.  Under the frame the phase of index g is
+    // D(g ^ x): entry i of the list becomes e_i = d[i ^ xm].  The body indexes
+    // by (lower register bit, higher register bit), so when qa holds the
+    // higher bit the two mixed entries trade places.
+#define NT_D2RR(k)                                                                        \
+  case OPK_D2RR * 4 + k:                                                                  \
+    if constexpr (D2RR_PAIRS[k][1] < R) {                                                 \
+      const uint32_t xm = xa | (((fx >> qc) & 1u) << 1);                                  \
+      const cx<T> e0 = perm4(op, 0, xm), e3 = perm4(op, 3, xm);                           \
+      const cx<T> e1 = perm4(op, 1, xm), e2 = perm4(op, 2, xm);                           \
+      const bool hi_a = am > bm;                                                          \
+      diag2<D2RR_PAIRS[k][0], D2RR_PAIRS[k][1], R>(v, w, vpin(e0), vpin(hi_a ? e2 : e1),  \
+                                                   vpin(hi_a ? e1 : e2), vpin(e3));       \
+    }                                                                                     \
+    break;
+    NT_D2RR(0)
+    NT_D2RR(1)
+    NT_D2RR(2)
+    NT_D2RR(3)
+    NT_D2RR(4)
+    NT_D2RR(5)
+#undef NT_D2RR
     default:
 #pragma unroll
       for (int r = 0; r < (1 << R); ++r) w[r] = v[r];

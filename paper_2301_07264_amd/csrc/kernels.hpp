@@ -34,12 +34,16 @@ enum : int32_t {
   OPK_G1X = 2,  // [[c, -i s], [-i s, c]]: m00 = c, m01 = -i s
   OPK_CX = 3,   // controlled X: qa target, qb control
   OPK_D1 = 4,   // diagonal (d0, d1) on qa, qa not a register qubit
-  OPK_D2 = 5,   // diagonal (d0..d3) on local index b_qa + 2 b_qb: both or neither in registers
+  OPK_D2 = 5,   // diagonal (d0..d3) on local index b_qa + 2 b_qb, neither qubit in the registers
   OPK_G2 = 6,   // dense 4x4 (quad segment)
   OPK_D2A = 7,  // diagonal on two qubits, qa in register bit b, qb not
   OPK_D2B = 8,  // diagonal on two qubits, qb in register bit b, qa not
   OPK_D1R = 9,  // diagonal on one qubit, qa in register bit b
+  // Diagonal on two qubits, both in the registers: code OPK_D2RR * 4 + k
+  // for the register-bit pair D2RR_PAIRS[k] (lower bit first), k = 0..5.
+  OPK_D2RR = 10,
 };
+constexpr int D2RR_PAIRS[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
 
 // One register segment: which local bits / global qubits the thread's
 // register slots and thread-id bits map to.
