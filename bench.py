@@ -31,10 +31,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
-# Vector ALU peak the gate kernels can reach: 256 CUs x 4 SIMDs x 16 lanes x
-# 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32 without packed-FP32
-# instructions (kept off on the test machines), and the same for FP64.
-ALU_PEAK_TFLOPS = 78.6
+# Vector ALU peaks (published, MI355X): FP32 157.3 TFLOP/s, FP64 78.6 TFLOP/s
+# (256 CUs x 4 SIMDs x 2.4 GHz; a wave64 FP32 FMA with VGPR operands issues
+# about every 2 cycles per SIMD, an FP64 FMA every 4).  Complex64 amplitudes
+# are FP32 arithmetic, complex128 FP64.
+ALU_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}
 
 # HBM bytes per gate-pass launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (calibrated against a device copy), per workload, valid for the kernel
@@ -245,10 +246,11 @@ def main():
                              f"each gate, {dt:.1f} s wall"}
 
     hbm_frac = achieved / HBM_PEAK_GBS
-    alu_frac = achieved_tf / ALU_PEAK_TFLOPS
+    alu_peak = ALU_PEAK_TFLOPS[args.prec]
+    alu_frac = achieved_tf / alu_peak
     hbm_view = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": hbm_frac, "traffic": traffic}
-    alu_view = {"bound": "alu", "achieved": achieved_tf, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+    alu_view = {"bound": "alu", "achieved": achieved_tf, "peak": alu_peak, "unit": "TFLOP/s",
                 "frac": alu_frac, "traffic": traffic}
     # the binding roofline is the one the kernel is closest to
     roofline = dict(alu_view if alu_frac >= hbm_frac else hbm_view)
@@ -392,8 +394,9 @@ def bench_batch(args, P, W):
     value = updates / (ms / 1e3)
     achieved_tf = pass_flops / (pass_ms / 1e3) / 1e12
     achieved_gbs = pass_bytes / (pass_ms / 1e3) / 1e9
-    alu_view = {"bound": "alu", "achieved": achieved_tf, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved_tf / ALU_PEAK_TFLOPS, "traffic": None}
+    alu_peak = ALU_PEAK_TFLOPS[args.prec]
+    alu_view = {"bound": "alu", "achieved": achieved_tf, "peak": alu_peak, "unit": "TFLOP/s",
+                "frac": achieved_tf / alu_peak, "traffic": None}
     hbm_view = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None}
     roofline = dict(alu_view if alu_view["frac"] >= hbm_view["frac"] else hbm_view)
