@@ -373,33 +373,63 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
   // rsel: register-bit masks of qa (bits 0..3) and qb (bits 4..7) in this
   // op's segment (0 when the qubit is not a register qubit), from the host.
   const uint32_t am = (uint32_t)op.rsel & 15u, bm = ((uint32_t)op.rsel >> 4) & 15u;
-  // dense general 2x2
   const cx<T> m00 = lent(op, 0), m01 = lent(op, 1), m10 = lent(op, 2), m11 = lent(op, 3);
-  cx<T> c00 = xa ? m11 : m00, c01 = xa ? m10 : m01, c10 = xa ? m01 : m10, c11 = xa ? m00 : m11;
-  if (za) {
-    c01 = cneg(c01);
-    c10 = cneg(c10);
-  }
+  // the frame-conjugated dense 2x2 (rows and columns permuted by x_a, the
+  // off-diagonal entries negated by z_a)
+  auto conj = [&](cx<T> &c00, cx<T> &c01, cx<T> &c10, cx<T> &c11) {
+    c00 = xa ? m11 : m00;
+    c01 = xa ? m10 : m01;
+    c10 = xa ? m01 : m10;
+    c11 = xa ? m00 : m11;
+    if (za) {
+      c01 = cneg(c01);
+      c10 = cneg(c10);
+    }
+  };
   // controlled X (control qb)
   const uint32_t qc = (uint32_t)op.qb;
   const uint32_t cv = 1u ^ ((fx >> qc) & 1u);
+  // The two most frequent kinds are tested first, each followed by a
+  // four-way branch on the register bit; everything else goes through one
+  // switch on the full code.
+  const int kind = code >> 2;
+  if (kind == OPK_G1) {
+    cx<T> c00, c01, c10, c11;
+    conj(c00, c01, c10, c11);
+    c00 = vpin(c00);
+    c01 = vpin(c01);
+    c10 = vpin(c10);
+    c11 = vpin(c11);
+    switch (code & 3) {
+      case 0: g1_apply<0, R>(v, w, c00, c01, c10, c11); break;
+      case 1: if constexpr (R > 1) g1_apply<1, R>(v, w, c00, c01, c10, c11); break;
+      case 2: if constexpr (R > 2) g1_apply<2, R>(v, w, c00, c01, c10, c11); break;
+      default: if constexpr (R > 3) g1_apply<3, R>(v, w, c00, c01, c10, c11); break;
+    }
+    return;
+  }
+  if (kind == OPK_CX) {
+    const bool take = ((gb >> qc) & 1u) != 0u;
+    switch (code & 3) {
+      case 0: cx_apply<0, R>(v, w, take, bm); break;
+      case 1: if constexpr (R > 1) cx_apply<1, R>(v, w, take, bm); break;
+      case 2: if constexpr (R > 2) cx_apply<2, R>(v, w, take, bm); break;
+      default: if constexpr (R > 3) cx_apply<3, R>(v, w, take, bm); break;
+    }
+    cx_frame(za, qc, qa, cv, fx, fz);
+    return;
+  }
   switch (code) {
 #define NT_G1(b)                                                                          \
-  case OPK_G1 * 4 + b:                                                                    \
-    if constexpr (b < R) g1_apply<b, R>(v, w, vpin(c00), vpin(c01), vpin(c10), vpin(c11));\
-    break;                                                                                \
   case OPK_G1R * 4 + b:                                                                   \
-    if constexpr (b < R)                                                                  \
+    if constexpr (b < R) {                                                                \
+      cx<T> c00, c01, c10, c11;                                                           \
+      conj(c00, c01, c10, c11);                                                           \
       g1r_apply<b, R>(v, w, vpin(c00.x), vpin(c01.x), vpin(c10.x), vpin(c11.x));          \
+    }                                                                                     \
     break;                                                                                \
   case OPK_G1X * 4 + b:                                                                   \
     if constexpr (b < R) g1x_apply<b, R>(v, w, vpin(m00.x), vpin(za ? -m01.y : m01.y));   \
-    break;                                                                                \
-  case OPK_CX * 4 + b:                                                                    \
-    if constexpr (b < R) {                                                                \
-      cx_apply<b, R>(v, w, ((gb >> qc) & 1u) != 0u, bm);                                  \
-      cx_frame(za, qc, qa, cv, fx, fz);                                                   \
-    }                                                                                     \
     break;
     NT_G1(0)
     NT_G1(1)
