@@ -139,7 +139,9 @@ template <typename T>
 static void upload_ops(DevPlan &dp, const std::vector<int32_t> &code, const std::vector<int32_t> &rsel,
                        hipStream_t s) {
   const Plan &P = dp.plan;
-  std::vector<ntk::DevOp<T>> ops(std::max<size_t>(P.ops.size(), 1));
+  // two zero padding entries: the gate kernel loads the descriptor one past
+  // a segment's last op
+  std::vector<ntk::DevOp<T>> ops(P.ops.size() + 2);
   std::memset(ops.data(), 0, ops.size() * sizeof(ntk::DevOp<T>));
   for (size_t o = 0; o < P.ops.size(); ++o) {
     const HostOp &h = P.ops[o];

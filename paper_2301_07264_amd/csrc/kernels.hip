@@ -298,6 +298,18 @@ DEV OpLite<T> load_lite(const DevOp<T> *ops, int o) {
   return h;
 }
 
+// Descriptor of op o, loaded only after the descriptor `prev` has arrived.
+// Scalar loads complete out of order, so a wait for any of them is a wait for
+// all: tying the index to `prev` through an empty asm makes the wait for the
+// op about to run come before this load is issued, which then has a whole op
+// to arrive.  The opaque index also keeps loop strength reduction from
+// splitting the load into one pointer per field.
+template <typename T>
+DEV OpLite<T> load_lite_after(const DevOp<T> *ops, int o, const OpLite<T> &prev) {
+  asm volatile("" : "+s"(o) : "s"(prev.code));
+  return load_lite(ops, o);
+}
+
 template <typename T>
 DEV cx<T> lent(const OpLite<T> &h, int i) {
   return cx<T>{h.m[2 * i], h.m[2 * i + 1]};
@@ -377,13 +389,25 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
   // the frame-conjugated dense 2x2 (rows and columns permuted by x_a, the
   // off-diagonal entries negated by z_a)
   auto conj = [&](cx<T> &c00, cx<T> &c01, cx<T> &c10, cx<T> &c11) {
-    c00 = xa ? m11 : m00;
-    c01 = xa ? m10 : m01;
-    c10 = xa ? m01 : m10;
-    c11 = xa ? m00 : m11;
-    if (za) {
-      c01 = cneg(c01);
-      c10 = cneg(c10);
+    if constexpr (sizeof(T) == 4) {
+      // complex64 entries as 64-bit words: one scalar select per entry, one
+      // XOR of both sign bits per negated entry
+      auto u = [](cx<T> c) { return __builtin_bit_cast(uint64_t, c); };
+      auto f = [](uint64_t x) { return __builtin_bit_cast(cx<T>, x); };
+      const uint64_t sgn = za ? 0x8000000080000000ull : 0ull;
+      c00 = f(xa ? u(m11) : u(m00));
+      c01 = f((xa ? u(m10) : u(m01)) ^ sgn);
+      c10 = f((xa ? u(m01) : u(m10)) ^ sgn);
+      c11 = f(xa ? u(m00) : u(m11));
+    } else {
+      c00 = xa ? m11 : m00;
+      c01 = xa ? m10 : m01;
+      c10 = xa ? m01 : m10;
+      c11 = xa ? m00 : m11;
+      if (za) {
+        c01 = cneg(c01);
+        c10 = cneg(c10);
+      }
     }
   };
   // controlled X (control qb)
@@ -724,25 +748,29 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     cx<T> v[NS], w[NS];
 #pragma unroll
     for (int r = 0; r < NS; ++r) v[r] = slot(r);
+    // Descriptors are double-buffered: a_op holds the op at an even offset,
+    // b_op the one after it; each is loaded while the other's op runs.  The
+    // op table carries padding entries after its last op, so the loads one
+    // past a segment's end stay inside it.
     int o = sg.op_begin;
-    if (o < sg.op_end) {
-      OpLite<T> cur = load_lite(ops, o);
-      for (; o < sg.op_end; o += 2) {
-        OpLite<T> nxt = cur;
-        if (o + 1 < sg.op_end) nxt = load_lite(ops, o + 1);   // next op's loads in flight
-        apply_reg_op<R, T>(cur, v, w, gb, fx, fz, fc);
+    const int oe = sg.op_end;
+    if (o < oe) {
+      OpLite<T> a_op = load_lite(ops, o), b_op;
+      for (;;) {
+        b_op = load_lite_after(ops, o + 1, a_op);
+        apply_reg_op<R, T>(a_op, v, w, gb, fx, fz, fc);
         take_events(o);
-        if (o + 1 < sg.op_end) {
-          cur = nxt;
-          if (o + 2 < sg.op_end) nxt = load_lite(ops, o + 2);
-          apply_reg_op<R, T>(cur, w, v, gb, fx, fz, fc);
-          take_events(o + 1);
-          cur = nxt;
-        } else {
+        if (o + 1 >= oe) {
           // odd op count: the last result is in w
 #pragma unroll
           for (int r = 0; r < NS; ++r) v[r] = w[r];
+          break;
         }
+        a_op = load_lite_after(ops, o + 2, b_op);
+        apply_reg_op<R, T>(b_op, w, v, gb, fx, fz, fc);
+        take_events(o + 1);
+        o += 2;
+        if (o >= oe) break;
       }
     }
 #pragma unroll
