@@ -520,9 +520,10 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
     NT_D2RR(5)
 #undef NT_D2RR
     default:
-#pragma unroll
-      for (int r = 0; r < (1 << R); ++r) w[r] = v[r];
-      break;
+      // the host only emits the codes above (it rejects anything else when
+      // it builds the plan); no identity copy here, which the compiler would
+      // otherwise hoist into the shared branches of the dispatch tree
+      __builtin_unreachable();
   }
 }
 
@@ -756,21 +757,19 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     const int oe = sg.op_end;
     if (o < oe) {
       OpLite<T> a_op = load_lite(ops, o), b_op;
-      for (;;) {
+      for (; o < oe; o += 2) {
         b_op = load_lite_after(ops, o + 1, a_op);
         apply_reg_op<R, T>(a_op, v, w, gb, fx, fz, fc);
         take_events(o);
-        if (o + 1 >= oe) {
+        if (o + 1 < oe) {
+          a_op = load_lite_after(ops, o + 2, b_op);
+          apply_reg_op<R, T>(b_op, w, v, gb, fx, fz, fc);
+          take_events(o + 1);
+        } else {
           // odd op count: the last result is in w
 #pragma unroll
           for (int r = 0; r < NS; ++r) v[r] = w[r];
-          break;
         }
-        a_op = load_lite_after(ops, o + 2, b_op);
-        apply_reg_op<R, T>(b_op, w, v, gb, fx, fz, fc);
-        take_events(o + 1);
-        o += 2;
-        if (o >= oe) break;
       }
     }
 #pragma unroll
