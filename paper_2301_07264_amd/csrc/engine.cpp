@@ -216,6 +216,7 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
     for (int q = 0; q < P.cfix; ++q)
       if (loc[q] != q) throw Error(NT_ERR_UNSUPPORTED, "internal: low qubits not local");
     for (size_t i = 0; i < loc.size(); ++i) dpass[p].locq[i] = (uint8_t)loc[i];
+    for (int bb = 0; bb < P.R && P.L - P.R + bb < (int)loc.size(); ++bb) dpass[p].hq[bb] = (uint8_t)loc[P.L - P.R + bb];
     for (size_t i = 0; i < nl.size(); ++i) dpass[p].nlq[i] = (uint8_t)nl[i];
     for (int s = ps.seg_begin; s < ps.seg_end; ++s) {
       const Segment &sg = P.segs[s];

@@ -179,6 +179,33 @@ DEV uint32_t swz(uint32_t j) {
   return j ^ ((j >> SW) & M) ^ ((j >> (2 * SW)) & M) ^ ((j >> (3 * SW)) & M) ^ ((j >> (4 * SW)) & M);
 }
 
+// A uniform table read as dwords with wide scalar loads (scalar loads have
+// no byte form: a byte field read directly becomes a vector load whose
+// latency every use then waits for), and byte i of it.
+template <typename S, int NW>
+DEV void cwords(const S *p, uint32_t (&w)[NW]) {
+  static_assert(sizeof(S) == 4 * NW, "whole table");
+  const NT_CONST uint32_t *q = reinterpret_cast<const NT_CONST uint32_t *>(cptr(p));
+#pragma unroll
+  for (int i = 0; i < NW; ++i) w[i] = q[i];
+}
+template <int NW>
+DEV uint32_t wbyte(const uint32_t (&w)[NW], int i) {
+  return (w[i >> 2] >> (8 * (i & 3))) & 0xffu;
+}
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
+
+// out[k] = XOR of base[b] over the set bits b of k, one XOR per entry
+// (each entry extends the one with k's lowest set bit cleared).  Used for the
+// uniform address terms of a thread's 2^R register slots: the global index
+// bits and the swizzled LDS offsets are both linear over GF(2) in k.
+template <int N>
+DEV void xor_span(const uint32_t (&base)[N], uint32_t (&out)[1 << N]) {
+  out[0] = 0u;
+#pragma unroll
+  for (int k = 1; k < (1 << N); ++k) out[k] = out[k & (k - 1)] ^ base[__builtin_ctz((unsigned)k)];
+}
+
 // Pauli frame update F <- P_q F for F = i^c X^x Z^z (P = X: x ^= q;
 // P = Z: c += 2 x_q, z ^= q; P = Y = iXZ: c += 1 + 2 x_q, x ^= q, z ^= q).
 // Written without branches so the frame stays in scalar registers.
@@ -636,48 +663,60 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     heavy_med = m.heavy_med;
   }
 
-  const NT_CONST DevPass &ps = *cptr(passp);
+  // Pass layout as dwords.  Thread-id bits at and above lt = L - R are zero
+  // (NT = 2^lt <= MAXT), and so are tile-id bits at and above ntile_bits;
+  // unused entries of the tables are zero, so the loops below run to
+  // compile-time bounds (tile bits in groups of four, the rest skipped).
+  constexpr int LTMAX = ilog2c(MAXT);
+  uint32_t pw[13];
+  cwords(passp, pw);
   uint32_t tilebase = 0;
-  for (int i = 0; i < a.ntile_bits; ++i) tilebase |= ((tile >> i) & 1u) << ps.nlq[i];
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    if (4 * g >= a.ntile_bits) break;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) tilebase |= ((tile >> (4 * g + u)) & 1u) << wbyte(pw, 16 + 4 * g + u);
+  }
   cx<T> *st = a.state + (uint64_t)b * a.state_stride;
-  const int lt = a.L - R;
   uint32_t dlo = 0;
-  for (int i = 0; i < lt; ++i) dlo |= ((tid >> i) & 1u) << ps.locq[i];
-  // Global-index bits of the coalesced layout's slot k: OR of hbit[b] over
-  // the set bits b of k (uniform).
-  uint32_t hbit[R];
 #pragma unroll
-  for (int bb = 0; bb < R; ++bb) hbit[bb] = 1u << ps.locq[lt + bb];
-  auto dhi = [&](int k) {
-    uint32_t v = 0;
+  for (int i = 0; i < LTMAX; ++i) dlo |= ((tid >> i) & 1u) << wbyte(pw, i);
+  // Coalesced layout: slot k of thread tid holds tile index tid + k * NT.
+  // Its global-index bits are tilebase | dlo | dk[k], dk[k] the XOR of
+  // hbit[b] over the set bits b of k; the swizzle is linear over GF(2), so its
+  // LDS byte offset is swz(tid) ^ lk[k] with lk[k] the XOR of swz(NT << b).
+  // Both tables are uniform; they are rebuilt where needed instead of being
+  // kept live across the segment loop.
+  uint32_t hbit[R], lbit[R];
 #pragma unroll
-    for (int bb = 0; bb < R; ++bb)
-      if ((k >> bb) & 1) v |= hbit[bb];
-    return v;
-  };
-  // The swizzle is linear over GF(2), so the LDS byte offset of coalesced
-  // slot k is swz(tid) ^ swz(k * NT), the second term uniform.
+  for (int bb = 0; bb < R; ++bb) {
+    hbit[bb] = 1u << wbyte(pw, 48 + bb);
+    lbit[bb] = swz<T>(NT << bb) * (uint32_t)sizeof(cx<T>);
+  }
   const uint32_t lds_tid = swz<T>(tid) * (uint32_t)sizeof(cx<T>);
-  auto lds_k = [&](int k) -> cx<T> & {
-    return *reinterpret_cast<cx<T> *>(smem_raw + (lds_tid ^ (swz<T>((uint32_t)k * NT) * (uint32_t)sizeof(cx<T>))));
-  };
-  const cx<T> *sp = st + (tilebase | dlo);   // dhi(k) bits are disjoint from tilebase | dlo
+  const cx<T> *sp = st + (tilebase | dlo);   // the dk bits are disjoint from tilebase | dlo
 
   // Load the tile (coalesced: thread-id bits are the low local bits).
   const int my_start = a.start ? cptr(a.start)[b] : 0;
-  if (my_start == a.pass_index && a.pass_index == 0) {
+  {
+    uint32_t dk[NS], lk[NS];
+    xor_span(hbit, dk);
+    xor_span(lbit, lk);
+    auto lds_k = [&](int k) -> cx<T> & { return *reinterpret_cast<cx<T> *>(smem_raw + (lds_tid ^ lk[k])); };
+    if (my_start == a.pass_index && a.pass_index == 0) {
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const uint32_t g = tilebase | dlo | dhi(k);
-      lds_k(k) = cx<T>{g == a.init_index ? T(1) : T(0), T(0)};
+      for (int k = 0; k < NS; ++k) {
+        const uint32_t g = tilebase | dlo | dk[k];
+        lds_k(k) = cx<T>{g == a.init_index ? T(1) : T(0), T(0)};
+      }
+    } else {
+      const cx<T> *src = (my_start == a.pass_index) ? a.ckpt + (tilebase | dlo) : sp;
+      cx<T> v[NS];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) v[k] = src[dk[k]];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) lds_k(k) = v[k];
     }
-  } else {
-    const cx<T> *src = (my_start == a.pass_index) ? a.ckpt + (tilebase | dlo) : sp;
-    cx<T> v[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) v[k] = src[dhi(k)];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) lds_k(k) = v[k];
   }
   __syncthreads();
 
@@ -718,32 +757,33 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   };
 
   for (int s = seg_begin; s < seg_end; ++s) {
-    const NT_CONST DevSeg &sg = cptr(segs)[s];
-    if (sg.kind == SEG_KIND_QUAD) {
-      apply_quad_lds<T>(cptr(ops)[sg.op_begin], lds, a.L, fx, fz);
-      take_events(sg.op_begin);
+    // segment table as dwords: kind, op_begin, op_end, then the byte arrays
+    // rpos (byte 12), rq (16), tpos (20), tq (36)
+    uint32_t sw[13];
+    cwords(segs + s, sw);
+    const int sg_kind = (int)sw[0], sg_op_begin = (int)sw[1], sg_op_end = (int)sw[2];
+    if (sg_kind == SEG_KIND_QUAD) {
+      apply_quad_lds<T>(cptr(ops)[sg_op_begin], lds, a.L, fx, fz);
+      take_events(sg_op_begin);
       __syncthreads();
       continue;
     }
     uint32_t jb = 0, gb = tilebase;
-    for (int i = 0; i < lt; ++i) {
+#pragma unroll
+    for (int i = 0; i < LTMAX; ++i) {
       const uint32_t bit = (tid >> i) & 1u;
-      jb |= bit << sg.tpos[i];
-      gb |= bit << sg.tq[i];
+      jb |= bit << wbyte(sw, 20 + i);
+      gb |= bit << wbyte(sw, 36 + i);
     }
     // LDS byte offset of slot r: swz(jb) ^ XOR of swz(bit of register b) over
     // the set bits b of r (linear swizzle; the second term is uniform).
     uint32_t sbit[R];
 #pragma unroll
-    for (int bb = 0; bb < R; ++bb) sbit[bb] = swz<T>(1u << sg.rpos[bb]) * (uint32_t)sizeof(cx<T>);
+    for (int bb = 0; bb < R; ++bb) sbit[bb] = swz<T>(1u << wbyte(sw, 12 + bb)) * (uint32_t)sizeof(cx<T>);
     const uint32_t sjb = swz<T>(jb) * (uint32_t)sizeof(cx<T>);
-    auto slot = [&](int r) -> cx<T> & {
-      uint32_t u = 0;
-#pragma unroll
-      for (int bb = 0; bb < R; ++bb)
-        if ((r >> bb) & 1) u ^= sbit[bb];
-      return *reinterpret_cast<cx<T> *>(smem_raw + (sjb ^ u));
-    };
+    uint32_t us[NS];
+    xor_span(sbit, us);
+    auto slot = [&](int r) -> cx<T> & { return *reinterpret_cast<cx<T> *>(smem_raw + (sjb ^ us[r])); };
     // Two register banks, ops alternating between them (v -> w -> v), so no
     // op has to copy its results back into the registers it read.
     cx<T> v[NS], w[NS];
@@ -753,8 +793,8 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     // b_op the one after it; each is loaded while the other's op runs.  The
     // op table carries padding entries after its last op, so the loads one
     // past a segment's end stay inside it.
-    int o = sg.op_begin;
-    const int oe = sg.op_end;
+    int o = sg_op_begin;
+    const int oe = sg_op_end;
     if (o < oe) {
       OpLite<T> a_op = load_lite(ops, o), b_op;
       for (; o < oe; o += 2) {
@@ -780,6 +820,10 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   // The epilogue recomputes its addresses instead of keeping 2^R of them
   // live across the segment loop.
   asm volatile("" : "+v"(dlo));
+  uint32_t dk[NS], lk[NS];
+  xor_span(hbit, dk);
+  xor_span(lbit, lk);
+  auto lds_k = [&](int k) -> cx<T> & { return *reinterpret_cast<cx<T> *>(smem_raw + (lds_tid ^ lk[k])); };
   const size_t ntiles = (size_t)1 << a.ntile_bits;
   if (score_here) {
     double ovr = 0.0, ovi = 0.0, nrm = 0.0, mass = 0.0;
@@ -787,7 +831,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     const bool want_t = a.crit == CRIT_TARGET, want_h = a.crit == CRIT_HEAVY;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      const uint32_t g = tilebase | dlo | dhi(k);
+      const uint32_t g = tilebase | dlo | dk[k];
       const cx<T> s = lds_k(k);
       const cx<T> r = refp[g ^ fx];
       double sr = (double)s.x, si = (double)s.y;
@@ -810,7 +854,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     double nrm = 0.0;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      const uint32_t g = tilebase | dlo | dhi(k);
+      const uint32_t g = tilebase | dlo | dk[k];
       const cx<T> s = lds_k(k);
       st[g] = s;
       const double sr = (double)s.x, si = (double)s.y;

@@ -64,7 +64,9 @@ struct DevSeg {
 struct DevPass {
   uint8_t locq[16];        // global qubit of tile-local bit i (ascending)
   uint8_t nlq[32];         // global qubit of tile-id bit i (ascending)
+  uint8_t hq[4];           // locq[L - R + b]: qubit of the coalesced layout's register bit b
 };
+static_assert(sizeof(DevPass) == 52 && sizeof(DevSeg) == 52, "tables are read as 13 dwords");
 
 // Components of a per-tile scoring partial: overlap re, overlap im, norm of
 // the trajectory's state, criterion mass (probability of the target basis
