@@ -621,12 +621,20 @@ DEV void block_reduce(double (&v)[NPART], double *out, unsigned char *smem) {
 }
 
 // MAXT: largest work-group this instantiation serves; WPE: waves per SIMD
-// it must fit (bounds the register budget so two work-groups share a CU).
-template <typename T, int R, int MAXT, int WPE>
+// it must fit (bounds the register budget so two work-groups share a CU);
+// SLDS: the work-group is exactly MAXT threads and its tile is static LDS.
+template <typename T, int R, int MAXT, int WPE, bool SLDS>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))) k_pass(const PassArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
   constexpr int NS = 1 << R;
+  // SLDS: the tile of exactly MAXT threads (MAXT * 2^R amplitudes) as a
+  // static array, whose LDS address is known when the kernel is compiled, so
+  // slot addresses need no base added; 0: the tile in dynamic LDS sized at
+  // launch (kernels whose work-groups vary in size).
+  constexpr size_t SLDS_BYTES = SLDS ? (size_t)MAXT * NS * sizeof(cx<T>) : 16;
+  __shared__ __align__(16) unsigned char smem_static[SLDS_BYTES];
+  extern __shared__ __align__(16) unsigned char smem_dyn[];
+  unsigned char *const smem_raw = SLDS ? smem_static : smem_dyn;
+  cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
   const uint32_t NT = blockDim.x;
   const uint32_t tid = threadIdx.x;
   const int b = (int)(blockIdx.x % (uint32_t)a.B);
@@ -880,16 +888,31 @@ hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, hipStream_t s)
   if (lds < 16 * NPART * sizeof(double)) lds = 16 * NPART * sizeof(double);
   if (blocks == 0) return hipSuccess;
   if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
-  // R = 4 work-groups are 2^(L-4) threads: 512 for complex64 (L = 13),
-  // 256 for complex128 (L = 12); two of them share a CU's LDS.
+  // R = 4 work-groups are 2^(L-4) threads: 512 or 256 for complex64
+  // (L = 13 or 12), 256 for complex128 (L = 12).  The two complex64 sizes
+  // have kernels with the tile in static LDS (measured faster); everything
+  // else uses dynamic LDS (for complex128 the static form measured slower).
   constexpr int MAXT4 = sizeof(T) == 4 ? 512 : 256;
   constexpr int WPE4 = sizeof(T) == 4 ? 4 : 2;
   if (nthreads > (R == 4 ? MAXT4 : 1024)) return hipErrorInvalidValue;
+  const dim3 grid((uint32_t)blocks), blk(nthreads);
   switch (R) {
-    case 1: hipLaunchKernelGGL((k_pass<T, 1, 1024, 1>), dim3((uint32_t)blocks), dim3(nthreads), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pass<T, 2, 1024, 1>), dim3((uint32_t)blocks), dim3(nthreads), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((k_pass<T, 3, 1024, 1>), dim3((uint32_t)blocks), dim3(nthreads), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_pass<T, 4, MAXT4, WPE4>), dim3((uint32_t)blocks), dim3(nthreads), lds, s, a); break;
+    case 1: hipLaunchKernelGGL((k_pass<T, 1, 1024, 1, false>), grid, blk, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pass<T, 2, 1024, 1, false>), grid, blk, lds, s, a); break;
+    case 3: hipLaunchKernelGGL((k_pass<T, 3, 1024, 1, false>), grid, blk, lds, s, a); break;
+    case 4:
+      if constexpr (sizeof(T) == 4) {
+        if (nthreads == 512 && a.L == 13) {
+          hipLaunchKernelGGL((k_pass<T, 4, 512, WPE4, true>), grid, blk, 0, s, a);
+          break;
+        }
+        if (nthreads == 256 && a.L == 12) {
+          hipLaunchKernelGGL((k_pass<T, 4, 256, WPE4, true>), grid, blk, 0, s, a);
+          break;
+        }
+      }
+      hipLaunchKernelGGL((k_pass<T, 4, MAXT4, WPE4, false>), grid, blk, lds, s, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
