@@ -42,14 +42,14 @@ ALU_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}
 # source they were taken on (profiles/hbm_traffic_*.md).
 MEASURED_TRAFFIC = {
     ("ghz_qft_layers24", "c64", 32): {
-        "bytes_per_launch": 8.418e9,
+        "bytes_per_launch": 8.416e9,
         "passes": 43,
-        "kernel_sha256": "d06523af38e650aa45e015cac6b7301791867b0a36d30ffc3f211bb856c40576",
+        "kernel_sha256": "231a97df2b312ced1e7d671b8eefd0eddcb8569b4a6ea3a5ba4269580f04dc7c",
     },
     ("qaoa3reg30", "c64", 4): {
         "bytes_per_launch": 6.560e10,
         "passes": 11,
-        "kernel_sha256": "d06523af38e650aa45e015cac6b7301791867b0a36d30ffc3f211bb856c40576",
+        "kernel_sha256": "231a97df2b312ced1e7d671b8eefd0eddcb8569b4a6ea3a5ba4269580f04dc7c",
     },
 }
 
