@@ -92,6 +92,17 @@ void Ctx::sync() { check_hip(hipStreamSynchronize(stream), "hipStreamSynchronize
 
 static size_t amp_bytes(int prec) { return prec == NT_C64 ? 8 : 16; }
 
+// LDS address swizzle of the gate kernels (complex64: SW = 4, complex128:
+// SW = 3): the low SW bits of a tile index are XORed with every higher SW-bit
+// chunk.  The kernels apply the same map to the thread part of a slot's index;
+// the register part is precomputed here per segment.
+static uint32_t lds_swizzle(uint32_t j, int SW) {
+  const uint32_t M = (1u << SW) - 1u;
+  uint32_t r = j;
+  for (int c = SW; c < 32; c += SW) r ^= (j >> c) & M;
+  return r;
+}
+
 // Order of a segment's thread-id bits: lanes 0..2^SW-1 take local positions
 // with distinct residues mod SW (conflict-free under the LDS swizzle), the
 // rest follow in ascending order.
@@ -277,6 +288,15 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
       for (size_t i = 0; i < tpos.size(); ++i) {
         d.tpos[i] = (uint8_t)tpos[i];
         d.tq[i] = (uint8_t)loc[tpos[i]];
+        d.tpos_w[i] = (uint32_t)tpos[i];
+        d.tq_w[i] = (uint32_t)loc[tpos[i]];
+      }
+      const uint32_t amp_bytes = pr == NT_C64 ? 8u : 16u;
+      for (int r = 0; r < (1 << R); ++r) {
+        uint32_t off = 0;
+        for (int b = 0; b < R; ++b)
+          if ((r >> b) & 1) off ^= lds_swizzle(1u << d.rpos[b], SW) * amp_bytes;
+        d.slot_off[r] = off;
       }
     }
   }

@@ -765,11 +765,10 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   };
 
   for (int s = seg_begin; s < seg_end; ++s) {
-    // segment table as dwords: kind, op_begin, op_end, then the byte arrays
-    // rpos (byte 12), rq (16), tpos (20), tq (36)
-    uint32_t sw[13];
-    cwords(segs + s, sw);
-    const int sg_kind = (int)sw[0], sg_op_begin = (int)sw[1], sg_op_end = (int)sw[2];
+    // segment table: scalar loads of whole dwords only (header, the widened
+    // thread-bit tables, the precomputed slot offsets)
+    const NT_CONST DevSeg &sg = cptr(segs)[s];
+    const int sg_kind = sg.kind, sg_op_begin = sg.op_begin, sg_op_end = sg.op_end;
     if (sg_kind == SEG_KIND_QUAD) {
       apply_quad_lds<T>(cptr(ops)[sg_op_begin], lds, a.L, fx, fz);
       take_events(sg_op_begin);
@@ -780,18 +779,13 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
 #pragma unroll
     for (int i = 0; i < LTMAX; ++i) {
       const uint32_t bit = (tid >> i) & 1u;
-      jb |= bit << wbyte(sw, 20 + i);
-      gb |= bit << wbyte(sw, 36 + i);
+      jb |= bit << sg.tpos_w[i];
+      gb |= bit << sg.tq_w[i];
     }
-    // LDS byte offset of slot r: swz(jb) ^ XOR of swz(bit of register b) over
-    // the set bits b of r (linear swizzle; the second term is uniform).
-    uint32_t sbit[R];
-#pragma unroll
-    for (int bb = 0; bb < R; ++bb) sbit[bb] = swz<T>(1u << wbyte(sw, 12 + bb)) * (uint32_t)sizeof(cx<T>);
+    // LDS byte offset of slot r: swz(jb) ^ slot_off[r] (the swizzle is linear
+    // over GF(2); the register part is uniform and comes from the host).
     const uint32_t sjb = swz<T>(jb) * (uint32_t)sizeof(cx<T>);
-    uint32_t us[NS];
-    xor_span(sbit, us);
-    auto slot = [&](int r) -> cx<T> & { return *reinterpret_cast<cx<T> *>(smem_raw + (sjb ^ us[r])); };
+    auto slot = [&](int r) -> cx<T> & { return *reinterpret_cast<cx<T> *>(smem_raw + (sjb ^ sg.slot_off[r])); };
     // Two register banks, ops alternating between them (v -> w -> v), so no
     // op has to copy its results back into the registers it read.
     cx<T> v[NS], w[NS];

@@ -58,6 +58,13 @@ struct DevSeg {
   uint8_t rq[4];     // global qubit of register bit b
   uint8_t tpos[16];  // local bit position of thread-id bit i
   uint8_t tq[16];    // global qubit of thread-id bit i
+  // Read by the gate kernel with scalar loads, precomputed on the host so a
+  // segment change costs no scalar arithmetic: the swizzled LDS byte offset
+  // term of register slot r (XOR of the swizzled offsets of the register
+  // bits set in r), and tpos / tq widened to one dword each.
+  uint32_t slot_off[16];
+  uint32_t tpos_w[16];
+  uint32_t tq_w[16];
 };
 
 // Tile layout of one pass.
@@ -66,7 +73,7 @@ struct DevPass {
   uint8_t nlq[32];         // global qubit of tile-id bit i (ascending)
   uint8_t hq[4];           // locq[L - R + b]: qubit of the coalesced layout's register bit b
 };
-static_assert(sizeof(DevPass) == 52 && sizeof(DevSeg) == 52, "tables are read as 13 dwords");
+static_assert(sizeof(DevPass) == 52, "the pass table is read as 13 dwords");
 
 // Components of a per-tile scoring partial: overlap re, overlap im, norm of
 // the trajectory's state, criterion mass (probability of the target basis
