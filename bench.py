@@ -44,12 +44,12 @@ MEASURED_TRAFFIC = {
     ("ghz_qft_layers24", "c64", 32): {
         "bytes_per_launch": 8.416e9,
         "passes": 43,
-        "kernel_sha256": "231a97df2b312ced1e7d671b8eefd0eddcb8569b4a6ea3a5ba4269580f04dc7c",
+        "kernel_sha256": "543a68c3ab2e5e2d15fec5df1d0f2a33084c07da5f08a2a8490f4fa2d7b46295",
     },
     ("qaoa3reg30", "c64", 4): {
         "bytes_per_launch": 6.560e10,
         "passes": 11,
-        "kernel_sha256": "231a97df2b312ced1e7d671b8eefd0eddcb8569b4a6ea3a5ba4269580f04dc7c",
+        "kernel_sha256": "543a68c3ab2e5e2d15fec5df1d0f2a33084c07da5f08a2a8490f4fa2d7b46295",
     },
 }
 
