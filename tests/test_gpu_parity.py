@@ -208,6 +208,60 @@ def test_uneven_error_models_states(P, ctx, orc):
 
 
 # ---------------------------------------------------------------------------
+# Register-heavy circuits: many CNOTs and two-qubit diagonals between random
+# pairs, so that the register-permutation CNOT (every target / control
+# register-bit pair), the per-lane CNOT, and the diagonal bodies with one or
+# both qubits in the registers all run, under error models that flip the
+# control value through the frame (X and Y errors) as well as its sign (Z).
+
+def _register_heavy_circuit(n, layers, seed):
+    rng = np.random.default_rng(seed)
+    gates = []
+    for _ in range(layers):
+        for q in range(n):
+            nm = ["U", "H", "RX", "RZ", "RY"][int(rng.integers(5))]
+            if nm == "U":
+                gates.append(W.Gate(nm, (q,), tuple(float(x) for x in rng.uniform(0, 2 * math.pi, 3))))
+            elif nm == "H":
+                gates.append(W.Gate(nm, (q,)))
+            else:
+                gates.append(W.Gate(nm, (q,), (float(rng.uniform(0, 2 * math.pi)),)))
+        for _ in range(2 * n):
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            nm = ["CNOT", "CNOT", "CZ", "CP", "RZZ"][int(rng.integers(5))]
+            if nm in ("CP", "RZZ"):
+                gates.append(W.Gate(nm, (a, b), (float(rng.uniform(0, 2 * math.pi)),)))
+            else:
+                gates.append(W.Gate(nm, (a, b)))
+    return W.Circuit(n, gates, f"regheavy{n}")
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("n,layers", [(6, 4), (11, 3), (16, 2)])
+def test_register_heavy_states(P, ctx, orc, prec, n, layers):
+    c = _register_heavy_circuit(n, layers, 300 + n)
+    h = _load(P, c, cid=9)
+    pr = P.NT_C128 if prec == "c128" else P.NT_C64
+    tol = 1e-12 if prec == "c128" else 1e-5
+    ftol = 1e-12 if prec == "c128" else 2e-5
+    P.nt_set_precision(ctx, pr)
+    npass, nseg, L = P.nt_plan_info(h, pr)
+    _say(f"register-heavy n={n} G={c.G} prec={prec} passes={npass} segments={nseg} L={L}")
+    for model in [(0.0, 0.0, 0.0), (0.2, 0.0, 0.0), (0.0, 0.1, 0.1), (0.1, 0.1, 0.1)]:
+        P.nt_set_error_model(ctx, *model)
+        for t in range(3):
+            g = P.nt_final_state(ctx, h, 21, t, pr)
+            o = orc.final_state(c, *model, 21, t, cid=9)
+            assert _l2(g, o) <= tol, (model, t, _l2(g, o))
+        N = 32
+        fid = np.zeros(N)
+        P.nt_run(ctx, h, 21, 0, N, TAU, fid)
+        f_o, _ = orc.run(c, *model, 21, 0, N, TAU, cid=9)
+        assert np.abs(fid - f_o).max() <= ftol, (model, np.abs(fid - f_o).max())
+    P.nt_circuit_free(h)
+
+
+# ---------------------------------------------------------------------------
 # Closed forms on the GPU path.
 
 @pytest.mark.parametrize("n", [5, 14, 17])
