@@ -254,8 +254,19 @@ nt_status nt_tolerable_rate(nt_ctx *ctx, const nt_circuit *c, double P_target, d
  *   rest of the circuit is one unitary applied to both states and leaves
  *   their overlap unchanged.  Exact in arithmetic; fidelities differ from
  *   the full run by rounding only (needs the checkpoints).
+ * NT_SHORTCUT_REUSE -- a trajectory's criterion value is kept after it is
+ *   simulated and reused by later runs of the same circuit, seed, precision,
+ *   criterion and short-cut flags whose error model has the same Pauli-type
+ *   proportions (p_x : p_y : p_z) -- e.g. the probes of nt_tolerable_rate or
+ *   nt_sweep with the uniform model.  Rates are not part of the random draws
+ *   (Sec. IV-B.2 sampling, common random numbers), so a trajectory's fired
+ *   sets at any two rates are nested, and two rates with the same number of
+ *   fired sites give it the same errors: (trajectory, count) identifies its
+ *   value, which is reused bit for bit.  The store is emptied by every
+ *   nt_set_shortcuts call, when any of the above changes, and when it
+ *   exceeds 2^24 values.
  * Default 0 (every trajectory simulated in full). */
-enum { NT_SHORTCUT_ZERO_FIRED = 1, NT_SHORTCUT_CHECKPOINT = 2, NT_SHORTCUT_LAST_ERROR = 4 };
+enum { NT_SHORTCUT_ZERO_FIRED = 1, NT_SHORTCUT_CHECKPOINT = 2, NT_SHORTCUT_LAST_ERROR = 4, NT_SHORTCUT_REUSE = 8 };
 nt_status nt_set_shortcuts(nt_ctx *ctx, int flags);
 
 /* ---- exhaustive single-error branch (Sec. IV-B.1, IV-C, IV-D) ---------------- */

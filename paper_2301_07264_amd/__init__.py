@@ -60,6 +60,7 @@ NT_CRIT_HEAVY = 2
 NT_SHORTCUT_ZERO_FIRED = 1
 NT_SHORTCUT_CHECKPOINT = 2
 NT_SHORTCUT_LAST_ERROR = 4
+NT_SHORTCUT_REUSE = 8
 
 
 class nt_gate(C.Structure):

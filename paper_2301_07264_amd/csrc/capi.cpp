@@ -360,9 +360,13 @@ nt_status nt_tolerable_rate(nt_ctx *ctx, const nt_circuit *c, double P_target, d
 
 nt_status nt_set_shortcuts(nt_ctx *ctx, int flags) {
   if (!ctx) return fail(NT_ERR_INVALID_ARG, "ctx is NULL");
-  if (flags & ~(NT_SHORTCUT_ZERO_FIRED | NT_SHORTCUT_CHECKPOINT | NT_SHORTCUT_LAST_ERROR))
+  if (flags & ~(NT_SHORTCUT_ZERO_FIRED | NT_SHORTCUT_CHECKPOINT | NT_SHORTCUT_LAST_ERROR | NT_SHORTCUT_REUSE))
     return fail(NT_ERR_INVALID_ARG, "unknown shortcut flag");
   ctx->impl->shortcuts = flags;
+  // every call empties the reuse store
+  ctx->impl->reuse.clear();
+  ctx->impl->reuse_values = 0;
+  ctx->impl->reuse_valid = false;
   g_last_error.clear();
   return NT_OK;
 }

@@ -802,6 +802,27 @@ void Ctx::run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n,
   const int S = (int)std::max<int64_t>(c.S, 1);
   const int np = (int)dp.plan.passes.size();
   std::vector<double> fh(n, 0.0);
+  const bool reuse_on = (shortcuts & SC_REUSE) != 0;
+  if (reuse_on) {
+    ReuseKey k;
+    k.serial = c.serial;
+    k.cid = c.cid;
+    k.tile = c.tile_override[dp.prec == NT_C64 ? 1 : 2];
+    k.seed = seed;
+    k.target = target;
+    k.c_x = th.c_x;
+    k.c_xy = th.c_xy;
+    k.always_types = th.always & 6u;
+    k.prec = dp.prec;
+    k.crit = crit;
+    k.flags = shortcuts & ~SC_REUSE;
+    if (!reuse_valid || !(k == reuse_key) || reuse_values > ((size_t)1 << 24)) {
+      reuse.clear();
+      reuse_values = 0;
+    }
+    reuse_key = k;
+    reuse_valid = true;
+  }
   const uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(n, (256u << 20) / ((uint64_t)S * 4)));
   const uint64_t bs = batch_size(c, dp, n);
   std::vector<int32_t> hcnt;
@@ -836,6 +857,19 @@ void Ctx::run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n,
         fh[off + b] = v_ref;
         continue;
       }
+      if (reuse_on) {
+        // same count at the same Pauli-type proportions: the same fired set
+        auto it = reuse.find(t0 + off + (uint64_t)b);
+        bool hit = false;
+        if (it != reuse.end())
+          for (const auto &e : it->second)
+            if (e.first == hcnt[b]) {
+              fh[off + b] = e.second;
+              hit = true;
+              break;
+            }
+        if (hit) continue;
+      }
       int32_t sp = 0, ep = np - 1;
       if (have_ckpt) sp = hcnt[b] ? dp.pass_of_op[hfirst[2 * b] >> 8] : np - 1;
       if (early_end) ep = hcnt[b] ? dp.pass_of_op[hfirst[2 * b + 1] >> 8] : np - 1;
@@ -867,7 +901,14 @@ void Ctx::run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n,
       check_hip(ntk::launch_sample(sa, stream), "k_sample launch");
       sa.tlist = nullptr;
       run_entries(*this, c, dp, B, S, st, tau, fsub.data(), early_end ? &en : nullptr);
-      for (int j = 0; j < B; ++j) fh[off + std::get<1>(act[a0 + j])] = fsub[j];
+      for (int j = 0; j < B; ++j) {
+        const int b = std::get<1>(act[a0 + j]);
+        fh[off + b] = fsub[j];
+        if (reuse_on) {
+          reuse[t0 + off + (uint64_t)b].emplace_back(hcnt[b], fsub[j]);
+          ++reuse_values;
+        }
+      }
     }
   }
   uint64_t cnt = 0;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <unordered_map>
 #include <memory>
 #include <vector>
 
@@ -63,7 +64,20 @@ struct PassRun {
 };
 
 // Shortcut flags (nt_set_shortcuts).
-enum : int { SC_ZERO_FIRED = 1, SC_CHECKPOINT = 2, SC_LAST_ERROR = 4 };
+enum : int { SC_ZERO_FIRED = 1, SC_CHECKPOINT = 2, SC_LAST_ERROR = 4, SC_REUSE = 8 };
+
+// Identity of the runs whose trajectory values may be reused
+// (NT_SHORTCUT_REUSE): everything a value depends on except the rate.
+struct ReuseKey {
+  uint64_t serial = 0, cid = 0, seed = 0, target = 0, c_x = 0, c_xy = 0;
+  uint32_t always_types = 0;
+  int prec = 0, crit = 0, flags = 0, tile = 0;   // tile: the plan's tile-width override (sets the reduction order)
+  bool operator==(const ReuseKey &o) const {
+    return serial == o.serial && cid == o.cid && seed == o.seed && target == o.target && c_x == o.c_x &&
+           c_xy == o.c_xy && always_types == o.always_types && prec == o.prec && crit == o.crit &&
+           flags == o.flags && tile == o.tile;
+  }
+};
 
 struct Ctx {
   int device = 0;
@@ -73,6 +87,11 @@ struct Ctx {
   int prec = NT_C128;
   uint64_t max_batch = 0;
   int shortcuts = 0;
+  // NT_SHORTCUT_REUSE store: trajectory -> (fired-site count, value) pairs
+  ReuseKey reuse_key;
+  bool reuse_valid = false;
+  std::unordered_map<uint64_t, std::vector<std::pair<int32_t, double>>> reuse;
+  size_t reuse_values = 0;
   int crit = 0;                // NT_CRIT_*
   uint64_t target = 0;         // basis state of NT_CRIT_TARGET_PROB
   std::map<std::pair<uint64_t, int>, std::unique_ptr<DevPlan>> plans;

@@ -17,7 +17,7 @@ from typing import Dict, List, Sequence
 import numpy as np
 
 from . import (GNN_RATES, NT_CRIT_FIDELITY, NT_ERR_NOT_BRACKETED, NT_SHORTCUT_CHECKPOINT,
-               NT_SHORTCUT_LAST_ERROR, NT_SHORTCUT_ZERO_FIRED, NtError, nt_circuit_info, nt_circuit_set_id,
+               NT_SHORTCUT_LAST_ERROR, NT_SHORTCUT_REUSE, NT_SHORTCUT_ZERO_FIRED, NtError, nt_circuit_info, nt_circuit_set_id,
                nt_exhaustive, nt_eq5, nt_gnn_create, nt_gnn_predict, nt_gnn_set_data, nt_gnn_train,
                nt_run_batch, nt_set_criterion, nt_set_error_model, nt_set_shortcuts, nt_sweep,
                nt_tolerable_rate, nt_tolerable_rate_guided)
@@ -70,10 +70,17 @@ def tolerable_rate_searches(ctx, h, model, P_target: float = 0.66, tol: float = 
     'eq5'       exhaustive single errors, Eq. 5's rate, search in [p/3, 3p]
                 (whole grid when that fails);
     'surrogate' the search in the surrogate's bracket (whole grid fallback).
-    Short-cuts (zero-fired, checkpoint, last error) are on for every route."""
-    nt_set_shortcuts(ctx, NT_SHORTCUT_ZERO_FIRED | NT_SHORTCUT_CHECKPOINT | NT_SHORTCUT_LAST_ERROR)
+    Short-cuts (zero-fired, checkpoint, last error) are on for every route;
+    values are reused only within a route (the store is cleared before each),
+    so no route profits from another's probes."""
+    flags = NT_SHORTCUT_ZERO_FIRED | NT_SHORTCUT_CHECKPOINT | NT_SHORTCUT_LAST_ERROR | NT_SHORTCUT_REUSE
+
+    def fresh():
+        nt_set_shortcuts(ctx, flags)   # also empties the reuse store
+
     res = {}
     try:
+        fresh()
         t0 = time.perf_counter()
         P = nt_sweep(ctx, h, GNN_RATES, seed, n_traj, tau)
         res["sweep"] = {"seconds": time.perf_counter() - t0, "probes": len(GNN_RATES),
@@ -82,6 +89,7 @@ def tolerable_rate_searches(ctx, h, model, P_target: float = 0.66, tol: float = 
         def search(lo, hi):
             return nt_tolerable_rate(ctx, h, P_target, tol, lo, hi, seed, n_traj, tau)
 
+        fresh()
         t0 = time.perf_counter()
         try:
             p, k = search(GRID_LO, GRID_HI)
@@ -91,6 +99,7 @@ def tolerable_rate_searches(ctx, h, model, P_target: float = 0.66, tol: float = 
             p, k = float("nan"), -1
         res["full"] = {"seconds": time.perf_counter() - t0, "probes": k, "p_star": p}
 
+        fresh()
         t0 = time.perf_counter()
         _, _, S = nt_circuit_info(h)
         _, pe, pr = nt_exhaustive(ctx, h, tau)
@@ -121,6 +130,7 @@ def tolerable_rate_searches(ctx, h, model, P_target: float = 0.66, tol: float = 
                     raise
         res["eq5"] = {"seconds": time.perf_counter() - t0, "probes": probes, "p_star": p, "p_eq5": p5}
 
+        fresh()
         t0 = time.perf_counter()
         try:
             p, k, br = nt_tolerable_rate_guided(ctx, h, model, P_target, tol, seed, n_traj, tau)

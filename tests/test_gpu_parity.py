@@ -413,6 +413,46 @@ def test_shortcuts_bit_identical(P, ctx, prec):
         P.nt_circuit_free(h)
 
 
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_reuse_bit_identical(P, ctx, prec):
+    """NT_SHORTCUT_REUSE: values reused across rates (repeats, nearby rates,
+    a changed seed, circuit id and criterion in between) equal those of
+    runs without it, bit for bit; so does a tolerable-rate search."""
+    pr = P.NT_C64 if prec == "c64" else P.NT_C128
+    c = _all_gates_circuit(16, 3, 22)
+    h = _load(P, c)
+    P.nt_set_precision(ctx, pr)
+    base_flags = P.NT_SHORTCUT_ZERO_FIRED | P.NT_SHORTCUT_CHECKPOINT | P.NT_SHORTCUT_LAST_ERROR
+    N = 96
+    steps = [(4, 2e-3), (4, 1e-3), (4, 2e-3), (4, 1.05e-3), (5, 1.05e-3), (4, 5e-3), (4, 1e-3)]
+
+    def runs(flags):
+        P.nt_set_shortcuts(ctx, flags)
+        out = []
+        for k, (seed, p) in enumerate(steps):
+            P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+            if k == 3:
+                P.nt_circuit_set_id(h, 2)      # new errors for the same (seed, trajectory)
+            f = np.zeros(N)
+            cnt, _ = P.nt_run(ctx, h, seed, 7, N, TAU, f)
+            out.append((cnt, f))
+        P.nt_circuit_set_id(h, 0)
+        return out
+
+    plain = runs(base_flags)
+    reused = runs(base_flags | P.NT_SHORTCUT_REUSE)
+    for (c0, f0), (c1, f1) in zip(plain, reused):
+        np.testing.assert_array_equal(f1.view(np.uint64), f0.view(np.uint64))
+        assert c1 == c0
+    P.nt_set_shortcuts(ctx, base_flags)
+    s0 = P.nt_tolerable_rate(ctx, h, 0.66, 0.01, 1e-4, 0.2, 3, 256, TAU)
+    P.nt_set_shortcuts(ctx, base_flags | P.NT_SHORTCUT_REUSE)
+    s1 = P.nt_tolerable_rate(ctx, h, 0.66, 0.01, 1e-4, 0.2, 3, 256, TAU)
+    assert s1 == s0
+    P.nt_set_shortcuts(ctx, 0)
+    P.nt_circuit_free(h)
+
+
 # ---------------------------------------------------------------------------
 # Exhaustive single-error branch (Sec. IV-B.1, Eq. 3), Eq. 4, Eq. 5 and the
 # method switch of Fig. 2, against the oracle.
