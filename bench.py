@@ -193,30 +193,44 @@ def main():
         # error-free prefixes are not simulated (bit-identical results), and a
         # trajectory is scored after its last error against the error-free
         # state there (the common unitary suffix keeps the overlap: exact in
-        # arithmetic, equal to the full run up to rounding).
-        P.nt_set_shortcuts(ctx, P.NT_SHORTCUT_ZERO_FIRED | P.NT_SHORTCUT_CHECKPOINT | P.NT_SHORTCUT_LAST_ERROR)
+        # arithmetic, equal to the full run up to rounding).  A trajectory
+        # whose fired set at a probe equals one it had at an earlier probe
+        # (same count: the sets are nested across rates) reuses that value.
+        P.nt_set_shortcuts(ctx, P.NT_SHORTCUT_ZERO_FIRED | P.NT_SHORTCUT_CHECKPOINT | P.NT_SHORTCUT_LAST_ERROR
+                           | P.NT_SHORTCUT_REUSE)
         P.nt_set_max_batch(ctx, 0)
         print("bench: timing the tolerable-rate search ...", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         # upper end: the tolerable rate is below 1/G whenever the target exceeds
-        # the one-error success probability (Sec. IV-D); widen if not bracketed
-        bracket = [1e-5, 1.0 / G]
-        try:
-            p_star, probes = P.nt_tolerable_rate(ctx, h, 0.66, 0.01, bracket[0], bracket[1], 0, args.ttr_traj, tau)
-        except P.NtError as e:
-            if e.status != P.NT_ERR_NOT_BRACKETED:
-                raise
-            bracket = [1e-5, 1e-2]
-            p_star, probes = P.nt_tolerable_rate(ctx, h, 0.66, 0.01, bracket[0], bracket[1], 0, args.ttr_traj, tau)
+        # the one-error success probability (Sec. IV-D).  Lower end: every
+        # error-free trajectory succeeds (F = 1), so P(p) >= (1 - p)^S and the
+        # tolerable rate is at least p0 = 1 - P*^(1/S); half of p0 keeps the
+        # Monte Carlo estimate there clear of P*.  Widen if not bracketed.
+        S = circ.S
+        p0 = 1.0 - 0.66 ** (1.0 / S)
+        probes = 0
+        p_star = None
+        for bracket in ([max(1e-5, p0 / 2), 1.0 / G], [1e-5, 1.0 / G], [1e-5, 1e-2]):
+            try:
+                p_star, k = P.nt_tolerable_rate(ctx, h, 0.66, 0.01, bracket[0], bracket[1], 0, args.ttr_traj, tau)
+                probes += k
+                break
+            except P.NtError as e:
+                if e.status != P.NT_ERR_NOT_BRACKETED:
+                    raise
+                probes += 2
+        else:
+            raise RuntimeError("tolerable rate not bracketed in [1e-5, 1e-2]")
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         P.nt_set_shortcuts(ctx, 0)
         ttr = {"seconds": dt, "p_star": p_star, "probes": probes, "P_target": 0.66, "tol": 0.01,
                "trajectories_per_probe": args.ttr_traj, "bracket": bracket, "search": "Illinois in log10 p",
                "shortcuts": "zero-fired skipped and start at the first-error checkpoint (bit-identical); "
-                            "scored after the last error (exact in arithmetic)",
-               "one_over_G": 1.0 / G}
+                            "scored after the last error (exact in arithmetic); values of trajectories whose "
+                            "fired set was already simulated at an earlier probe reused (bit-identical)",
+               "one_over_G": 1.0 / G, "zero_error_bound": p0}
 
     cpu = None
     if not args.no_cpu_baseline:
