@@ -1045,22 +1045,25 @@ hipError_t launch_norm_final(const double *partials, int ntiles, double *nref, h
 template <typename T>
 __global__ void __launch_bounds__(256) k_unframe(const cx<T> *st, cx<T> *out, uint64_t dim,
                                                  const uint32_t *frame) {
-  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= dim) return;
   const uint32_t x = frame[0], z = frame[1], c = frame[2] & 3u;
-  const uint64_t src = k ^ (uint64_t)x;
-  cx<T> v = st[src];
-  if (__popc(z & (uint32_t)src) & 1u) v = cneg(v);
-  cx<T> o = v;
-  if (c == 1u) o = cx<T>{-v.y, v.x};
-  else if (c == 2u) o = cneg(v);
-  else if (c == 3u) o = cx<T>{v.y, -v.x};
-  out[k] = o;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < dim; k += stride) {
+    const uint64_t src = k ^ (uint64_t)x;
+    cx<T> v = st[src];
+    if (__popc(z & (uint32_t)src) & 1u) v = cneg(v);
+    cx<T> o = v;
+    if (c == 1u) o = cx<T>{-v.y, v.x};
+    else if (c == 2u) o = cneg(v);
+    else if (c == 3u) o = cx<T>{v.y, -v.x};
+    out[k] = o;
+  }
 }
 
 template <typename T>
 hipError_t launch_unframe(const cx<T> *st, cx<T> *out, uint64_t dim, const uint32_t *frame, hipStream_t s) {
-  const uint64_t blocks = (dim + 255) / 256;
+  // grid-stride: a dispatch holds fewer than 2^32 work-items, and 2^32
+  // amplitudes (32 qubits) would reach that
+  const uint64_t blocks = std::min<uint64_t>((dim + 255) / 256, (uint64_t)1 << 16);
   hipLaunchKernelGGL((k_unframe<T>), dim3((uint32_t)blocks), dim3(256), 0, s, st, out, dim, frame);
   return hipGetLastError();
 }

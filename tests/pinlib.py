@@ -175,3 +175,27 @@ def enumerate_success_weights(circuit, tau):
 def success_poly(c, S, p):
     w = np.arange(len(c))
     return float(np.sum(c * (1 - p) ** (S - w) * (p / 3) ** w))
+
+
+def ghz_chain_all_fired(n, pauli):
+    """Nonzero amplitudes {index: value} of the GHZ circuit H(0), CNOT(j ->
+    j+1) for j < n-1, with `pauli` ('X' or 'Z') fired at every site.
+
+    Each error is moved to the end through the later CNOTs, which map X on a
+    control to X on control and target and Z on a target to Z on control and
+    target and leave the rest alone.  X: qubit j ends with j + 2 flips for
+    j <= n-2 (one from the H error, one from the error on j as a control, j
+    from the errors on the targets 1..j carried down the chain) and n for
+    j = n-1, so X acts on the odd j <= n-2 and on n-1 when n is odd.  Z: the
+    errors stay where they fire; every qubit but the last collects two, the
+    last one, so the result is Z on qubit n-1."""
+    full = (1 << n) - 1
+    h = 1 / math.sqrt(2)
+    if pauli == "X":
+        mask = sum(1 << j for j in range(n - 1) if j % 2 == 1)
+        if n % 2 == 1:
+            mask |= 1 << (n - 1)
+        return {mask: h, mask ^ full: h}
+    if pauli == "Z":
+        return {0: h, full: -h}
+    raise ValueError(pauli)

@@ -137,6 +137,22 @@ def test_ghz_closed_form(orc, n):
     assert np.count_nonzero(np.abs(psi) > 0) == 2
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("pauli", ["X", "Z"])
+def test_ghz_chain_every_site_fired(orc, n, pauli):
+    """Every site fires one Pauli (p = 1 of one type): the oracle's sampled
+    run, a brute-force simulation of the pattern and the propagation
+    argument of pinlib.ghz_chain_all_fired agree."""
+    c = W.ghz(n)
+    want = np.zeros(1 << n, complex)
+    for k, a in pinlib.ghz_chain_all_fired(n, pauli).items():
+        want[k] = a
+    code = {"X": 1, "Z": 3}[pauli]
+    np.testing.assert_allclose(pinlib.simulate_pattern(c, [code] * c.S), want, atol=1e-14)
+    model = (1.0, 0.0, 0.0) if pauli == "X" else (0.0, 0.0, 1.0)
+    np.testing.assert_allclose(orc.final_state(c, *model, 3, 0), want, atol=1e-15)
+
+
 @pytest.mark.parametrize("n", [3, 5, 8])
 def test_qft_basis_states_vs_fft(orc, n):
     N = 1 << n
