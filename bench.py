@@ -44,12 +44,12 @@ MEASURED_TRAFFIC = {
     ("ghz_qft_layers24", "c64", 32): {
         "bytes_per_launch": 8.416e9,
         "passes": 43,
-        "kernel_sha256": "543a68c3ab2e5e2d15fec5df1d0f2a33084c07da5f08a2a8490f4fa2d7b46295",
+        "kernel_sha256": "2d59e6f5e14cc3ce0e57e30ffe199dcc31c3afc51c121cb4f8f2433ee0fd4ab4",
     },
     ("qaoa3reg30", "c64", 4): {
         "bytes_per_launch": 6.560e10,
         "passes": 11,
-        "kernel_sha256": "543a68c3ab2e5e2d15fec5df1d0f2a33084c07da5f08a2a8490f4fa2d7b46295",
+        "kernel_sha256": "2d59e6f5e14cc3ce0e57e30ffe199dcc31c3afc51c121cb4f8f2433ee0fd4ab4",
     },
 }
 
