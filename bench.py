@@ -79,13 +79,16 @@ def main():
     ap.add_argument("--cpu-traj", type=int, default=1, help="oracle trajectories timed on the host")
     ap.add_argument("--traffic", type=str, default=None,
                     help="JSON file with measured HBM bytes per pass launch (rocprofv3 counters)")
-    ap.add_argument("--ttr", action="store_true",
-                    help="also time the tolerable-rate search (P* = 0.66 +- 0.01, 10^4 trajectories per probe, "
-                         "exact short-cuts on)")
+    ap.add_argument("--ttr", dest="ttr", action="store_true", default=None,
+                    help="time the tolerable-rate search (P* = 0.66 +- 0.01, 10^4 trajectories per probe, "
+                         "exact short-cuts on); default on for the 24-qubit workload")
+    ap.add_argument("--no-ttr", dest="ttr", action="store_false", help="skip the tolerable-rate search")
     ap.add_argument("--ttr-traj", type=int, default=10000)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device copy of this many bytes (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.ttr is None:
+        args.ttr = args.workload == "ghz_qft_layers24"
     if args.copy_bytes:
         import torch
         x = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda:0")
