@@ -205,16 +205,23 @@ def main():
         print("bench: timing the tolerable-rate search ...", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        # upper end: the tolerable rate is below 1/G whenever the target exceeds
-        # the one-error success probability (Sec. IV-D).  Lower end: every
-        # error-free trajectory succeeds (F = 1), so P(p) >= (1 - p)^S and the
-        # tolerable rate is at least p0 = 1 - P*^(1/S); half of p0 keeps the
-        # Monte Carlo estimate there clear of P*.  Widen if not bracketed.
+        # Lower end: every error-free trajectory succeeds (F = 1), so
+        # P(p) >= (1 - p)^S and the tolerable rate is at least
+        # p0 = 1 - P*^(1/S); half of p0 keeps the Monte Carlo estimate there
+        # clear of P*.  Upper end: first 2 p0, where P would be P*^2 if every
+        # error were fatal, then 1/G (the tolerable rate is below 1/G whenever
+        # the target exceeds the one-error success probability, Sec. IV-D),
+        # then the whole grid.  A retried bracket re-evaluates rates already
+        # probed from the stored trajectory values, so a failed first guess
+        # costs little; every evaluation is still counted as a probe.
         S = circ.S
         p0 = 1.0 - 0.66 ** (1.0 / S)
         probes = 0
         p_star = None
-        for bracket in ([max(1e-5, p0 / 2), 1.0 / G], [1e-5, 1.0 / G], [1e-5, 1e-2]):
+        lo0 = max(1e-5, p0 / 2)
+        tries = [[lo0, min(2 * p0, 1.0 / G)], [lo0, 1.0 / G], [1e-5, 1.0 / G], [1e-5, 1e-2]]
+        tries = [t for i, t in enumerate(tries) if t[0] < t[1] and t not in tries[:i]]
+        for bracket in tries:
             try:
                 p_star, k = P.nt_tolerable_rate(ctx, h, 0.66, 0.01, bracket[0], bracket[1], 0, args.ttr_traj, tau)
                 probes += k
