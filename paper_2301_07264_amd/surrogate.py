@@ -64,12 +64,15 @@ def _interp_crossing(rates: Sequence[float], P: Sequence[float], target: float) 
 
 def tolerable_rate_searches(ctx, h, model, P_target: float = 0.66, tol: float = 0.01, n_traj: int = 2048,
                             seed: int = 0, tau: float = 0.9) -> Dict[str, dict]:
-    """Time to the tolerable rate of one circuit by four routes:
+    """Time to the tolerable rate of one circuit by five routes:
     'sweep'     the plain 13-point Monte Carlo sweep, crossing interpolated;
     'full'      the regula-falsi search over the whole grid [1e-5, 1e-2];
     'eq5'       exhaustive single errors, Eq. 5's rate, search in [p/3, 3p]
                 (whole grid when that fails);
-    'surrogate' the search in the surrogate's bracket (whole grid fallback).
+    'surrogate' the search in the surrogate's bracket (whole grid fallback);
+    'bound'     no model: the bracket [p0/2, 2 p0] from the zero-error bound
+                p0 = 1 - P*^(1/S) (P(p) >= (1 - p)^S), then [p0/2, 1/G],
+                then the whole grid.
     Short-cuts (zero-fired, checkpoint, last error) are on for every route;
     values are reused only within a route (the store is cleared before each),
     so no route profits from another's probes."""
@@ -139,6 +142,26 @@ def tolerable_rate_searches(ctx, h, model, P_target: float = 0.66, tol: float = 
                 raise
             p, k, br = float("nan"), -1, (GRID_LO, GRID_HI)
         res["surrogate"] = {"seconds": time.perf_counter() - t0, "probes": k, "p_star": p, "bracket": br}
+
+        fresh()
+        t0 = time.perf_counter()
+        _, G, S = nt_circuit_info(h)
+        p0 = 1.0 - P_target ** (1.0 / max(S, 1))
+        lo0 = max(GRID_LO, p0 / 2)
+        tries = [[lo0, min(2 * p0, 1.0 / max(G, 1), GRID_HI)], [lo0, min(1.0 / max(G, 1), GRID_HI)],
+                 [GRID_LO, GRID_HI]]
+        tries = [t for i, t in enumerate(tries) if t[0] < t[1] and t not in tries[:i]]
+        p, probes, br = float("nan"), 0, tries[-1]
+        for br in tries:
+            try:
+                p, k = search(br[0], br[1])
+                probes += k
+                break
+            except NtError as e:
+                if e.status != NT_ERR_NOT_BRACKETED:
+                    raise
+                probes += 2
+        res["bound"] = {"seconds": time.perf_counter() - t0, "probes": probes, "p_star": p, "bracket": br, "p0": p0}
     finally:
         nt_set_shortcuts(ctx, 0)
     return res
