@@ -340,12 +340,18 @@ nt_status nt_gnn_train(nt_gnn *m, int epochs, int batch_graphs, double lr, uint6
 /* Predicted success probabilities, out [n][13] (host). */
 nt_status nt_gnn_predict(nt_gnn *m, const nt_circuit *const *circuits, int n, int exact, float *out);
 
-/* Tolerable rate with the surrogate's bracket: from the predicted curve, the
- * grid interval where it crosses P_target widened by one grid step on each
- * side (the whole grid [1e-5, 1e-2] when it does not cross); then
- * nt_tolerable_rate inside it, and over [1e-5, 1e-2] if that bracket turns
- * out not to hold the target.  bracket_out (may be NULL): the bracket the
- * search ended in.  *n_probes counts every Monte Carlo evaluation. */
+/* Tolerable rate guided by the surrogate (an accelerator of the search of
+ * Sec. IV-D, not part of the paper).  From the predicted curve, the rate p^
+ * where it crosses P_target (linear in log10 p between the two grid points
+ * around the crossing).  One Monte Carlo probe at p^; if it is within tol of
+ * P_target, p^ is the answer.  Otherwise nt_tolerable_rate in half a grid
+ * step (a factor 10^(1/8)) from p^ on the side the probe points to, then in
+ * the grid interval of the crossing widened by one grid step per side, then
+ * over the whole grid [1e-5, 1e-2]; when the prediction does not cross
+ * P_target, the whole grid directly.  With NT_SHORTCUT_REUSE on, rates probed
+ * again cost no simulation.  bracket_out (may be NULL): the bracket the
+ * search ended in ([p^, p^] after a one-probe answer).  *n_probes counts
+ * every Monte Carlo evaluation, repeated ones included. */
 nt_status nt_tolerable_rate_guided(nt_ctx *ctx, const nt_circuit *c, nt_gnn *m, double P_target, double tol,
                                    uint64_t seed, uint64_t n_traj, double tau, double *p_star, int *n_probes,
                                    double bracket_out[2]);

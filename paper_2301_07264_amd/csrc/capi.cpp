@@ -626,20 +626,48 @@ nt_status nt_tolerable_rate_guided(nt_ctx *ctx, const nt_circuit *c, nt_gnn *m, 
       j = k;
       break;
     }
-  double lo = grid_lo, hi = grid_hi;
-  if (j >= 0) {
-    lo = gnn::output_rate(std::max(0, j - 1));
-    hi = gnn::output_rate(std::min(gnn::OUT - 1, j + 2));
-  }
   int probes = 0, pr = 0;
-  s = nt_tolerable_rate(ctx, c, P_target, tol, lo, hi, seed, n_traj, tau, p_star, &pr);
-  probes += pr;
-  if (s == NT_ERR_NOT_BRACKETED && (lo > grid_lo || hi < grid_hi)) {
-    lo = grid_lo;
-    hi = grid_hi;
-    pr = 0;
+  double lo = grid_lo, hi = grid_hi;
+  if (j < 0) {
     s = nt_tolerable_rate(ctx, c, P_target, tol, lo, hi, seed, n_traj, tau, p_star, &pr);
     probes += pr;
+  } else {
+    // 1. One Monte Carlo probe at the predicted crossing (linear in log10 p
+    //    between the two grid points); done if it meets the tolerance.
+    const double x0 = std::log10(gnn::output_rate(j)), x1 = std::log10(gnn::output_rate(j + 1));
+    const double t = ((double)pred[j] - P_target) / ((double)pred[j] - (double)pred[j + 1]);
+    const double ph = std::pow(10.0, x0 + t * (x1 - x0));
+    double Ph = 0.0;
+    s = nt_sweep(ctx, c, &ph, 1, seed, n_traj, tau, &Ph);
+    if (s) {
+      if (n_probes) *n_probes = 0;
+      return s;
+    }
+    probes = 1;
+    lo = hi = ph;
+    if (std::fabs(Ph - P_target) <= tol) {
+      *p_star = ph;
+      s = NT_OK;
+    } else {
+      // 2. Half a grid step from the probe, on the side its value points
+      //    to; 3. the grid interval widened by one step per side; 4. the
+      //    whole grid.  Rates probed before are evaluated again (from the
+      //    stored trajectory values when NT_SHORTCUT_REUSE is on).
+      const double half = std::pow(10.0, 0.125);
+      double tries[3][2] = {{Ph > P_target ? ph : std::max(grid_lo, ph / half),
+                             Ph > P_target ? std::min(grid_hi, ph * half) : ph},
+                            {gnn::output_rate(std::max(0, j - 1)), gnn::output_rate(std::min(gnn::OUT - 1, j + 2))},
+                            {grid_lo, grid_hi}};
+      s = NT_ERR_NOT_BRACKETED;
+      for (int k = 0; k < 3 && s == NT_ERR_NOT_BRACKETED; ++k) {
+        if (!(tries[k][0] < tries[k][1])) continue;
+        lo = tries[k][0];
+        hi = tries[k][1];
+        pr = 0;
+        s = nt_tolerable_rate(ctx, c, P_target, tol, lo, hi, seed, n_traj, tau, p_star, &pr);
+        probes += pr;
+      }
+    }
   }
   if (n_probes) *n_probes = probes;
   if (bracket_out) {

@@ -69,7 +69,8 @@ def tolerable_rate_searches(ctx, h, model, P_target: float = 0.66, tol: float = 
     'full'      the regula-falsi search over the whole grid [1e-5, 1e-2];
     'eq5'       exhaustive single errors, Eq. 5's rate, search in [p/3, 3p]
                 (whole grid when that fails);
-    'surrogate' the search in the surrogate's bracket (whole grid fallback);
+    'surrogate' one probe at the surrogate's predicted crossing, then the
+                search in brackets around it (whole grid fallback);
     'bound'     no model: the bracket [p0/2, 2 p0] from the zero-error bound
                 p0 = 1 - P*^(1/S) (P(p) >= (1 - p)^S), then [p0/2, 1/G],
                 then the whole grid.
