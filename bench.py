@@ -214,29 +214,50 @@ def main():
         # then the whole grid.  A retried bracket re-evaluates rates already
         # probed from the stored trajectory values, so a failed first guess
         # costs little; every evaluation is still counted as a probe.
+        # Two stages over the same trajectories (common random numbers): the
+        # search on the first N/5 of them, then all N: one probe at the coarse
+        # answer (its first N/5 trajectories are found in the reuse store),
+        # which is the answer if it meets the tolerance, else the search in
+        # a tenth of a decade on the side that probe points to.
         S = circ.S
         p0 = 1.0 - 0.66 ** (1.0 / S)
-        probes = 0
-        p_star = None
-        lo0 = max(1e-5, p0 / 2)
-        tries = [[lo0, min(2 * p0, 1.0 / G)], [lo0, 1.0 / G], [1e-5, 1.0 / G], [1e-5, 1e-2]]
-        tries = [t for i, t in enumerate(tries) if t[0] < t[1] and t not in tries[:i]]
-        for bracket in tries:
-            try:
-                p_star, k = P.nt_tolerable_rate(ctx, h, 0.66, 0.01, bracket[0], bracket[1], 0, args.ttr_traj, tau)
-                probes += k
-                break
-            except P.NtError as e:
-                if e.status != P.NT_ERR_NOT_BRACKETED:
-                    raise
-                probes += 2
-        else:
+        N_full = args.ttr_traj
+        N_coarse = max(1, N_full // 5)
+
+        def bracketed_search(tries, ntraj):
+            k_sum = 0
+            for br in tries:
+                if not br[0] < br[1]:
+                    continue
+                try:
+                    p, k = P.nt_tolerable_rate(ctx, h, 0.66, 0.01, br[0], br[1], 0, ntraj, tau)
+                    return p, k_sum + k, br
+                except P.NtError as e:
+                    if e.status != P.NT_ERR_NOT_BRACKETED:
+                        raise
+                    k_sum += 2
             raise RuntimeError("tolerable rate not bracketed in [1e-5, 1e-2]")
+
+        lo0 = max(1e-5, p0 / 2)
+        wide = [[lo0, min(2 * p0, 1.0 / G)], [lo0, 1.0 / G], [1e-5, 1.0 / G], [1e-5, 1e-2]]
+        p_c, k_c, br_c = bracketed_search(wide, N_coarse)
+        P_c = float(P.nt_sweep(ctx, h, [p_c], 0, N_full, tau)[0])
+        k_f = 1
+        if abs(P_c - 0.66) <= 0.01:
+            p_star, bracket = p_c, [p_c, p_c]
+        else:
+            f = 10.0 ** 0.1
+            side = [p_c, min(p_c * f, 1e-2)] if P_c > 0.66 else [max(p_c / f, 1e-5), p_c]
+            p_star, k, bracket = bracketed_search([side] + wide, N_full)
+            k_f += k
+        probes = k_c + k_f
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         P.nt_set_shortcuts(ctx, 0)
-        ttr = {"seconds": dt, "p_star": p_star, "probes": probes, "P_target": 0.66, "tol": 0.01,
-               "trajectories_per_probe": args.ttr_traj, "bracket": bracket, "search": "Illinois in log10 p",
+        ttr = {"seconds": dt, "p_star": p_star, "probes": probes,
+               "probes_by_stage": {f"{N_coarse} trajectories": k_c, f"{N_full} trajectories": k_f},
+               "P_target": 0.66, "tol": 0.01, "trajectories_per_probe": N_full, "bracket": bracket,
+               "search": "Illinois in log10 p; N/5 trajectories, then all N from the coarse answer",
                "shortcuts": "zero-fired skipped and start at the first-error checkpoint (bit-identical); "
                             "scored after the last error (exact in arithmetic); values of trajectories whose "
                             "fired set was already simulated at an earlier probe reused (bit-identical)",
