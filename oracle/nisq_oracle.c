@@ -37,8 +37,9 @@
  *   - random draws: Philox4x64-10 (Salmon et al., SC'11), key = (seed,
  *     circuit id), counter = (site, trajectory, 0, 0).  A site fires iff
  *     word0 < thr(p_x+p_y+p_z); its type is X if word1 < thr(p_x/sum), else
- *     Y if word1 < thr((p_x+p_y)/sum), else Z; thr(x) = floor(x * 2^64), or
- *     "always" when x >= 1.  The rate is not in the counter, so fired sets are
+ *     Y if word1 < thr((p_x+p_y)/sum), else Z (thr(1/3) and thr(2/3) when
+ *     p_x = p_y = p_z, so that the split does not depend on the rate);
+ *     thr(x) = floor(x * 2^64), or "always" when x >= 1.  The rate is not in the counter, so fired sets are
  *     nested across rates (common random numbers);
  *   - the fidelity criterion is the indicator F >= tau, with
  *     F = |<R|psi>|^2 / (<R|R><psi|psi>);
@@ -186,7 +187,12 @@ typedef struct {
 static void make_thresholds(double px, double py, double pz, thresholds *th) {
   double sum = px + py + pz;
   th->t_fire = orc_threshold(sum, &th->a_fire);
-  if (sum > 0) {
+  if (sum > 0 && px == py && py == pz) {
+    /* uniform model: the type split is exactly one third each, whatever the
+     * rate (px / sum would round differently from rate to rate) */
+    th->c_x = orc_threshold(1.0 / 3.0, &th->a_x);
+    th->c_xy = orc_threshold(2.0 / 3.0, &th->a_xy);
+  } else if (sum > 0) {
     th->c_x = orc_threshold(px / sum, &th->a_x);
     th->c_xy = orc_threshold((px + py) / sum, &th->a_xy);
   } else {

@@ -279,7 +279,13 @@ Thresholds make_thresholds(double px, double py, double pz) {
   double sum = px + py + pz;
   bool a0, a1 = false, a2 = false;
   t.t_fire = thr(sum, &a0);
-  if (sum > 0) {
+  if (sum > 0 && px == py && py == pz) {
+    // uniform model: exactly one third each, whatever the rate (px / sum
+    // rounds differently from rate to rate, and the type draws must be the
+    // same at every rate for the fired sets to be nested with equal types)
+    t.c_x = thr(1.0 / 3.0, &a1);
+    t.c_xy = thr(2.0 / 3.0, &a2);
+  } else if (sum > 0) {
     t.c_x = thr(px / sum, &a1);
     t.c_xy = thr((px + py) / sum, &a2);
   }

@@ -219,6 +219,17 @@ def test_thresholds(orc):
     p = 1e-3
     th, alw = orc.thresholds(p / 3, p / 3, p / 3)
     assert int(th[0]) == math.floor(math.ldexp((p / 3 + p / 3) + p / 3, 64))
+    # uniform model: the type split is thr(1/3), thr(2/3) at every rate, also
+    # where (p/3) / (p/3 + p/3 + p/3) rounds away from 1/3
+    third = math.floor(math.ldexp(1.0 / 3.0, 64))
+    two_thirds = math.floor(math.ldexp(2.0 / 3.0, 64))
+    drifts = 0
+    for p in (6.8e-5, 1e-4, 1.4318e-4, 2.7e-4, 1e-3, 0.3):
+        th, alw = orc.thresholds(p / 3, p / 3, p / 3)
+        assert (int(th[1]), int(th[2])) == (third, two_thirds)
+        x = p / 3
+        drifts += math.floor(math.ldexp(x / (x + x + x), 64)) != third
+    assert drifts > 0   # the plain quotient would move the split with the rate
 
 
 # --------------------------------------------------------------------------
