@@ -23,6 +23,7 @@ Prints one JSON line.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -217,8 +218,9 @@ def main():
         # Two stages over the same trajectories (common random numbers): the
         # search on the first N/5 of them, then all N: one probe at the coarse
         # answer (its first N/5 trajectories are found in the reuse store),
-        # which is the answer if it meets the tolerance, else the search in
-        # a tenth of a decade on the side that probe points to.
+        # which is the answer if it meets the tolerance; else one Newton step
+        # in log10 p from it, then the search between the two (or in a tenth
+        # of a decade on the side the probe points to).
         S = circ.S
         p0 = 1.0 - 0.66 ** (1.0 / S)
         N_full = args.ttr_traj
@@ -243,13 +245,30 @@ def main():
         p_c, k_c, br_c = bracketed_search(wide, N_coarse)
         P_c = float(P.nt_sweep(ctx, h, [p_c], 0, N_full, tau)[0])
         k_f = 1
+        p_star = None
         if abs(P_c - 0.66) <= 0.01:
             p_star, bracket = p_c, [p_c, p_c]
         else:
-            f = 10.0 ** 0.1
-            side = [p_c, min(p_c * f, 1e-2)] if P_c > 0.66 else [max(p_c / f, 1e-5), p_c]
-            p_star, k, bracket = bracketed_search([side] + wide, N_full)
-            k_f += k
+            # Newton step in log10 p with the slope of the coarse stage's
+            # bracket (its ends at N/5 come from the reuse store)
+            P_lo, P_hi = (float(x) for x in P.nt_sweep(ctx, h, br_c, 0, N_coarse, tau))
+            k_c += 2
+            slope = (P_lo - P_hi) / (math.log10(br_c[1]) - math.log10(br_c[0]))
+            side = None
+            if slope > 0:
+                p1 = min(max(p_c * 10.0 ** ((P_c - 0.66) / slope), 1e-5), 1e-2)
+                P_1 = float(P.nt_sweep(ctx, h, [p1], 0, N_full, tau)[0])
+                k_f += 1
+                if abs(P_1 - 0.66) <= 0.01:
+                    p_star, bracket = p1, [p1, p1]
+                elif (P_1 - 0.66) * (P_c - 0.66) < 0:
+                    side = [min(p_c, p1), max(p_c, p1)]
+            if p_star is None:
+                if side is None:
+                    f = 10.0 ** 0.1
+                    side = [p_c, min(p_c * f, 1e-2)] if P_c > 0.66 else [max(p_c / f, 1e-5), p_c]
+                p_star, k, bracket = bracketed_search([side] + wide, N_full)
+                k_f += k
         probes = k_c + k_f
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
