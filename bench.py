@@ -23,7 +23,6 @@ Prints one JSON line.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -206,69 +205,16 @@ def main():
         print("bench: timing the tolerable-rate search ...", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        # Lower end: every error-free trajectory succeeds (F = 1), so
-        # P(p) >= (1 - p)^S and the tolerable rate is at least
-        # p0 = 1 - P*^(1/S); half of p0 keeps the Monte Carlo estimate there
-        # clear of P*.  Upper end: first 2 p0, where P would be P*^2 if every
-        # error were fatal, then 1/G (the tolerable rate is below 1/G whenever
-        # the target exceeds the one-error success probability, Sec. IV-D),
-        # then the whole grid.  A retried bracket re-evaluates rates already
-        # probed from the stored trajectory values, so a failed first guess
-        # costs little; every evaluation is still counted as a probe.
-        # Two stages over the same trajectories (common random numbers): the
-        # search on the first N/5 of them, then all N: one probe at the coarse
-        # answer (its first N/5 trajectories are found in the reuse store),
-        # which is the answer if it meets the tolerance; else one Newton step
-        # in log10 p from it, then the search between the two (or in a tenth
-        # of a decade on the side the probe points to).
+        # nt_tolerable_rate_auto: Illinois regula falsi in log10 p, first on
+        # N/5 of the trajectories in brackets from the zero-error bound
+        # p0 = 1 - P*^(1/S) (P(p) >= (1 - p)^S: error-free trajectories
+        # succeed) and 1/G (Sec. IV-D), then on all N from the coarse answer
+        # (one probe, one Newton step, then a bracket between them).
         S = circ.S
         p0 = 1.0 - 0.66 ** (1.0 / S)
         N_full = args.ttr_traj
         N_coarse = max(1, N_full // 5)
-
-        def bracketed_search(tries, ntraj):
-            k_sum = 0
-            for br in tries:
-                if not br[0] < br[1]:
-                    continue
-                try:
-                    p, k = P.nt_tolerable_rate(ctx, h, 0.66, 0.01, br[0], br[1], 0, ntraj, tau)
-                    return p, k_sum + k, br
-                except P.NtError as e:
-                    if e.status != P.NT_ERR_NOT_BRACKETED:
-                        raise
-                    k_sum += 2
-            raise RuntimeError("tolerable rate not bracketed in [1e-5, 1e-2]")
-
-        lo0 = max(1e-5, p0 / 2)
-        wide = [[lo0, min(2 * p0, 1.0 / G)], [lo0, 1.0 / G], [1e-5, 1.0 / G], [1e-5, 1e-2]]
-        p_c, k_c, br_c = bracketed_search(wide, N_coarse)
-        P_c = float(P.nt_sweep(ctx, h, [p_c], 0, N_full, tau)[0])
-        k_f = 1
-        p_star = None
-        if abs(P_c - 0.66) <= 0.01:
-            p_star, bracket = p_c, [p_c, p_c]
-        else:
-            # Newton step in log10 p with the slope of the coarse stage's
-            # bracket (its ends at N/5 come from the reuse store)
-            P_lo, P_hi = (float(x) for x in P.nt_sweep(ctx, h, br_c, 0, N_coarse, tau))
-            k_c += 2
-            slope = (P_lo - P_hi) / (math.log10(br_c[1]) - math.log10(br_c[0]))
-            side = None
-            if slope > 0:
-                p1 = min(max(p_c * 10.0 ** ((P_c - 0.66) / slope), 1e-5), 1e-2)
-                P_1 = float(P.nt_sweep(ctx, h, [p1], 0, N_full, tau)[0])
-                k_f += 1
-                if abs(P_1 - 0.66) <= 0.01:
-                    p_star, bracket = p1, [p1, p1]
-                elif (P_1 - 0.66) * (P_c - 0.66) < 0:
-                    side = [min(p_c, p1), max(p_c, p1)]
-            if p_star is None:
-                if side is None:
-                    f = 10.0 ** 0.1
-                    side = [p_c, min(p_c * f, 1e-2)] if P_c > 0.66 else [max(p_c / f, 1e-5), p_c]
-                p_star, k, bracket = bracketed_search([side] + wide, N_full)
-                k_f += k
+        p_star, k_c, k_f, bracket = P.nt_tolerable_rate_auto(ctx, h, 0.66, 0.01, 0, N_full, tau)
         probes = k_c + k_f
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0

@@ -242,6 +242,32 @@ nt_status nt_tolerable_rate(nt_ctx *ctx, const nt_circuit *c, double P_target, d
                             double p_lo, double p_hi, uint64_t seed, uint64_t n_traj,
                             double tau, double *p_star, int *n_probes);
 
+/* Tolerable uniform rate without a caller's bracket: the search of
+ * nt_tolerable_rate (Sec. IV-D) in two stages over the same trajectories.
+ *  1. Coarse: nt_tolerable_rate on the first max(1, n_traj/5) trajectories,
+ *     in [p0/2, min(2 p0, 1/G)], then [p0/2, 1/G], [1e-6, 1/G], [1e-6, 0.5]
+ *     until one holds the target.  p0 = 1 - P_target^(1/S): a trajectory with
+ *     no fired site succeeds under the fidelity criterion, so
+ *     P(p) >= (1 - p)^S and the tolerable rate is at least p0; 1/G is the
+ *     paper's bound (Sec. IV-D); at 2 p0, P would be P_target^2 if every
+ *     error were fatal.
+ *  2. Full: one probe with all n_traj trajectories at the coarse answer p_c,
+ *     the answer if within tol of P_target; else one Newton step in log10 p
+ *     with the slope of the coarse bracket, the answer if within tol; else
+ *     nt_tolerable_rate between the two probes (or a tenth of a decade from
+ *     p_c on the side its probe points to), falling back to the stage-1
+ *     brackets, all with n_traj trajectories.
+ * The answer always has a full-sample success probability within tol of
+ * P_target (or is the midpoint of a bracket narrower than 0.1%).  Cheap with
+ * NT_SHORTCUT_REUSE on: the coarse trajectories and rates probed again are
+ * not simulated again.  *n_coarse / *n_full (may be NULL): Monte Carlo
+ * evaluations per stage, repeated ones included; bracket_out (may be NULL):
+ * the last bracket searched ([p, p] for an answer found by a single probe).
+ * NT_ERR_NOT_BRACKETED when no bracket holds the target. */
+nt_status nt_tolerable_rate_auto(nt_ctx *ctx, const nt_circuit *c, double P_target, double tol, uint64_t seed,
+                                 uint64_t n_traj, double tau, double *p_star, int *n_coarse, int *n_full,
+                                 double bracket_out[2]);
+
 /* Exact short-cuts for Monte Carlo runs (results stay bit-identical):
  * NT_SHORTCUT_ZERO_FIRED -- a trajectory with no fired site ends in the
  *   error-free state, so its fidelity is 1 without simulating it (for the

@@ -43,6 +43,7 @@ EXPORTED = [
     "nt_create", "nt_destroy", "nt_set_error_model", "nt_set_precision", "nt_set_max_batch",
     "nt_circuit_load", "nt_circuit_load_text", "nt_circuit_free", "nt_circuit_info",
     "nt_circuit_set_id", "nt_plan_info", "nt_plan_export", "nt_run", "nt_sweep", "nt_tolerable_rate",
+    "nt_tolerable_rate_auto",
     "nt_sample_sites", "nt_final_state", "nt_reference_state", "nt_timing_enable",
     "nt_timing_reset", "nt_timing_read", "nt_last_error", "nt_version",
     "nt_set_shortcuts", "nt_exhaustive", "nt_eq4", "nt_eq5", "nt_success_probability",
@@ -111,6 +112,7 @@ def lib() -> C.CDLL:
         "nt_run": ([P, P, u64, u64, u64, dbl, P, P, P], i32),
         "nt_sweep": ([P, P, P, i32, u64, u64, dbl, P], i32),
         "nt_tolerable_rate": ([P, P, dbl, dbl, dbl, dbl, u64, u64, dbl, P, P], i32),
+        "nt_tolerable_rate_auto": ([P, P, dbl, dbl, u64, u64, dbl, P, P, P, P], i32),
         "nt_sample_sites": ([P, P, u64, u64, u64, P, P, P, i64, P], i32),
         "nt_final_state": ([P, P, u64, u64, P, i64], i32),
         "nt_reference_state": ([P, P, P, i64], i32),
@@ -314,6 +316,17 @@ def nt_tolerable_rate(ctx, circ, P_target: float, tol: float, p_lo: float, p_hi:
     _check(lib().nt_tolerable_rate(ctx, circ, P_target, tol, p_lo, p_hi, seed, n_traj, tau,
                                    C.byref(ps), C.byref(npb)))
     return ps.value, npb.value
+
+
+def nt_tolerable_rate_auto(ctx, circ, P_target: float, tol: float, seed: int, n_traj: int, tau: float):
+    """Returns (p_star, coarse evaluations, full evaluations, (lo, hi) of the last bracket)."""
+    ps = C.c_double()
+    kc = C.c_int()
+    kf = C.c_int()
+    br = (C.c_double * 2)()
+    _check(lib().nt_tolerable_rate_auto(ctx, circ, P_target, tol, seed, n_traj, tau, C.byref(ps), C.byref(kc),
+                                        C.byref(kf), br))
+    return ps.value, kc.value, kf.value, (br[0], br[1])
 
 
 def nt_sample_sites(ctx, circ, seed: int, traj_begin: int, n_traj: int, cap: Optional[int] = None):

@@ -358,6 +358,90 @@ nt_status nt_tolerable_rate(nt_ctx *ctx, const nt_circuit *c, double P_target, d
   return NT_OK;
 }
 
+nt_status nt_tolerable_rate_auto(nt_ctx *ctx, const nt_circuit *c, double P_target, double tol, uint64_t seed,
+                                 uint64_t n_traj, double tau, double *p_star, int *n_coarse, int *n_full,
+                                 double bracket_out[2]) {
+  nt_status s = check_run_args(ctx, c, tau);
+  if (s) return s;
+  if (!p_star) return fail(NT_ERR_INVALID_ARG, "p_star is NULL");
+  if (!(P_target > 0 && P_target < 1) || !(tol >= 0)) return fail(NT_ERR_INVALID_ARG, "need 0 < P_target < 1, tol >= 0");
+  if (n_traj == 0) return fail(NT_ERR_INVALID_ARG, "n_traj must be > 0");
+  const double S = (double)std::max<int64_t>(c->impl->S, 1), G = (double)std::max<size_t>(c->impl->gates.size(), 1);
+  const double p0 = 1.0 - std::pow(P_target, 1.0 / S);
+  const double lo0 = std::max(1e-6, 0.5 * p0), pmax = 0.5;
+  const double wide[4][2] = {{lo0, std::min(2.0 * p0, 1.0 / G)}, {lo0, 1.0 / G}, {1e-6, 1.0 / G}, {1e-6, pmax}};
+  int kc = 0, kf = 0;
+  double br[2] = {0.0, 0.0};
+  auto finish = [&](nt_status st) {
+    if (n_coarse) *n_coarse = kc;
+    if (n_full) *n_full = kf;
+    if (bracket_out) {
+      bracket_out[0] = br[0];
+      bracket_out[1] = br[1];
+    }
+    return st;
+  };
+  // nt_tolerable_rate over a list of brackets until one holds the target
+  auto search = [&](const double (*tries)[2], int nt, uint64_t n, int *k) -> nt_status {
+    nt_status st = NT_ERR_NOT_BRACKETED;
+    for (int i = 0; i < nt && st == NT_ERR_NOT_BRACKETED; ++i) {
+      if (!(tries[i][0] > 0 && tries[i][0] < tries[i][1] && tries[i][1] <= 1)) continue;
+      br[0] = tries[i][0];
+      br[1] = tries[i][1];
+      int pr = 0;
+      st = nt_tolerable_rate(ctx, c, P_target, tol, br[0], br[1], seed, n, tau, p_star, &pr);
+      *k += pr;
+    }
+    return st;
+  };
+  const uint64_t nc = std::max<uint64_t>(1, n_traj / 5);
+  s = search(wide, 4, nc, &kc);
+  if (s) return finish(s);
+  const double pc = *p_star, bc0 = br[0], bc1 = br[1];
+  double Pc = 0.0;
+  s = nt_sweep(ctx, c, &pc, 1, seed, n_traj, tau, &Pc);
+  if (s) return finish(s);
+  ++kf;
+  if (std::fabs(Pc - P_target) <= tol) {
+    *p_star = pc;
+    br[0] = br[1] = pc;
+    return finish(NT_OK);
+  }
+  double side[1][2] = {{0.0, 0.0}};
+  bool have_side = false;
+  double Pb[2] = {0.0, 0.0};
+  const double bce[2] = {bc0, bc1};
+  s = nt_sweep(ctx, c, bce, 2, seed, nc, tau, Pb);
+  if (s) return finish(s);
+  kc += 2;
+  const double slope = (Pb[0] - Pb[1]) / (std::log10(bc1) - std::log10(bc0));
+  if (slope > 0) {
+    const double p1 = std::min(pmax, std::max(1e-6, pc * std::pow(10.0, (Pc - P_target) / slope)));
+    double P1 = 0.0;
+    s = nt_sweep(ctx, c, &p1, 1, seed, n_traj, tau, &P1);
+    if (s) return finish(s);
+    ++kf;
+    if (std::fabs(P1 - P_target) <= tol) {
+      *p_star = p1;
+      br[0] = br[1] = p1;
+      return finish(NT_OK);
+    }
+    if ((P1 - P_target) * (Pc - P_target) < 0) {
+      side[0][0] = std::min(pc, p1);
+      side[0][1] = std::max(pc, p1);
+      have_side = true;
+    }
+  }
+  if (!have_side) {
+    const double f = std::pow(10.0, 0.1);
+    side[0][0] = Pc > P_target ? pc : std::max(1e-6, pc / f);
+    side[0][1] = Pc > P_target ? std::min(pmax, pc * f) : pc;
+  }
+  s = search(side, 1, n_traj, &kf);
+  if (s == NT_ERR_NOT_BRACKETED) s = search(wide, 4, n_traj, &kf);
+  return finish(s);
+}
+
 nt_status nt_set_shortcuts(nt_ctx *ctx, int flags) {
   if (!ctx) return fail(NT_ERR_INVALID_ARG, "ctx is NULL");
   if (flags & ~(NT_SHORTCUT_ZERO_FIRED | NT_SHORTCUT_CHECKPOINT | NT_SHORTCUT_LAST_ERROR | NT_SHORTCUT_REUSE))

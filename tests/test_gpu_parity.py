@@ -338,6 +338,49 @@ def test_sweep_and_tolerable_rate_vs_oracle(P, ctx, orc):
     P.nt_circuit_free(h)
 
 
+@pytest.mark.parametrize("name,maker,N", [
+    ("8 qubits", lambda: W.config0(), 1000),
+    ("16 qubits, 20 layers", lambda: W.config1(n=16, layers=20), 2000),
+])
+def test_tolerable_rate_auto(P, ctx, orc, name, maker, N):
+    """The two-stage search without a caller's bracket: its answer meets the
+    criterion on all N trajectories (checked with the oracle's sweep at that
+    rate where the oracle finishes quickly, else with an independent library
+    run), with and without the exact short-cuts, and both agree."""
+    c = maker()
+    h = _load(P, c)
+    P.nt_set_precision(ctx, P.NT_C128 if c.n <= 8 else P.NT_C64)
+    answers = []
+    for sc in (0, P.NT_SHORTCUT_ZERO_FIRED | P.NT_SHORTCUT_CHECKPOINT | P.NT_SHORTCUT_REUSE):
+        P.nt_set_shortcuts(ctx, sc)
+        _say(f"auto search, {name}, short-cuts {sc}")
+        p, kc, kf, br = P.nt_tolerable_rate_auto(ctx, h, 0.66, 0.01, 0, N, TAU)
+        assert kc >= 2 and kf >= 1 and br[0] <= p <= br[1]
+        answers.append((p, kc, kf))
+    P.nt_set_shortcuts(ctx, 0)
+    # bit-identical short-cuts: the same probes, the same answer
+    assert answers[0] == answers[1]
+    p = answers[0][0]
+    if c.n <= 8:
+        Pm = float(orc.sweep(c, [p], 0, N, TAU)[0])
+    else:
+        Pm = float(P.nt_sweep(ctx, h, [p], 0, N, TAU)[0])
+    assert abs(Pm - 0.66) <= 0.01 + 1e-12
+    assert p < 1.0 / c.G          # below 1/G (Sec. IV-D)
+    P.nt_circuit_free(h)
+
+
+def test_tolerable_rate_auto_arguments(P, ctx):
+    h = _load(P, W.config0())
+    for bad in ((0.0, 0.01), (1.0, 0.01), (0.66, -1.0)):
+        with pytest.raises(P.NtError) as ei:
+            P.nt_tolerable_rate_auto(ctx, h, bad[0], bad[1], 0, 100, TAU)
+        assert ei.value.status == P.NT_ERR_INVALID_ARG
+    with pytest.raises(P.NtError):
+        P.nt_tolerable_rate_auto(ctx, h, 0.66, 0.01, 0, 0, TAU)
+    P.nt_circuit_free(h)
+
+
 # ---------------------------------------------------------------------------
 # The 24-qubit workload at full size: reference state vs the oracle, and a
 # few trajectories' fidelities, in the precision and launch shape the
