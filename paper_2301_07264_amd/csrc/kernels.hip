@@ -314,14 +314,32 @@ struct OpLite {
 
 template <typename T>
 DEV OpLite<T> load_lite(const DevOp<T> *ops, int o) {
-  const NT_CONST DevOp<T> &op = cptr(ops)[o];
   OpLite<T> h;
-  h.code = op.cls;
-  h.qa = op.qa;
-  h.qb = op.qb;
-  h.rsel = op.rsel;
+  if constexpr (sizeof(T) == 4) {
+    // header and the four entries: the first 12 dwords of the descriptor
+    struct W12 {
+      uint32_t w[12];
+    };
+    const NT_CONST W12 &q = *reinterpret_cast<const NT_CONST W12 *>(
+        reinterpret_cast<const NT_CONST char *>(cptr(ops)) + ((uint32_t)o << 8));
+    uint32_t w[12];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) h.m[i] = op.m[i];
+    for (int i = 0; i < 12; ++i) w[i] = q.w[i];
+    h.code = (int32_t)w[0];
+    h.qa = (int32_t)w[1];
+    h.qb = (int32_t)w[2];
+    h.rsel = (int32_t)w[3];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) h.m[i] = __builtin_bit_cast(T, w[4 + i]);
+  } else {
+    const NT_CONST DevOp<T> &op = cptr(ops)[o];
+    h.code = op.cls;
+    h.qa = op.qa;
+    h.qb = op.qb;
+    h.rsel = op.rsel;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) h.m[i] = op.m[i];
+  }
   return h;
 }
 
@@ -439,7 +457,8 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
   };
   // controlled X (control qb)
   const uint32_t qc = (uint32_t)op.qb;
-  const uint32_t cv = 1u ^ ((fx >> qc) & 1u);
+  const uint32_t xc = (fx >> qc) & 1u;   // frame X on qb
+  const uint32_t cv = 1u ^ xc;
   // The two most frequent kinds are tested first, each followed by a
   // four-way branch on the register bit; everything else goes through one
   // switch on the full code.
@@ -496,7 +515,7 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
     break;                                                                                \
   case OPK_D2A * 4 + b:                                                                   \
     if constexpr (b < R) {                                                                \
-      const uint32_t t = ((gb >> qc) & 1u) ^ ((fx >> qc) & 1u);                           \
+      const uint32_t t = ((gb >> qc) & 1u) ^ xc;                                          \
       const cx<T> lo = t ? m10 : m00, hi = t ? m11 : m01;                                 \
       diag_bit<b, R>(v, w, xa ? hi : lo, xa ? lo : hi);                                   \
     }                                                                                     \
@@ -504,7 +523,7 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
   case OPK_D2B * 4 + b:                                                                   \
     if constexpr (b < R) {                                                                \
       const uint32_t t = ((gb >> qa) & 1u) ^ xa;                                          \
-      const uint32_t xb = (fx >> qc) & 1u;                                                \
+      const uint32_t xb = xc;                                                             \
       const cx<T> lo = t ? m01 : m00, hi = t ? m11 : m10;                                 \
       diag_bit<b, R>(v, w, xb ? hi : lo, xb ? lo : hi);                                   \
     }                                                                                     \
@@ -519,7 +538,7 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
       break;
     }
     case OPK_D2 * 4: {
-      const uint32_t xm = xa | (((fx >> qc) & 1u) << 1);
+      const uint32_t xm = xa | (xc << 1);
       d2_apply<R>(v, w, perm4(op, 0, xm), perm4(op, 1, xm), perm4(op, 2, xm), perm4(op, 3, xm), (gb >> qa) & 1u,
                   (gb >> qc) & 1u);
       break;
@@ -531,7 +550,7 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
 #define NT_D2RR(k)                                                                        \
   case OPK_D2RR * 4 + k:                                                                  \
     if constexpr (D2RR_PAIRS[k][1] < R) {                                                 \
-      const uint32_t xm = xa | (((fx >> qc) & 1u) << 1);                                  \
+      const uint32_t xm = xa | (xc << 1);                                  \
       const cx<T> e0 = perm4(op, 0, xm), e3 = perm4(op, 3, xm);                           \
       const cx<T> e1 = perm4(op, 1, xm), e2 = perm4(op, 2, xm);                           \
       const bool hi_a = am > bm;                                                          \

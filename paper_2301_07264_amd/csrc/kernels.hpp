@@ -23,7 +23,12 @@ template <typename T>
 struct DevOp {
   int32_t cls, qa, qb, rsel;
   T m[32];
+  // padding to a power of two (256 bytes for complex64 tables, 512 for
+  // complex128): the gate kernel addresses op o as base + (o << 8) with one
+  // shift instead of a 64-bit multiply
+  int32_t pad[sizeof(T) == 4 ? 28 : 60];
 };
+static_assert(sizeof(DevOp<float>) == 256 && sizeof(DevOp<double>) == 512, "op table stride");
 
 // Op dispatch codes: kind * 4 + register bit (kinds with a register
 // qubit) or kind * 4 (diagonal kinds without one).  G2 ops live in quad
