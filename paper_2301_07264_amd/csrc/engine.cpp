@@ -148,7 +148,7 @@ static int32_t op_code(const HostOp &h, int rbit) {
 // dense qubit for register-segment ops, tile-local positions for quad ops).
 template <typename T>
 static void upload_ops(DevPlan &dp, const std::vector<int32_t> &code, const std::vector<int32_t> &rsel,
-                       hipStream_t s) {
+                       const std::vector<char> &swap_ab, hipStream_t s) {
   const Plan &P = dp.plan;
   // two zero padding entries: the gate kernel loads the descriptor one past
   // a segment's last op
@@ -170,6 +170,15 @@ static void upload_ops(DevPlan &dp, const std::vector<int32_t> &code, const std:
     for (int i = 0; i < nent; ++i) {
       d.m[2 * i] = (T)h.m[i].real();
       d.m[2 * i + 1] = (T)h.m[i].imag();
+    }
+    if (swap_ab[o]) {
+      // two-qubit diagonal with qa on the higher register bit: the qubits
+      // trade roles, so the entries of local index b_qa + 2 b_qb = 1 and 2
+      // trade places
+      d.qa = h.qb;
+      d.qb = h.qa;
+      std::swap(d.m[2], d.m[4]);
+      std::swap(d.m[3], d.m[5]);
     }
   }
   dp.ops.ensure(ops.size() * sizeof(ntk::DevOp<T>));
@@ -219,6 +228,7 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
   std::vector<ntk::DevPass> dpass(P.passes.size());
   std::memset(dpass.data(), 0, dpass.size() * sizeof(ntk::DevPass));
   std::vector<int32_t> rsel(P.ops.size(), 0), code(P.ops.size(), 0);
+  std::vector<char> swap_ab(P.ops.size(), 0);
   for (size_t p = 0; p < P.passes.size(); ++p) {
     const Pass &ps = P.passes[p];
     std::vector<int> loc, nl;
@@ -264,6 +274,11 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
           if (h.cls == OPC_D2 && bm && !am) code[o] = ntk::OPK_D2B * 4 + __builtin_ctz((unsigned)bm);
           if (h.cls == OPC_D2 && am && bm) {
             const int lo = __builtin_ctz((unsigned)(am < bm ? am : bm)), hi = __builtin_ctz((unsigned)(am < bm ? bm : am));
+            // the kernel takes qa on the lower register bit
+            if (am > bm) {
+              swap_ab[o] = 1;
+              rsel[o] = bm | (am << 4);
+            }
             int k = 0;
             while (k < 6 && !(ntk::D2RR_PAIRS[k][0] == lo && ntk::D2RR_PAIRS[k][1] == hi)) ++k;
             if (k == 6) throw Error(NT_ERR_UNSUPPORTED, "internal: register-bit pair out of range");
@@ -306,8 +321,8 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
   dp->segs.ensure(segs.size() * sizeof(ntk::DevSeg));
   check_hip(hipMemcpyAsync(dp->segs.p, segs.data(), segs.size() * sizeof(ntk::DevSeg), hipMemcpyHostToDevice, stream),
             "upload segments");
-  if (pr == NT_C64) upload_ops<float>(*dp, code, rsel, stream);
-  else upload_ops<double>(*dp, code, rsel, stream);
+  if (pr == NT_C64) upload_ops<float>(*dp, code, rsel, swap_ab, stream);
+  else upload_ops<double>(*dp, code, rsel, swap_ab, stream);
 
   const size_t S = std::max<size_t>(P.app_site.size(), 1);
   std::vector<int32_t> ident(S);

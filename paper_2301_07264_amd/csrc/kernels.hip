@@ -360,11 +360,18 @@ DEV cx<T> lent(const OpLite<T> &h, int i) {
   return cx<T>{h.m[2 * i], h.m[2 * i + 1]};
 }
 
-// Entry i ^ xm of a 4-entry list, xm uniform in 0..3 (scalar selects).
+// Entries e[i] = entry i ^ xm of a 4-entry list, xm uniform in 0..3: two
+// rounds of conditional swaps (bit 0 of xm swaps within pairs, bit 1 swaps
+// the pairs), eight scalar selects instead of a select chain per entry.
 template <typename T>
-DEV cx<T> perm4(const OpLite<T> &h, int i, uint32_t xm) {
-  const cx<T> e0 = lent(h, i), e1 = lent(h, i ^ 1), e2 = lent(h, i ^ 2), e3 = lent(h, i ^ 3);
-  return xm == 0u ? e0 : (xm == 1u ? e1 : (xm == 2u ? e2 : e3));
+DEV void perm4(const OpLite<T> &h, uint32_t xm, cx<T> &e0, cx<T> &e1, cx<T> &e2, cx<T> &e3) {
+  const cx<T> a0 = lent(h, 0), a1 = lent(h, 1), a2 = lent(h, 2), a3 = lent(h, 3);
+  const bool s0 = (xm & 1u) != 0u, s1 = (xm & 2u) != 0u;
+  const cx<T> b0 = s0 ? a1 : a0, b1 = s0 ? a0 : a1, b2 = s0 ? a3 : a2, b3 = s0 ? a2 : a3;
+  e0 = s1 ? b2 : b0;
+  e1 = s1 ? b3 : b1;
+  e2 = s1 ? b0 : b2;
+  e3 = s1 ? b1 : b3;
 }
 
 // Diagonal whose phase is p1 on the slots with register bit B set and p0
@@ -429,7 +436,7 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
   const uint32_t xa = (fx >> qa) & 1u, za = (fz >> qa) & 1u;
   // rsel: register-bit masks of qa (bits 0..3) and qb (bits 4..7) in this
   // op's segment (0 when the qubit is not a register qubit), from the host.
-  const uint32_t am = (uint32_t)op.rsel & 15u, bm = ((uint32_t)op.rsel >> 4) & 15u;
+  const uint32_t bm = ((uint32_t)op.rsel >> 4) & 15u;
   const cx<T> m00 = lent(op, 0), m01 = lent(op, 1), m10 = lent(op, 2), m11 = lent(op, 3);
   // the frame-conjugated dense 2x2 (rows and columns permuted by x_a, the
   // off-diagonal entries negated by z_a)
@@ -489,6 +496,32 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
     cx_frame(za, qc, qa, cv, fx, fz);
     return;
   }
+  // Diagonal on two register qubits (qa on the lower register bit, the host
+  // orders them): the phase of slot group (b_qa, b_qb) is D[(b_qa, b_qb) ^
+  // (x_qa, x_qb)] under the frame.
+  const uint32_t d2k = (uint32_t)(code - OPK_D2RR * 4);
+  if (d2k < 6u) {
+    cx<T> e0, e1, e2, e3;
+    perm4(op, xa | (xc << 1), e0, e1, e2, e3);
+    switch (d2k) {
+#define NT_D2RR(k)                                                                               \
+  case k:                                                                                        \
+    if constexpr (D2RR_PAIRS[k][1] < R)                                                          \
+      diag2<D2RR_PAIRS[k][0], D2RR_PAIRS[k][1], R>(v, w, vpin(e0), vpin(e1), vpin(e2), vpin(e3)); \
+    break;
+      NT_D2RR(0)
+      NT_D2RR(1)
+      NT_D2RR(2)
+      NT_D2RR(3)
+      NT_D2RR(4)
+      default:
+        if constexpr (D2RR_PAIRS[5][1] < R)
+          diag2<D2RR_PAIRS[5][0], D2RR_PAIRS[5][1], R>(v, w, vpin(e0), vpin(e1), vpin(e2), vpin(e3));
+        break;
+#undef NT_D2RR
+    }
+    return;
+  }
   switch (code) {
 #define NT_G1(b)                                                                          \
   case OPK_G1R * 4 + b:                                                                   \
@@ -538,33 +571,11 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
       break;
     }
     case OPK_D2 * 4: {
-      const uint32_t xm = xa | (xc << 1);
-      d2_apply<R>(v, w, perm4(op, 0, xm), perm4(op, 1, xm), perm4(op, 2, xm), perm4(op, 3, xm), (gb >> qa) & 1u,
-                  (gb >> qc) & 1u);
+      cx<T> e0, e1, e2, e3;
+      perm4(op, xa | (xc << 1), e0, e1, e2, e3);
+      d2_apply<R>(v, w, e0, e1, e2, e3, (gb >> qa) & 1u, (gb >> qc) & 1u);
       break;
     }
-    // Both qubits in the registers.  Under the frame the phase of index g is
-    // D(g ^ x): entry i of the list becomes e_i = d[i ^ xm].  The body indexes
-    // by (lower register bit, higher register bit), so when qa holds the
-    // higher bit the two mixed entries trade places.
-#define NT_D2RR(k)                                                                        \
-  case OPK_D2RR * 4 + k:                                                                  \
-    if constexpr (D2RR_PAIRS[k][1] < R) {                                                 \
-      const uint32_t xm = xa | (xc << 1);                                  \
-      const cx<T> e0 = perm4(op, 0, xm), e3 = perm4(op, 3, xm);                           \
-      const cx<T> e1 = perm4(op, 1, xm), e2 = perm4(op, 2, xm);                           \
-      const bool hi_a = am > bm;                                                          \
-      diag2<D2RR_PAIRS[k][0], D2RR_PAIRS[k][1], R>(v, w, vpin(e0), vpin(hi_a ? e2 : e1),  \
-                                                   vpin(hi_a ? e1 : e2), vpin(e3));       \
-    }                                                                                     \
-    break;
-    NT_D2RR(0)
-    NT_D2RR(1)
-    NT_D2RR(2)
-    NT_D2RR(3)
-    NT_D2RR(4)
-    NT_D2RR(5)
-#undef NT_D2RR
     default:
       // the host only emits the codes above (it rejects anything else when
       // it builds the plan); no identity copy here, which the compiler would
