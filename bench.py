@@ -44,12 +44,12 @@ MEASURED_TRAFFIC = {
     ("ghz_qft_layers24", "c64", 32): {
         "bytes_per_launch": 8.416e9,
         "passes": 43,
-        "kernel_sha256": "2d59e6f5e14cc3ce0e57e30ffe199dcc31c3afc51c121cb4f8f2433ee0fd4ab4",
+        "kernel_sha256": "1cb2e86e906d1774e4af44faf26818dbf07d692fae89efb85b3d8532068555f3",
     },
     ("qaoa3reg30", "c64", 4): {
         "bytes_per_launch": 6.560e10,
         "passes": 11,
-        "kernel_sha256": "2d59e6f5e14cc3ce0e57e30ffe199dcc31c3afc51c121cb4f8f2433ee0fd4ab4",
+        "kernel_sha256": "1cb2e86e906d1774e4af44faf26818dbf07d692fae89efb85b3d8532068555f3",
     },
 }
 
