@@ -430,6 +430,57 @@ def test_gpu_error_paths(P, ctx):
     P.nt_circuit_free(h)
 
 
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_degenerate_circuits(P, ctx, orc, prec):
+    """Degenerate inputs: a circuit without gates (no sites, every
+    trajectory is |0..0>, the tolerable rate does not exist), one-qubit
+    circuits under no errors, some errors and every site fired, and a single
+    trajectory, against the oracle."""
+    pr = P.NT_C64 if prec == "c64" else P.NT_C128
+    tol_f = 2e-5 if prec == "c64" else 1e-12
+    tol_a = 1e-5 if prec == "c64" else 1e-12
+    P.nt_set_precision(ctx, pr)
+    # no gates
+    h = _load(P, W.Circuit(3, []))
+    P.nt_set_error_model(ctx, 0.1, 0.1, 0.1)
+    f = np.zeros(5)
+    cnt, pv = P.nt_run(ctx, h, 0, 0, 5, TAU, f)
+    assert cnt == 5 and pv == 1.0
+    np.testing.assert_array_equal(f, np.ones(5))
+    psi = P.nt_final_state(ctx, h, 0, 0, pr)
+    assert psi[0] == 1 and np.count_nonzero(psi) == 1
+    with pytest.raises(P.NtError) as ei:
+        P.nt_tolerable_rate(ctx, h, 0.66, 0.01, 1e-4, 1e-1, 0, 20, TAU)
+    assert ei.value.status == P.NT_ERR_NOT_BRACKETED
+    P.nt_circuit_free(h)
+    # one qubit, every one-qubit kind
+    rng = np.random.default_rng(8)
+    gates = []
+    for name in ("H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ", "U", "H", "RX"):
+        npar = W.GATE_NPARAM[name]
+        gates.append(W.Gate(name, (0,), tuple(float(x) for x in rng.uniform(0, 2 * np.pi, npar))))
+    c = W.Circuit(1, gates)
+    h = _load(P, c, cid=5)
+    for model in ((0.0, 0.0, 0.0), (0.1, 0.05, 0.15), (1 / 3, 1 / 3, 1 / 3)):
+        _say(f"one qubit, {prec}, model {model}")
+        P.nt_set_error_model(ctx, *model)
+        N = 40
+        f = np.zeros(N)
+        cnt, _ = P.nt_run(ctx, h, 2, 0, N, TAU, f)
+        f_o, c_o = orc.run(c, *model, 2, 0, N, TAU, cid=5)
+        assert float(np.abs(f - f_o).max()) <= tol_f
+        margin = np.abs(f_o - TAU) < tol_f
+        assert cnt == c_o or margin.any()
+        for t in (0, 1, 7):
+            psi = P.nt_final_state(ctx, h, 2, t, pr).astype(np.complex128)
+            assert _l2(psi, orc.final_state(c, *model, 2, t, cid=5)) <= tol_a
+        # a single trajectory
+        f1 = np.zeros(1)
+        P.nt_run(ctx, h, 2, 7, 1, TAU, f1)
+        assert abs(f1[0] - f_o[7]) <= tol_f
+    P.nt_circuit_free(h)
+
+
 # ---------------------------------------------------------------------------
 # Exact short-cuts (zero-fired trajectories, error-free checkpoints) give
 # bit-identical results to the plain run.
