@@ -99,7 +99,7 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_bytes, "copies": 3}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported "
               f"(trajectories would shard by range with one count all-reduce; not built).",
               file=sys.stderr)
         sys.exit(2)

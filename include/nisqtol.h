@@ -55,7 +55,7 @@ extern "C" {
 typedef enum nt_status {
   NT_OK = 0,
   NT_ERR_INVALID_ARG = 1,      /* bad argument; nothing was changed */
-  NT_ERR_UNSUPPORTED = 2,      /* valid request this build cannot serve */
+  NT_ERR_UNSUPPORTED = 2,      /* valid request the library cannot serve */
   NT_ERR_OUT_OF_MEMORY = 3,    /* size check failed before any allocation, or an allocation failed */
   NT_ERR_DEVICE = 4,           /* HIP runtime error; message carries hipGetErrorString */
   NT_ERR_BUFFER_TOO_SMALL = 5, /* required size returned through the size argument */
