@@ -25,10 +25,14 @@
  *   - Random draws: Philox4x64-10 (Salmon et al., SC'11), key = (seed,
  *     circuit id), counter = (site, trajectory, 0, 0).  A site fires iff
  *     word0 < floor((p_x+p_y+p_z) * 2^64) (always when the sum is >= 1); its
- *     Pauli is X if word1 < floor(p_x/sum * 2^64), else Y if
- *     word1 < floor((p_x+p_y)/sum * 2^64), else Z (a fraction >= 1 means
+ *     Pauli is X if word1 < c_X, else Y if word1 < c_XY, else Z.  When
+ *     p_x == p_y == p_z (the uniform model of every sweep and search),
+ *     c_X = floor(2^64 / 3) and c_XY = floor(2^64 * 2/3), the thresholds of
+ *     the correctly rounded doubles 1/3 and 2/3, at every rate; otherwise
+ *     c_X = floor(p_x/sum * 2^64) and c_XY = floor((p_x+p_y)/sum * 2^64),
+ *     each fraction rounded once in IEEE FP64 (a fraction >= 1 means
  *     "always").  Rates are not part of the counter, so the fired sets of one
- *     trajectory are nested across rates.
+ *     trajectory are nested across rates, with the same Pauli types.
  *   - Fidelity criterion: F = |<R|psi>|^2 / (<R|R><psi|psi>) against the
  *     error-free final state R of the same precision; a trajectory succeeds
  *     iff F >= tau (Sec. II criteria; Sec. IV-C).
@@ -117,7 +121,9 @@ nt_status nt_set_max_batch(nt_ctx *ctx, uint64_t max_batch);
 /* ---- circuits (host objects; ctx may be NULL) ---------------------------- */
 
 /* Copies gates[0..n_gates) after validating qubits (0 <= q < n, distinct for
- * two-qubit kinds), kinds, arity and matrices.  1 <= n_qubits <= 32. */
+ * two-qubit kinds), kinds, arity and matrices.  1 <= n_qubits <= 32.
+ * 0 <= n_gates <= 2^22 (NT_ERR_UNSUPPORTED above: the device event words
+ * hold an op index in 24 bits, and sites in 32-bit integers). */
 nt_status nt_circuit_load(nt_ctx *ctx, int n_qubits, const nt_gate *gates, int64_t n_gates,
                           nt_circuit **out);
 
@@ -268,7 +274,9 @@ nt_status nt_tolerable_rate_auto(nt_ctx *ctx, const nt_circuit *c, double P_targ
                                  uint64_t n_traj, double tau, double *p_star, int *n_coarse, int *n_full,
                                  double bracket_out[2]);
 
-/* Exact short-cuts for Monte Carlo runs (results stay bit-identical):
+/* Short-cuts for Monte Carlo runs.  ZERO_FIRED, CHECKPOINT and REUSE keep
+ * every value bit-identical to the full run; LAST_ERROR is exact in
+ * arithmetic only (see below):
  * NT_SHORTCUT_ZERO_FIRED -- a trajectory with no fired site ends in the
  *   error-free state, so its fidelity is 1 without simulating it (for the
  *   probability criteria: the error-free state's value, computed once);
@@ -278,8 +286,10 @@ nt_status nt_tolerable_rate_auto(nt_ctx *ctx, const nt_circuit *c, double P_targ
  * NT_SHORTCUT_LAST_ERROR -- a trajectory is scored right after the pass
  *   holding its last error, against the error-free state at that point: the
  *   rest of the circuit is one unitary applied to both states and leaves
- *   their overlap unchanged.  Exact in arithmetic; fidelities differ from
- *   the full run by rounding only (needs the checkpoints).
+ *   their overlap unchanged.  Exact in arithmetic only: fidelities differ
+ *   from the full run by rounding, so a trajectory within rounding of tau
+ *   can change sides and the success count can differ from the full run's
+ *   (needs the checkpoints).  Not bit-identical, unlike the other three.
  * NT_SHORTCUT_REUSE -- a trajectory's criterion value is kept after it is
  *   simulated and reused by later runs of the same circuit, seed, precision,
  *   criterion and short-cut flags whose error model has the same Pauli-type
@@ -409,9 +419,12 @@ nt_status nt_reference_state(nt_ctx *ctx, const nt_circuit *c, void *amps_out, i
  * algorithmic HBM bytes (each pass reads and writes every state once; the
  * first pass only writes; the scoring pass reads the state and the
  * reference), amplitude-updates (gates x amplitudes x trajectories) and
- * algorithmic floating-point operations (per amplitude: dense 2x2 14,
- * diagonal 6, controlled X 0, dense 4x4 30; the fused scoring 8).  Reading
- * synchronizes the stream. */
+ * algorithmic floating-point operations, counted per gate of the circuit
+ * whatever ops the plan fuses them into (per amplitude: a permutation with
+ * unit phases such as X, Y, CNOT or SWAP 0; a diagonal 6 per entry other
+ * than 1, averaged over the amplitudes, so RZ and RZZ 6, Z, S and T 3, CZ
+ * and CP 1.5; any other one-qubit gate 14, two-qubit gate 30; the fused
+ * scoring 8).  Reading synchronizes the stream. */
 nt_status nt_timing_enable(nt_ctx *ctx, int enable);
 nt_status nt_timing_reset(nt_ctx *ctx);
 nt_status nt_timing_read(nt_ctx *ctx, int64_t *n_launches, double *ms_total, double *bytes_total,

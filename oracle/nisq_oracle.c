@@ -407,19 +407,6 @@ static double fidelity(int n, const cplx *r, const cplx *psi) {
   return a * a / (nr * np);
 }
 
-static double fidelity_par(int n, const cplx *r, const cplx *psi) {
-  int64_t dim = (int64_t)1 << n;
-  double ovr = 0, ovi = 0, nr = 0, np = 0;
-#pragma omp parallel for schedule(static) reduction(+ : ovr, ovi, nr, np)
-  for (int64_t k = 0; k < dim; ++k) {
-    cplx t = conj(r[k]) * psi[k];
-    ovr += creal(t); ovi += cimag(t);
-    nr += creal(r[k]) * creal(r[k]) + cimag(r[k]) * cimag(r[k]);
-    np += creal(psi[k]) * creal(psi[k]) + cimag(psi[k]) * cimag(psi[k]);
-  }
-  return (ovr * ovr + ovi * ovi) / (nr * np);
-}
-
 double orc_fidelity(int n, const double *r_ri, const double *psi_ri) {
   return fidelity(n, (const cplx *)r_ri, (const cplx *)psi_ri);
 }
@@ -482,7 +469,7 @@ int orc_run(int n, int64_t G, const int32_t *kind, const int32_t *q0, const int3
     for (uint64_t i = 0; i < N && !err; ++i) {
       int64_t nf = orc_sample_trajectory(seed, cid, t0 + i, c.S, px, py, pz, fs, fp, c.S);
       run_trajectory(&c, 0, fs, fp, nf, psi, 1);
-      double F = fidelity_par(n, ref, psi);
+      double F = fidelity(n, ref, psi);
       if (fid_out) fid_out[i] = F;
       if (F >= tau) ++cnt;
     }
@@ -604,7 +591,7 @@ int orc_exhaustive(int n, int64_t G, const int32_t *kind, const int32_t *q0, con
       int32_t s = (int32_t)(i / 3);
       uint8_t pa = (uint8_t)(1 + i % 3);
       run_trajectory(&c, 0, &s, &pa, 1, psi, 1);
-      fid_out[i] = fidelity_par(n, ref, psi);
+      fid_out[i] = fidelity(n, ref, psi);
     }
     free(psi);
   } else {

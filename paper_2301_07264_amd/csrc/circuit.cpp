@@ -260,6 +260,35 @@ std::vector<HostOp> classify(const Circuit &c) {
   return ops;
 }
 
+// Algorithmic flops per amplitude of one gate, from its own matrix (a
+// complex multiply is 6 flops, a complex add 2):
+//   a permutation whose entries are 1, -1, i or -i (X, Y, CNOT, SWAP): 0;
+//   a diagonal: 6 for each entry other than 1, averaged over the amplitudes
+//     (RZ and RZZ 6, Z, S and T 3, CZ and CP 1.5: only |11> changes);
+//   any other one-qubit gate: 2 complex multiplies and 1 add per amplitude,
+//     14; any other two-qubit gate: 4 multiplies and 3 adds, 30.
+double gate_flops(const HostGate &g) {
+  const int d = g.nq == 1 ? 2 : 4;
+  bool diag = true, perm = true;
+  int nonunit = 0;
+  for (int r = 0; r < d; ++r) {
+    int nz = 0;
+    for (int s = 0; s < d; ++s) {
+      const cd v = g.m[r * d + s];
+      if (is_zero(v)) continue;
+      ++nz;
+      if (r != s) diag = false;
+      const bool unit_phase = (v == cd(1, 0) || v == cd(-1, 0) || v == cd(0, 1) || v == cd(0, -1));
+      if (!unit_phase) perm = false;
+    }
+    if (nz != 1) perm = false;
+    if (!(g.m[r * d + r] == cd(1, 0))) ++nonunit;
+  }
+  if (diag) return 6.0 * nonunit / d;
+  if (perm) return 0.0;
+  return g.nq == 1 ? 14.0 : 30.0;
+}
+
 uint32_t HostOp::need_mask() const {
   switch (cls) {
     case OPC_G1: case OPC_C1: return 1u << qa;

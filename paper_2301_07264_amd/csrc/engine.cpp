@@ -203,20 +203,11 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
   const int L = P.L, R = P.R;
   dp->nthreads = 1 << (L - R);
   const int SW = pr == NT_C64 ? 4 : 3;
-  // Algorithmic flops per amplitude of each op class (complex multiply 6,
-  // complex add 2): dense 2x2: (4 mul + 2 add) per pair -> 14 per amplitude;
-  // diagonal: 6; controlled X: a permutation, 0; dense 4x4: (16 mul + 12 add)
-  // per quad -> 30.
+  // Algorithmic flops per amplitude of each pass: the sum over its gates of
+  // each gate's own count (gate_flops), whatever ops the plan made of them.
   for (const Pass &ps : P.passes) {
     double f = 0;
-    for (int o = ps.op_begin; o < ps.op_end; ++o) {
-      switch (P.ops[o].cls) {
-        case OPC_G1: f += 14; break;
-        case OPC_D1: case OPC_D2: f += 6; break;
-        case OPC_C1: break;
-        case OPC_G2: f += 30; break;
-      }
-    }
+    for (int o = ps.op_begin; o < ps.op_end; ++o) f += gate_flops(c.gates[(size_t)P.ops[o].gate]);
     dp->pass_flops_per_amp.push_back(f);
   }
   dp->pass_of_op.assign(P.ops.size(), 0);
@@ -799,10 +790,13 @@ void Ctx::score_entries(const Circuit &c, DevPlan &dp, int B, const std::vector<
   run_entries(*this, c, dp, B, ev_stride, st, tau, fid_host);
 }
 
-// Monte Carlo run with the exact short-cuts: a trajectory with no fired site
-// has the reference state itself (F = 1 exactly, not simulated), and a
-// trajectory starts from the error-free checkpoint before the pass holding
-// its first error.  Results are bit-identical to the plain run.
+// Monte Carlo run with the short-cuts: a trajectory with no fired site has
+// the reference state itself (F = 1 exactly, not simulated), a trajectory
+// starts from the error-free checkpoint before the pass holding its first
+// error, and values of fired sets already simulated are reused; with these
+// the results are bit-identical to the plain run.  The last-error short-cut
+// (scoring right after the pass of the last error) is exact in arithmetic
+// only: its fidelities differ from the plain run's by rounding.
 void Ctx::run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
                        uint64_t *count_out, double *sum_out) {
   DevPlan &dp = plan_for(c, prec);

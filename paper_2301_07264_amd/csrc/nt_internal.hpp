@@ -99,6 +99,7 @@ int kind_from_name(const std::string &s);
 Circuit *load_circuit(int n, const nt_gate *gates, int64_t G);
 Circuit *load_circuit_text(const char *path);
 std::vector<HostOp> classify(const Circuit &c);
+double gate_flops(const HostGate &g);   // algorithmic flops per amplitude
 
 // plan.cpp
 Plan make_plan(const Circuit &c, int max_tile_qubits, int max_reg, int cfix);

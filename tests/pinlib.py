@@ -199,3 +199,45 @@ def ghz_chain_all_fired(n, pauli):
     if pauli == "Z":
         return {0: h, full: -h}
     raise ValueError(pauli)
+
+
+# ---------------------------------------------------------------------------
+# Tensor-network simulator for large states (n ~ 20-22), independent of the
+# oracle's index-bit loops: the state is an n-axis array of shape (2,)*n
+# (numpy's C order puts qubit n-1 on axis 0, so qubit q is axis n-1-q), and a
+# gate is a tensordot of its local unitary with the axes of its qubits.
+
+def _axis(n, q):
+    return n - 1 - q
+
+
+def tn_apply(psi, n, qubits, U):
+    """Apply a local unitary (2x2, or 4x4 on local index b_q0 + 2 b_q1)."""
+    t = psi.reshape((2,) * n)
+    if len(qubits) == 1:
+        ax = _axis(n, qubits[0])
+        out = np.tensordot(U, t, axes=([1], [ax]))
+        out = np.moveaxis(out, 0, ax)
+    else:
+        a, b = _axis(n, qubits[0]), _axis(n, qubits[1])
+        # local index i = b_q0 + 2 b_q1 -> reshaped U4[b1_out, b0_out, b1_in, b0_in]
+        U4 = np.asarray(U).reshape(2, 2, 2, 2)
+        out = np.tensordot(U4, t, axes=([2, 3], [b, a]))
+        out = np.moveaxis(out, [0, 1], [b, a])
+    return np.ascontiguousarray(out).reshape(-1)
+
+
+def tn_simulate(circuit, fired=None, init_index=0):
+    """Final state; fired: {site: pauli code} with sites in gate order, then
+    listed-qubit order."""
+    n = circuit.n
+    psi = np.zeros(1 << n, complex)
+    psi[init_index] = 1
+    s = 0
+    for g in circuit.gates:
+        psi = tn_apply(psi, n, list(g.qubits), gate_unitary(g.name, g.params, g.matrix))
+        for q in g.qubits:
+            if fired and s in fired:
+                psi = tn_apply(psi, n, [q], PAULI[fired[s]])
+            s += 1
+    return psi
