@@ -6,9 +6,14 @@ different sizes in shared launches).
   * against the CPU oracle, on the batched workload's first 32 instances
     (n in 10..20, 336..2592 gates, circuit id = instance seed): every
     instance with n <= 16 at trajectories [0, 8), and the n = 17, 18 ones at
-    [0, 2); fidelities within 1e-12 (c128) / 2e-5 (c64), equal success
-    counts outside the margin of the precision's fidelity error around tau.
+    [0, 2), computed here; the n = 19, 20 ones at [0, 2) against stored
+    oracle values (tests/golden/config2_oracle_large.json, written by
+    tests/golden/make_config2_golden.py, which calls only the oracle);
+    fidelities within 1e-12 (c128) / 2e-5 (c64), equal success counts
+    outside the margin of the precision's fidelity error around tau.
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -99,8 +104,15 @@ def test_batch_device_output_and_criteria(P, ctx):
 _ORACLE_CACHE = {}
 
 
+GOLD2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config2_oracle_large.json")
+
+
 def _oracle_subset(orc):
     if not _ORACLE_CACHE:
+        with open(GOLD2) as f:
+            gold = json.load(f)
+        assert gold["p"] == P_ERR and gold["seed"] == 0
+        stored = {g["circuit_seed"]: g for g in gold["instances"]}
         for s in range(32):
             c = W.config2(s)
             if c.n <= 16:
@@ -108,6 +120,9 @@ def _oracle_subset(orc):
             elif c.n <= 18:
                 nt = 2
             else:
+                g = stored[s]
+                assert (g["n"], g["G"], g["S"]) == (c.n, c.G, c.S)
+                _ORACLE_CACHE[s] = np.asarray(g["F"])
                 continue
             fid, _ = orc.run(c, P_ERR / 3, P_ERR / 3, P_ERR / 3, 0, 0, nt, TAU, cid=s)
             _ORACLE_CACHE[s] = fid
