@@ -76,6 +76,8 @@ def lib():
         L.orc_tolerable_rate.restype = i32
         L.orc_exhaustive.argtypes = circ + [i32, P]
         L.orc_exhaustive.restype = i32
+        L.orc_tolerable_rate_fig3.argtypes = circ + [dbl, dbl, u64, u64, u64, dbl, i32, P, P, P, P]
+        L.orc_tolerable_rate_fig3.restype = i32
         L.orc_eq4.argtypes = [P, dbl, P]
         L.orc_eq4.restype = dbl
         L.orc_eq5.argtypes = [dbl, P, dbl, dbl]
@@ -236,6 +238,20 @@ def tolerable_rate(circuit, P_target, tol, p_lo, p_hi, seed, N, tau, cid: int = 
     rc = lib().orc_tolerable_rate(*oc.args(), P_target, tol, p_lo, p_hi, seed, cid, N, tau,
                                   nthreads, _p(ps), _p(npb))
     return rc, float(ps[0]), int(npb[0])
+
+
+def tolerable_rate_fig3(circuit, P_target, tol, seed, N, tau, cid: int = 0, nthreads: int = 0):
+    """The paper's steps (exhaustive first, Eq. 5 or Monte Carlo at increasing
+    rates).  Returns (status, p_star, method, n_probes, [P_X, P_Y, P_Z, P_R]);
+    status 1 = not bracketed, method 0 = Eq. 5, 1 = Monte Carlo."""
+    oc = OCircuit(circuit)
+    ps = np.zeros(1, np.float64)
+    meth = np.zeros(1, np.int32)
+    npb = np.zeros(1, np.int32)
+    p4 = np.zeros(4, np.float64)
+    rc = lib().orc_tolerable_rate_fig3(*oc.args(), P_target, tol, seed, cid, N, tau, nthreads,
+                                       _p(ps), _p(meth), _p(npb), _p(p4))
+    return rc, float(ps[0]), int(meth[0]), int(npb[0]), p4
 
 
 def exhaustive(circuit, nthreads: int = 0) -> np.ndarray:

@@ -613,6 +613,91 @@ int orc_exhaustive(int n, int64_t G, const int32_t *kind, const int32_t *q0, con
   return 0;
 }
 
+double orc_eq5(double P_target, const double P_e[3], double P_R, double units);
+
+/* Tolerable uniform rate by the paper's steps (Sec. IV-D, Fig. 3), fidelity
+ * criterion:
+ *   1. exhaustive single-error simulation (Sec. IV-B.1): the success
+ *      probability P_e of the states with one error of type e, and P_R = 1;
+ *   2. success evaluation at one average error: by Eq. 4 with E(N_e) = 1/3
+ *      for each type, P1 = sum_e P_e / 3;
+ *   3. P1 <= P*: at most one error is tolerable, and Eq. 5 gives the rate,
+ *      with the S error locations as its units (the paper writes G);
+ *   4. otherwise Monte Carlo at increasing rates p_k = 2^k / S (one average
+ *      error at k = 0) while the success probability stays at or above P*;
+ *      a rate within tol of P* is the answer, else orc_tolerable_rate
+ *      searches between the last two rates.  (If the success probability at
+ *      1/S is already below P*, the rates decrease by halves instead until
+ *      it is not.)
+ * method: 0 = Eq. 5, 1 = Monte Carlo; P4 (may be NULL): P_e (X, Y, Z), P_R.
+ * Returns 0, 1 if no rate in [1e-9, 0.5] brackets P* (or P_R < P*), or an
+ * error code of the runs. */
+int orc_tolerable_rate_fig3(int n, int64_t G, const int32_t *kind, const int32_t *q0, const int32_t *q1,
+                            const double *params, const double *umats, double P_target, double tol,
+                            uint64_t seed, uint64_t cid, uint64_t N, double tau, int nthreads,
+                            double *p_star, int *method, int *n_probes, double *P4) {
+  int64_t S = 0;
+  for (int64_t g = 0; g < G; ++g) S += kind_arity(kind[g]);
+  *n_probes = 0;
+  if (S == 0) return 1;
+  double *fe = (double *)malloc(sizeof(double) * (size_t)(3 * S));
+  if (!fe) return -2;
+  int rc = orc_exhaustive(n, G, kind, q0, q1, params, umats, nthreads, fe);
+  if (rc) { free(fe); return rc; }
+  double P_e[3];
+  for (int e = 0; e < 3; ++e) {
+    double cnt = 0;
+    for (int64_t s = 0; s < S; ++s) cnt += fe[3 * s + e] >= tau ? 1.0 : 0.0;
+    P_e[e] = cnt / (double)S;
+  }
+  free(fe);
+  const double P_R = 1.0 >= tau ? 1.0 : 0.0;
+  if (P4) { P4[0] = P_e[0]; P4[1] = P_e[1]; P4[2] = P_e[2]; P4[3] = P_R; }
+  if (P_R < P_target) return 1;
+  const double P1 = (P_e[0] + P_e[1] + P_e[2]) / 3.0;
+  if (P1 <= P_target && P1 != P_R) {
+    *method = 0;
+    *p_star = orc_eq5(P_target, P_e, P_R, (double)S);
+    return 0;
+  }
+  *method = 1;
+  int probes = 0;
+  double p = 1.0 / (double)S;
+  double P = mc_success(n, G, kind, q0, q1, params, umats, p, seed, cid, N, tau, nthreads, &rc);
+  if (rc) return rc;
+  ++probes;
+  double lo, hi;
+  if (fabs(P - P_target) <= tol) { *p_star = p; *n_probes = probes; return 0; }
+  if (P >= P_target) {
+    for (;;) {
+      lo = p;
+      p *= 2.0;
+      if (p > 0.5) { *n_probes = probes; return 1; }
+      P = mc_success(n, G, kind, q0, q1, params, umats, p, seed, cid, N, tau, nthreads, &rc);
+      if (rc) return rc;
+      ++probes;
+      if (fabs(P - P_target) <= tol) { *p_star = p; *n_probes = probes; return 0; }
+      if (P < P_target) { hi = p; break; }
+    }
+  } else {
+    for (;;) {
+      hi = p;
+      p *= 0.5;
+      if (p < 1e-9) { *n_probes = probes; return 1; }
+      P = mc_success(n, G, kind, q0, q1, params, umats, p, seed, cid, N, tau, nthreads, &rc);
+      if (rc) return rc;
+      ++probes;
+      if (fabs(P - P_target) <= tol) { *p_star = p; *n_probes = probes; return 0; }
+      if (P >= P_target) { lo = p; break; }
+    }
+  }
+  int k = 0;
+  rc = orc_tolerable_rate(n, G, kind, q0, q1, params, umats, P_target, tol, lo, hi, seed, cid, N, tau, nthreads,
+                          p_star, &k);
+  *n_probes = probes + k;
+  return rc;
+}
+
 /* Eq. 4 with per-type single-error success probabilities P_e (e = X, Y, Z),
  * the error-free success P_R, and expected error counts E_e. */
 double orc_eq4(const double P_e[3], double P_R, const double E_e[3]) {

@@ -519,3 +519,67 @@ def test_heavy_output_quantum_volume(orc):
     v = orc.run_criterion(c, 0.25, 0.25, 0.25, 0, 0, 400, 2)
     # 400 trajectories of a fully scrambled state: mean 1/2 within ~5 sigma
     assert abs(v.mean() - 0.5) < 0.05
+
+
+# --------------------------------------------------------------------------
+# The paper's tolerable-rate steps (Sec. IV-D, Fig. 3): exhaustive simulation
+# first, Eq. 5 when at most one error is tolerable, else Monte Carlo at
+# increasing rates.
+
+def _single_error_success(circ, tau):
+    """P_e (X, Y, Z) from brute-force single-error states (Kronecker sims)."""
+    ops = pinlib.circuit_unitaries(circ)
+    S = len(pinlib.site_list(circ))
+    ref = pinlib.simulate_pattern(circ, [0] * S, ops)
+    P = []
+    for e in (1, 2, 3):
+        ok = 0
+        for s in range(S):
+            pat = [0] * S
+            pat[s] = e
+            ok += pinlib.fid(ref, pinlib.simulate_pattern(circ, pat, ops)) >= tau
+        P.append(ok / S)
+    return np.array(P), S
+
+
+def test_fig3_eq5_branch_vs_bruteforce(orc):
+    rng = np.random.default_rng(21)
+    c = W.random_layers(3, 2, rng)
+    tau, Pt = 0.9, 0.66
+    P_e, S = _single_error_success(c, tau)
+    P1 = P_e.mean()
+    assert P1 <= Pt            # this circuit tolerates at most one error on average
+    rc, p, method, probes, p4 = orc.tolerable_rate_fig3(c, Pt, 0.01, 0, 1000, tau)
+    assert rc == 0 and method == 0 and probes == 0
+    np.testing.assert_array_equal(p4[:3], P_e)
+    assert p4[3] == 1.0
+    want = (Pt - 1.0) / (P1 - 1.0) / S          # Eq. 5 with S error locations
+    assert abs(p - want) <= 1e-15 * want
+    assert p <= 1.0 / S                          # the corollary of Eq. 5 (Sec. IV-D)
+
+
+def test_fig3_monte_carlo_branch_vs_exact_root(orc):
+    from scipy.optimize import brentq
+    # Two qubits, each prepared with Bloch vector (1, 1, 1)/sqrt(3), then
+    # identity rotations (more error sites, no change of state): any Pauli
+    # on one qubit leaves F = 1/3, on both F = 1/9.  With tau = 0.3 every
+    # single error is tolerated (P1 = 1), so the steps go to Monte Carlo.
+    th = math.acos(1 / math.sqrt(3))
+    g = []
+    for q in (0, 1):
+        g.append(W.Gate("U", (q,), (math.pi / 4, th, 0.0)))
+        g += [W.Gate("RZ", (q,), (0.0,)) for _ in range(3)]
+    c = W.Circuit(2, g)
+    tau, Pt, tol, N = 0.3, 0.66, 0.01, 20000
+    P_e, S = _single_error_success(c, tau)
+    assert P_e.tolist() == [1.0, 1.0, 1.0]
+    rc, p, method, probes, p4 = orc.tolerable_rate_fig3(c, Pt, tol, 5, N, tau)
+    assert rc == 0 and method == 1 and probes >= 2
+    assert p4.tolist() == [1.0, 1.0, 1.0, 1.0]
+    cw = pinlib.enumerate_success_weights(c, tau)
+    P_exact = pinlib.success_poly(cw, S, p)
+    sigma = math.sqrt(Pt * (1 - Pt) / N)
+    assert abs(P_exact - Pt) <= tol + 5 * sigma
+    root = brentq(lambda x: pinlib.success_poly(cw, S, x) - Pt, 1e-6, 0.5)
+    assert root > 1.0 / S          # more than one error on average is tolerable
+    assert abs(math.log10(p / root)) < 0.05
