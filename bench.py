@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--eval-circuits", type=int, default=16)
     ap.add_argument("--batch", type=int, default=0, help="trajectories per step (0: 32 for 24 qubits, 4 for 30)")
     ap.add_argument("--prec", choices=["c64", "c128"], default="c64")
+    ap.add_argument("--fusion", type=int, choices=[0, 1, 2], default=0,
+                    help="gate fusion of the plan: 0 automatic, 1 none, 2 two-qubit blocks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-traj", type=int, default=1, help="oracle trajectories timed on the host")
     ap.add_argument("--traffic", type=str, default=None,
@@ -133,9 +135,11 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = P.nt_create(0, stream.cuda_stream)
     h = P.nt_circuit_load(ctx, circ)
+    P.nt_circuit_set_fusion(h, prec, args.fusion)
     P.nt_set_precision(ctx, prec)
     P.nt_set_max_batch(ctx, B)
     n_pass, n_seg, L = P.nt_plan_info(h, prec)
+    n_ops, n_blocks = P.nt_plan_ops(h, prec)
 
     fid_dev = torch.empty(B, dtype=torch.float64, device="cuda:0")
     state = {"t": 0, "step": 0, "count": 0}
@@ -285,7 +289,8 @@ def main():
         "config": {"workload": wl,
                    "trajectories_per_step": B, "n_qubits": n, "gates": G, "sites": S,
                    "amplitudes": args.prec, "passes_per_trajectory": n_pass, "segments": n_seg,
-                   "tile_qubits": L, "parallelism": "single GPU, trajectory batch"},
+                   "tile_qubits": L, "ops_per_trajectory": n_ops, "fused_blocks": n_blocks,
+                   "parallelism": "single GPU, trajectory batch"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_tolerable_rate": ttr,
@@ -379,6 +384,7 @@ def bench_batch(args, P, W):
     for s, c in enumerate(circs):
         h = P.nt_circuit_load(ctx, c)
         P.nt_circuit_set_id(h, s)
+        P.nt_circuit_set_fusion(h, prec, args.fusion)
         hs.append(h)
     P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
     vals = torch.empty(n_circ, N, dtype=torch.float64, device="cuda:0")

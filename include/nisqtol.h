@@ -150,6 +150,16 @@ nt_status nt_circuit_set_id(nt_circuit *c, uint64_t circuit_id);
  * range. */
 nt_status nt_circuit_set_tile(nt_circuit *c, int prec, int tile_qubits);
 
+/* Gate fusion of the circuit's plan at precision `prec`: 0 = automatic
+ * (currently two-qubit blocks), 1 = none (one op per gate), 2 = two-qubit
+ * blocks: a CNOT takes the one-qubit gate just before it on its target and
+ * on its control into one op (both qubits then sit in registers).  An error
+ * after one of the block's one-qubit gates still acts right after that gate
+ * (Sec. IV-B): it enters the Pauli frame before the block's CNOT is applied
+ * to the frame.  Results change at rounding level only.
+ * NT_ERR_INVALID_ARG for other widths. */
+nt_status nt_circuit_set_fusion(nt_circuit *c, int prec, int width);
+
 /* Autotuner: runs n_traj trajectories (seed, current error model) with each
  * allowed tile width from the largest down to two below it, keeps the
  * fastest as the circuit's tile width (nt_circuit_set_tile) and returns it.
@@ -164,12 +174,18 @@ nt_status nt_autotune(nt_ctx *ctx, nt_circuit *c, uint64_t seed, uint64_t n_traj
 nt_status nt_plan_info(const nt_circuit *c, int prec, int *n_passes, int *n_segments,
                        int *tile_qubits);
 
-/* Host-only export of that plan, for checking it: for each op in application
- * order its gate index, pass and segment (arrays of n_gates); the local-qubit
- * mask of each pass (n_passes) and the register-qubit mask of each segment
- * (n_segments).  Any pointer may be NULL; sizes must match nt_plan_info. */
+/* Host-only export of that plan, for checking it: for each gate in
+ * application order its gate index, pass and segment (arrays of n_gates; the
+ * gates of a fused block appear in the order the block applies them); the
+ * local-qubit mask of each pass (n_passes) and the register-qubit mask of
+ * each segment (n_segments).  Any pointer may be NULL; sizes must match
+ * nt_plan_info. */
 nt_status nt_plan_export(const nt_circuit *c, int prec, int32_t *op_gate, int32_t *op_pass,
                          int32_t *op_segment, uint64_t *pass_local_mask, uint64_t *segment_reg_mask);
+
+/* Host-only: ops the plan runs per trajectory (a fused block counts once)
+ * and the number of fused blocks. */
+nt_status nt_plan_ops(const nt_circuit *c, int prec, int64_t *n_ops, int64_t *n_fused);
 
 /* ---- success criterion (Sec. II, Sec. V) ----------------------------------- */
 
@@ -273,6 +289,30 @@ nt_status nt_tolerable_rate(nt_ctx *ctx, const nt_circuit *c, double P_target, d
 nt_status nt_tolerable_rate_auto(nt_ctx *ctx, const nt_circuit *c, double P_target, double tol, uint64_t seed,
                                  uint64_t n_traj, double tau, double *p_star, int *n_coarse, int *n_full,
                                  double bracket_out[2]);
+
+/* Tolerable uniform rate by the paper's steps (Sec. IV-D, Fig. 3), for the
+ * fidelity criterion:
+ *   1. exhaustive single-error simulation (nt_exhaustive): P_e per Pauli
+ *      type, P_R of the error-free state;
+ *   2. the success probability at one average error, by Eq. 4 with
+ *      E(N_e) = 1/3 per type: P1 = (P_X + P_Y + P_Z) / 3;
+ *   3. if P1 <= P_target, at most one error is tolerable and Eq. 5 gives the
+ *      rate (nt_eq5 with the S error locations as units): *method = 0, no
+ *      Monte Carlo run;
+ *   4. otherwise Monte Carlo at increasing rates 2^k / S, k = 0, 1, ...
+ *      (trajectories [0, n_traj), uniform model) while the success
+ *      probability stays at or above P_target (by halves below 1/S when it
+ *      is already under the target there); a rate within tol is the answer,
+ *      else nt_tolerable_rate searches between the last two rates
+ *      (the paper's Powell search, read as in nt_tolerable_rate):
+ *      *method = 1.
+ * n_probes (may be NULL): Monte Carlo evaluations, including the search's.
+ * P_single (may be NULL): P_X, P_Y, P_Z, P_R from step 1.
+ * NT_ERR_NOT_BRACKETED when P_R < P_target or no rate in [1e-9, 0.5]
+ * brackets the target; NT_ERR_UNSUPPORTED for the measurement criteria. */
+nt_status nt_tolerable_rate_fig3(nt_ctx *ctx, const nt_circuit *c, double P_target, double tol, uint64_t seed,
+                                 uint64_t n_traj, double tau, double *p_star, int *method, int *n_probes,
+                                 double P_single[4]);
 
 /* Short-cuts for Monte Carlo runs.  ZERO_FIRED, CHECKPOINT and REUSE keep
  * every value bit-identical to the full run; LAST_ERROR is exact in

@@ -43,14 +43,14 @@ EXPORTED = [
     "nt_create", "nt_destroy", "nt_set_error_model", "nt_set_precision", "nt_set_max_batch",
     "nt_circuit_load", "nt_circuit_load_text", "nt_circuit_free", "nt_circuit_info",
     "nt_circuit_set_id", "nt_plan_info", "nt_plan_export", "nt_run", "nt_sweep", "nt_tolerable_rate",
-    "nt_tolerable_rate_auto",
+    "nt_tolerable_rate_auto", "nt_tolerable_rate_fig3",
     "nt_sample_sites", "nt_final_state", "nt_reference_state", "nt_timing_enable",
     "nt_timing_reset", "nt_timing_read", "nt_last_error", "nt_version",
     "nt_set_shortcuts", "nt_exhaustive", "nt_eq4", "nt_eq5", "nt_success_probability",
     "nt_set_criterion", "nt_run_batch",
     "nt_gnn_create", "nt_gnn_destroy", "nt_gnn_graph", "nt_gnn_params", "nt_gnn_set_params",
     "nt_gnn_set_data", "nt_gnn_loss_grad", "nt_gnn_train", "nt_gnn_predict", "nt_tolerable_rate_guided",
-    "nt_circuit_set_tile", "nt_autotune",
+    "nt_circuit_set_tile", "nt_circuit_set_fusion", "nt_autotune", "nt_plan_ops",
 ]
 
 GNN_RATES = [10.0 ** (-5.0 + j / 4.0) for j in range(13)]
@@ -113,6 +113,7 @@ def lib() -> C.CDLL:
         "nt_sweep": ([P, P, P, i32, u64, u64, dbl, P], i32),
         "nt_tolerable_rate": ([P, P, dbl, dbl, dbl, dbl, u64, u64, dbl, P, P], i32),
         "nt_tolerable_rate_auto": ([P, P, dbl, dbl, u64, u64, dbl, P, P, P, P], i32),
+        "nt_tolerable_rate_fig3": ([P, P, dbl, dbl, u64, u64, dbl, P, P, P, P], i32),
         "nt_sample_sites": ([P, P, u64, u64, u64, P, P, P, i64, P], i32),
         "nt_final_state": ([P, P, u64, u64, P, i64], i32),
         "nt_reference_state": ([P, P, P, i64], i32),
@@ -133,6 +134,8 @@ def lib() -> C.CDLL:
         "nt_gnn_predict": ([P, P, i32, i32, P], i32),
         "nt_tolerable_rate_guided": ([P, P, P, dbl, dbl, u64, u64, dbl, P, P, P], i32),
         "nt_circuit_set_tile": ([P, i32, i32], i32),
+        "nt_circuit_set_fusion": ([P, i32, i32], i32),
+        "nt_plan_ops": ([P, i32, P, P], i32),
         "nt_autotune": ([P, P, u64, u64, P, P], i32),
         "nt_exhaustive": ([P, P, dbl, P, P, P], i32),
         "nt_eq4": ([P, dbl, P, P], i32),
@@ -285,6 +288,7 @@ def nt_run(ctx, circ, seed: int, traj_begin: int, n_traj: int, tau: float,
     return cnt.value, p.value
 
 
+
 def nt_run_batch(ctx, circs, seed: int, traj_begin: int, n_traj: int, tau: float,
                  vals_out: Optional[np.ndarray] = None, vals_out_ptr: Optional[int] = None):
     """Many circuits at once.  Returns (counts[n_circ], p[n_circ]).  vals_out:
@@ -327,6 +331,19 @@ def nt_tolerable_rate_auto(ctx, circ, P_target: float, tol: float, seed: int, n_
     _check(lib().nt_tolerable_rate_auto(ctx, circ, P_target, tol, seed, n_traj, tau, C.byref(ps), C.byref(kc),
                                         C.byref(kf), br))
     return ps.value, kc.value, kf.value, (br[0], br[1])
+
+
+def nt_tolerable_rate_fig3(ctx, circ, P_target: float, tol: float, seed: int, n_traj: int, tau: float):
+    """The paper's steps: exhaustive simulation, then Eq. 5 or Monte Carlo at
+    increasing rates.  Returns (p_star, method, Monte Carlo evaluations,
+    [P_X, P_Y, P_Z, P_R]); method 0 = Eq. 5, 1 = Monte Carlo."""
+    ps = C.c_double()
+    meth = C.c_int()
+    k = C.c_int()
+    p4 = np.zeros(4, np.float64)
+    _check(lib().nt_tolerable_rate_fig3(ctx, circ, P_target, tol, seed, n_traj, tau, C.byref(ps), C.byref(meth),
+                                        C.byref(k), _ptr(p4)))
+    return ps.value, meth.value, k.value, p4
 
 
 def nt_sample_sites(ctx, circ, seed: int, traj_begin: int, n_traj: int, cap: Optional[int] = None):
@@ -507,6 +524,17 @@ def nt_tolerable_rate_guided(ctx, circ, m, P_target: float, tol: float, seed: in
 
 def nt_circuit_set_tile(circ, prec: int, tile_qubits: int) -> None:
     _check(lib().nt_circuit_set_tile(circ, prec, tile_qubits))
+
+
+def nt_plan_ops(circ, prec: int):
+    """Returns (ops run per error-free trajectory, fused blocks)."""
+    a, b = C.c_int64(), C.c_int64()
+    _check(lib().nt_plan_ops(circ, prec, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def nt_circuit_set_fusion(circ, prec: int, width: int) -> None:
+    _check(lib().nt_circuit_set_fusion(circ, prec, width))
 
 
 def nt_autotune(ctx, circ, seed: int, n_traj: int):

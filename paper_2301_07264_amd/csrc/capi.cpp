@@ -156,6 +156,15 @@ nt_status nt_circuit_set_tile(nt_circuit *c, int prec, int tile_qubits) {
   return NT_OK;
 }
 
+nt_status nt_circuit_set_fusion(nt_circuit *c, int prec, int width) {
+  if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
+  if (prec != NT_C64 && prec != NT_C128) return fail(NT_ERR_INVALID_ARG, "precision must be NT_C64 or NT_C128");
+  if (width < 0 || width > 2) return fail(NT_ERR_INVALID_ARG, "fusion width must be 0, 1 or 2");
+  c->impl->fuse_width[prec == NT_C64 ? 1 : 2] = width;
+  g_last_error.clear();
+  return NT_OK;
+}
+
 nt_status nt_autotune(nt_ctx *ctx, nt_circuit *c, uint64_t seed, uint64_t n_traj, int *tile_out, double *ms_out) {
   nt_status s = check_run_args(ctx, c, 0.9);
   if (s) return s;
@@ -202,12 +211,23 @@ nt_status nt_plan_info(const nt_circuit *c, int prec, int *n_passes, int *n_segm
   });
 }
 
+nt_status nt_plan_ops(const nt_circuit *c, int prec, int64_t *n_ops, int64_t *n_fused) {
+  if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
+  if (prec != NT_C64 && prec != NT_C128) return fail(NT_ERR_INVALID_ARG, "precision must be NT_C64 or NT_C128");
+  return guard([&] {
+    nt::Plan P = nt::choose_plan(*c->impl, prec);
+    if (n_ops) *n_ops = (int64_t)P.ops.size();
+    if (n_fused) *n_fused = P.n_fused;
+  });
+}
+
 nt_status nt_plan_export(const nt_circuit *c, int prec, int32_t *op_gate, int32_t *op_pass, int32_t *op_segment,
                          uint64_t *pass_local_mask, uint64_t *segment_reg_mask) {
   if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
   if (prec != NT_C64 && prec != NT_C128) return fail(NT_ERR_INVALID_ARG, "precision must be NT_C64 or NT_C128");
   return guard([&] {
     nt::Plan P = nt::choose_plan(*c->impl, prec);
+    size_t k = 0;   // gates in application order
     for (size_t p = 0; p < P.passes.size(); ++p) {
       const nt::Pass &ps = P.passes[p];
       if (pass_local_mask) pass_local_mask[p] = ps.local_mask;
@@ -217,9 +237,14 @@ nt_status nt_plan_export(const nt_circuit *c, int prec, int32_t *op_gate, int32_
         for (int q : sg.reg_q) m |= 1ull << q;
         if (segment_reg_mask) segment_reg_mask[s] = m;
         for (int o = sg.op_begin; o < sg.op_end; ++o) {
-          if (op_gate) op_gate[o] = P.ops[o].gate;
-          if (op_pass) op_pass[o] = (int32_t)p;
-          if (op_segment) op_segment[o] = s;
+          const nt::HostOp &h = P.ops[o];
+          for (int g : {h.pre[0], h.pre[1], h.gate}) {   // a fused block: its three gates
+            if (g < 0) continue;
+            if (op_gate) op_gate[k] = g;
+            if (op_pass) op_pass[k] = (int32_t)p;
+            if (op_segment) op_segment[k] = s;
+            ++k;
+          }
         }
       }
     }
@@ -440,6 +465,97 @@ nt_status nt_tolerable_rate_auto(nt_ctx *ctx, const nt_circuit *c, double P_targ
   s = search(side, 1, n_traj, &kf);
   if (s == NT_ERR_NOT_BRACKETED) s = search(wide, 4, n_traj, &kf);
   return finish(s);
+}
+
+nt_status nt_tolerable_rate_fig3(nt_ctx *ctx, const nt_circuit *c, double P_target, double tol, uint64_t seed,
+                                 uint64_t n_traj, double tau, double *p_star, int *method, int *n_probes,
+                                 double P_single[4]) {
+  nt_status s = check_run_args(ctx, c, tau);
+  if (s) return s;
+  if (!p_star) return fail(NT_ERR_INVALID_ARG, "p_star is NULL");
+  if (!(P_target > 0 && P_target < 1) || !(tol >= 0)) return fail(NT_ERR_INVALID_ARG, "need 0 < P_target < 1, tol >= 0");
+  if (n_traj == 0) return fail(NT_ERR_INVALID_ARG, "n_traj must be > 0");
+  if (ctx->impl->crit != NT_CRIT_FIDELITY)
+    return fail(NT_ERR_UNSUPPORTED, "the tolerable-rate steps use the fidelity criterion");
+  int probes = 0, meth = -1;
+  if (n_probes) *n_probes = 0;
+  if (c->impl->S == 0) return fail(NT_ERR_NOT_BRACKETED, "a circuit without error sites has no tolerable rate");
+  // 1. exhaustive single-error simulation (Sec. IV-B.1)
+  double P_e[3] = {0, 0, 0}, P_R = 0;
+  s = guard([&] { ctx->impl->exhaustive(*c->impl, tau, nullptr, P_e, &P_R); });
+  if (s) return s;
+  if (P_single) {
+    P_single[0] = P_e[0]; P_single[1] = P_e[1]; P_single[2] = P_e[2]; P_single[3] = P_R;
+  }
+  if (method) *method = -1;
+  if (P_R < P_target) return fail(NT_ERR_NOT_BRACKETED, "the error-free state misses the target");
+  const double S = (double)c->impl->S;
+  // 2. success at one average error: Eq. 4 with E(N_e) = 1/3 per type
+  const double P1 = (P_e[0] + P_e[1] + P_e[2]) / 3.0;
+  if (P1 <= P_target && P1 != P_R) {
+    // 3. at most one error is tolerable: Eq. 5 over the S error locations
+    s = nt_eq5(P_target, P_e, P_R, S, p_star);
+    if (s) return s;
+    if (method) *method = 0;
+    return NT_OK;
+  }
+  // 4. Monte Carlo at increasing rates 2^k / S while the success stays at or
+  // above the target (decreasing by halves when it is already below at 1/S),
+  // then the search between the last two rates
+  meth = 1;
+  if (method) *method = meth;
+  auto P_at = [&](double p, double *P) {
+    ++probes;
+    return nt_sweep(ctx, c, &p, 1, seed, n_traj, tau, P);
+  };
+  auto done = [&](nt_status st) {
+    if (n_probes) *n_probes = probes;
+    return st;
+  };
+  double p = 1.0 / S, P = 0.0, lo = 0.0, hi = 0.0;
+  s = P_at(p, &P);
+  if (s) return done(s);
+  if (std::fabs(P - P_target) <= tol) {
+    *p_star = p;
+    return done(NT_OK);
+  }
+  if (P >= P_target) {
+    for (;;) {
+      lo = p;
+      p *= 2.0;
+      if (p > 0.5) return done(fail(NT_ERR_NOT_BRACKETED, "success stays above the target up to p = 0.5"));
+      s = P_at(p, &P);
+      if (s) return done(s);
+      if (std::fabs(P - P_target) <= tol) {
+        *p_star = p;
+        return done(NT_OK);
+      }
+      if (P < P_target) {
+        hi = p;
+        break;
+      }
+    }
+  } else {
+    for (;;) {
+      hi = p;
+      p *= 0.5;
+      if (p < 1e-9) return done(fail(NT_ERR_NOT_BRACKETED, "success stays below the target down to p = 1e-9"));
+      s = P_at(p, &P);
+      if (s) return done(s);
+      if (std::fabs(P - P_target) <= tol) {
+        *p_star = p;
+        return done(NT_OK);
+      }
+      if (P >= P_target) {
+        lo = p;
+        break;
+      }
+    }
+  }
+  int k = 0;
+  s = nt_tolerable_rate(ctx, c, P_target, tol, lo, hi, seed, n_traj, tau, p_star, &k);
+  probes += k;
+  return done(s);
 }
 
 nt_status nt_set_shortcuts(nt_ctx *ctx, int flags) {

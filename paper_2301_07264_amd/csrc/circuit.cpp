@@ -292,7 +292,7 @@ double gate_flops(const HostGate &g) {
 uint32_t HostOp::need_mask() const {
   switch (cls) {
     case OPC_G1: case OPC_C1: return 1u << qa;
-    case OPC_G2: return (1u << qa) | (1u << qb);
+    case OPC_G2: case OPC_UCX: return (1u << qa) | (1u << qb);
     default: return 0u;
   }
 }

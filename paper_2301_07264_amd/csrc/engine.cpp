@@ -18,6 +18,8 @@
 
 namespace nt {
 
+static_assert(SITE_INTERIOR == ntk::EV_INTERIOR, "interior-site flag of the planner and the gate kernel");
+
 void check_hip(hipError_t e, const char *what) {
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -41,7 +43,21 @@ bool is_device_pointer(const void *p) {
 
 DevBuf::~DevBuf() { release(); }
 
+void *Arena::take(size_t n) {
+  const size_t at = (off + 255) & ~(size_t)255;
+  if (at > cap || n > cap - at)
+    throw Error(NT_ERR_UNSUPPORTED, "this call needs more than the " + std::to_string(cap >> 20) +
+                                        " MiB scratch array of the allocation-free entry point");
+  off = at + n;
+  return base + at;
+}
+
 void DevBuf::release() {
+  if (arena) {              // arena space is never freed
+    p = nullptr;
+    bytes = 0;
+    return;
+  }
   // queued work may still read the buffer
   if (p) (void)hipDeviceSynchronize();
   if (p) (void)hipFree(p);
@@ -52,6 +68,11 @@ void DevBuf::release() {
 void DevBuf::ensure(size_t n) {
   if (n == 0) n = 16;
   if (n <= bytes) return;
+  if (arena) {
+    p = arena->take(n);
+    bytes = n;
+    return;
+  }
   release();
   check_hip(hipMalloc(&p, n), "hipMalloc");
   bytes = n;
@@ -166,10 +187,32 @@ static void upload_ops(DevPlan &dp, const std::vector<int32_t> &code, const std:
       case OPC_G1: case OPC_C1: case OPC_D2: nent = 4; break;
       case OPC_D1: nent = 2; break;
       case OPC_G2: nent = 16; break;
+      case OPC_UCX: nent = 4; break;
     }
     for (int i = 0; i < nent; ++i) {
       d.m[2 * i] = (T)h.m[i].real();
       d.m[2 * i + 1] = (T)h.m[i].imag();
+    }
+    if (h.cls == OPC_UCX) {
+      // the control's 2x2 under each frame X^x Z^z on the control: rows and
+      // columns permuted by x, off-diagonal entries negated by z (rounded
+      // once, then permuted and negated exactly, as the kernel's own
+      // conjugation of a 2x2 does)
+      T r[8];
+      for (int i = 0; i < 4; ++i) {
+        r[2 * i] = (T)h.m[4 + i].real();
+        r[2 * i + 1] = (T)h.m[4 + i].imag();
+      }
+      for (int x = 0; x < 2; ++x)
+        for (int z = 0; z < 2; ++z) {
+          T *e = d.m + 8 + 8 * (x + 2 * z);
+          const int src[4] = {x ? 3 : 0, x ? 2 : 1, x ? 1 : 2, x ? 0 : 3};
+          for (int i = 0; i < 4; ++i) {
+            const bool neg = z && (i == 1 || i == 2);
+            e[2 * i] = neg ? -r[2 * src[i]] : r[2 * src[i]];
+            e[2 * i + 1] = neg ? -r[2 * src[i] + 1] : r[2 * src[i] + 1];
+          }
+        }
     }
     if (swap_ab[o]) {
       // two-qubit diagonal with qa on the higher register bit: the qubits
@@ -186,33 +229,33 @@ static void upload_ops(DevPlan &dp, const std::vector<int32_t> &code, const std:
             "upload ops");
 }
 
-DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
-  // the tile override is part of the key: changing it builds a new plan
-  auto key = std::make_pair(c.serial, pr + 16 * c.tile_override[pr == NT_C64 ? 1 : 2]);
-  auto it = plans.find(key);
-  if (it != plans.end()) {
-    it->second->last_use = ++use_clock;
-    return *it->second;
-  }
-  evict_plans();
-  auto dp = std::make_unique<DevPlan>();
-  dp->last_use = ++use_clock;
-  dp->prec = pr;
-  dp->plan = choose_plan(c, pr);
-  const Plan &P = dp->plan;
+// Device tables of a plan (ops, segments, passes, site order and tags), in
+// dp's buffers, and its per-pass bookkeeping; dp.plan and dp.prec are set.
+void Ctx::upload_plan(const Circuit &c, DevPlan &dp) {
+  const int pr = dp.prec;
+  const Plan &P = dp.plan;
   const int L = P.L, R = P.R;
-  dp->nthreads = 1 << (L - R);
+  dp.nthreads = 1 << (L - R);
   const int SW = pr == NT_C64 ? 4 : 3;
   // Algorithmic flops per amplitude of each pass: the sum over its gates of
   // each gate's own count (gate_flops), whatever ops the plan made of them.
   for (const Pass &ps : P.passes) {
     double f = 0;
-    for (int o = ps.op_begin; o < ps.op_end; ++o) f += gate_flops(c.gates[(size_t)P.ops[o].gate]);
-    dp->pass_flops_per_amp.push_back(f);
+    int ng = 0;
+    for (int o = ps.op_begin; o < ps.op_end; ++o) {
+      const HostOp &h = P.ops[o];
+      for (int g : {h.pre[0], h.pre[1], h.gate}) {
+        if (g < 0) continue;
+        f += gate_flops(c.gates[(size_t)g]);
+        ++ng;
+      }
+    }
+    dp.pass_flops_per_amp.push_back(f);
+    dp.pass_gates.push_back(ng);
   }
-  dp->pass_of_op.assign(P.ops.size(), 0);
+  dp.pass_of_op.assign(P.ops.size(), 0);
   for (size_t p = 0; p < P.passes.size(); ++p)
-    for (int o = P.passes[p].op_begin; o < P.passes[p].op_end; ++o) dp->pass_of_op[o] = (int)p;
+    for (int o = P.passes[p].op_begin; o < P.passes[p].op_end; ++o) dp.pass_of_op[o] = (int)p;
 
   std::vector<ntk::DevSeg> segs(std::max<size_t>(P.segs.size(), 1));
   std::memset(segs.data(), 0, segs.size() * sizeof(ntk::DevSeg));
@@ -245,6 +288,17 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
           if (pa >= L || pb >= L) throw Error(NT_ERR_UNSUPPORTED, "internal: quad op qubit not local");
           rsel[o] = pa | (pb << 4);
           code[o] = op_code(h, 0);
+        } else if (h.cls == OPC_UCX) {
+          // fused block: both qubits in the registers; the dispatch code
+          // names the register bits of the target and the control
+          auto rbit = [&](int q) {
+            auto it = std::find(sg.reg_q.begin(), sg.reg_q.end(), q);
+            if (it == sg.reg_q.end()) throw Error(NT_ERR_UNSUPPORTED, "internal: fused block outside the registers");
+            return (int)(it - sg.reg_q.begin());
+          };
+          const int bt = rbit(h.qa), bc = rbit(h.qb);
+          rsel[o] = (1 << bt) | ((1 << bc) << 4);
+          code[o] = ntk::OPK_UCX * 4 + bt * 4 + bc;
         } else if (h.cls == OPC_G1 || h.cls == OPC_C1 || h.cls == OPC_D1 || h.cls == OPC_D2) {
           auto rmask = [&](int q) -> int32_t {
             if (q < 0) return 0;
@@ -306,14 +360,14 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
       }
     }
   }
-  dp->passes.ensure(dpass.size() * sizeof(ntk::DevPass));
-  check_hip(hipMemcpyAsync(dp->passes.p, dpass.data(), dpass.size() * sizeof(ntk::DevPass), hipMemcpyHostToDevice,
+  dp.passes.ensure(dpass.size() * sizeof(ntk::DevPass));
+  check_hip(hipMemcpyAsync(dp.passes.p, dpass.data(), dpass.size() * sizeof(ntk::DevPass), hipMemcpyHostToDevice,
                            stream), "upload passes");
-  dp->segs.ensure(segs.size() * sizeof(ntk::DevSeg));
-  check_hip(hipMemcpyAsync(dp->segs.p, segs.data(), segs.size() * sizeof(ntk::DevSeg), hipMemcpyHostToDevice, stream),
+  dp.segs.ensure(segs.size() * sizeof(ntk::DevSeg));
+  check_hip(hipMemcpyAsync(dp.segs.p, segs.data(), segs.size() * sizeof(ntk::DevSeg), hipMemcpyHostToDevice, stream),
             "upload segments");
-  if (pr == NT_C64) upload_ops<float>(*dp, code, rsel, swap_ab, stream);
-  else upload_ops<double>(*dp, code, rsel, swap_ab, stream);
+  if (pr == NT_C64) upload_ops<float>(dp, code, rsel, swap_ab, stream);
+  else upload_ops<double>(dp, code, rsel, swap_ab, stream);
 
   const size_t S = std::max<size_t>(P.app_site.size(), 1);
   std::vector<int32_t> ident(S);
@@ -322,17 +376,34 @@ DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
     ident[k] = (int32_t)k;
     itag[k] = (uint32_t)k << 8;
   }
-  dp->app_order.ensure(S * 4);
-  dp->app_tag.ensure(S * 4);
-  dp->site_order.ensure(S * 4);
-  dp->site_tag.ensure(S * 4);
+  dp.app_order.ensure(S * 4);
+  dp.app_tag.ensure(S * 4);
+  dp.site_order.ensure(S * 4);
+  dp.site_tag.ensure(S * 4);
   if (!P.app_site.empty()) {
-    check_hip(hipMemcpyAsync(dp->app_order.p, P.app_site.data(), P.app_site.size() * 4, hipMemcpyHostToDevice, stream), "upload");
-    check_hip(hipMemcpyAsync(dp->app_tag.p, P.app_tag.data(), P.app_tag.size() * 4, hipMemcpyHostToDevice, stream), "upload");
+    check_hip(hipMemcpyAsync(dp.app_order.p, P.app_site.data(), P.app_site.size() * 4, hipMemcpyHostToDevice, stream), "upload");
+    check_hip(hipMemcpyAsync(dp.app_tag.p, P.app_tag.data(), P.app_tag.size() * 4, hipMemcpyHostToDevice, stream), "upload");
   }
-  check_hip(hipMemcpyAsync(dp->site_order.p, ident.data(), S * 4, hipMemcpyHostToDevice, stream), "upload");
-  check_hip(hipMemcpyAsync(dp->site_tag.p, itag.data(), S * 4, hipMemcpyHostToDevice, stream), "upload");
+  check_hip(hipMemcpyAsync(dp.site_order.p, ident.data(), S * 4, hipMemcpyHostToDevice, stream), "upload");
+  check_hip(hipMemcpyAsync(dp.site_tag.p, itag.data(), S * 4, hipMemcpyHostToDevice, stream), "upload");
   sync();   // host vectors go out of scope
+}
+
+DevPlan &Ctx::plan_for(const Circuit &c, int pr) {
+  // the tile and fusion overrides are part of the key: changing them builds a new plan
+  const int slot = pr == NT_C64 ? 1 : 2;
+  auto key = std::make_pair(c.serial, pr + 16 * c.tile_override[slot] + 1024 * c.fuse_width[slot]);
+  auto it = plans.find(key);
+  if (it != plans.end()) {
+    it->second->last_use = ++use_clock;
+    return *it->second;
+  }
+  evict_plans();
+  auto dp = std::make_unique<DevPlan>();
+  dp->last_use = ++use_clock;
+  dp->prec = pr;
+  dp->plan = choose_plan(c, pr);
+  upload_plan(c, *dp);
   DevPlan &ref = *dp;
   plans.emplace(key, std::move(dp));
   return ref;
@@ -465,7 +536,7 @@ static void run_passes(Ctx &cx, const Circuit &c, DevPlan &dp, ntk::cx<T> *state
       e1 = take_event(cx.ev_pool);
       check_hip(hipEventRecord(e0, cx.stream), "hipEventRecord");
     }
-    check_hip(ntk::launch_pass<T>(a, P.R, dp.nthreads, cx.stream), "k_pass launch");
+    check_hip(ntk::launch_pass<T>(a, P.R, dp.nthreads, P.n_fused > 0, cx.stream), "k_pass launch");
     if (cx.timing) {
       check_hip(hipEventRecord(e1, cx.stream), "hipEventRecord");
       // algorithmic HBM bytes: every pass reads and writes each state once,
@@ -477,7 +548,7 @@ static void run_passes(Ctx &cx, const Circuit &c, DevPlan &dp, ntk::cx<T> *state
       double refr = (a.flags & ntk::PF_SCORE) ? 1.0 : 0.0;
       cx.ev_pending.emplace_back(e0, e1);
       cx.ev_bytes.push_back(per_state * Bp * (reads + writes + refr));
-      cx.ev_updates.push_back((double)dim * Bp * (ps.op_end - ps.op_begin));
+      cx.ev_updates.push_back((double)dim * Bp * dp.pass_gates[p]);
       double fl = dp.pass_flops_per_amp[p] + ((a.flags & ntk::PF_SCORE) ? 8.0 : 0.0);
       cx.ev_flops.push_back((double)dim * Bp * fl);
       if (cx.ev_pending.size() >= 2048) cx.timing_flush();
@@ -501,7 +572,7 @@ void Ctx::ensure_reference(const Circuit &c, DevPlan &dp) {
   dp.ref_partials.ensure(ntiles * ntk::NPART * sizeof(double));
   ev_count.ensure(sizeof(int32_t) * 4);
   events.ensure(16);
-  check_hip(hipMemsetAsync(ev_count.p, 0, sizeof(int32_t), stream), "hipMemsetAsync");
+  check_hip(ntk::launch_zero_words(ev_count.as<uint32_t>(), 1, stream), "k_zero_words launch");
   bool was = timing;
   timing = false;
   PassRun r;
@@ -583,7 +654,7 @@ void Ctx::run(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double t
   const uint64_t bs = batch_size(c, dp, n);
   const bool dev_out = is_device_pointer(fid_out);
   count.ensure(sizeof(uint64_t));
-  check_hip(hipMemsetAsync(count.p, 0, sizeof(uint64_t), stream), "hipMemsetAsync");
+  check_hip(ntk::launch_zero_words(count.as<uint32_t>(), 2, stream), "k_zero_words launch");
   if (!dev_out) fid.ensure((size_t)bs * sizeof(double));
   // host copy of the values when their sum is asked for and fid_out is not on the host
   std::vector<double> hv(sum_out && (!fid_out || dev_out) ? n : 0);
@@ -631,7 +702,7 @@ double Ctx::heavy_median(const Circuit &c, DevPlan &dp) {
   auto select = [&](uint64_t k) {
     uint64_t prefix = 0;
     for (int shift = 48; shift >= 0; shift -= 16) {
-      check_hip(hipMemsetAsync(hist.p, 0, 65536 * sizeof(uint32_t), stream), "hipMemsetAsync");
+      check_hip(ntk::launch_zero_words(hist.as<uint32_t>(), 65536, stream), "k_zero_words launch");
       if (dp.prec == NT_C64)
         check_hip(ntk::launch_prob_hist<float>(dp.ref.as<ntk::cx<float>>(), dim, shift, prefix, hist.as<uint32_t>(),
                                                stream), "k_prob_hist launch");
@@ -714,7 +785,7 @@ bool Ctx::ensure_checkpoints(const Circuit &c, DevPlan &dp) {
   r.last_flags = ntk::PF_STORE | ntk::PF_NORM;
   ev_count.ensure(sizeof(int32_t) * 4);
   events.ensure(16);
-  check_hip(hipMemsetAsync(ev_count.p, 0, sizeof(int32_t), stream), "hipMemsetAsync");
+  check_hip(ntk::launch_zero_words(ev_count.as<uint32_t>(), 1, stream), "k_zero_words launch");
   r.events = events.as<uint32_t>();
   r.ev_count = ev_count.as<int32_t>();
   r.partials = dp.ref_partials.as<double>();
@@ -816,7 +887,7 @@ void Ctx::run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n,
     ReuseKey k;
     k.serial = c.serial;
     k.cid = c.cid;
-    k.tile = c.tile_override[dp.prec == NT_C64 ? 1 : 2];
+    k.tile = c.tile_override[dp.prec == NT_C64 ? 1 : 2] + 64 * c.fuse_width[dp.prec == NT_C64 ? 1 : 2];
     k.seed = seed;
     k.target = target;
     k.c_x = th.c_x;
@@ -1086,7 +1157,7 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
   const bool dev_out = is_device_pointer(vals_out);
   bvals.ensure(nc * n * sizeof(double));
   bcounts.ensure(nc * sizeof(uint64_t));
-  check_hip(hipMemsetAsync(bcounts.p, 0, nc * sizeof(uint64_t), stream), "hipMemsetAsync");
+  check_hip(ntk::launch_zero_words(bcounts.as<uint32_t>(), 2 * (uint64_t)nc, stream), "k_zero_words launch");
   double *vals_dev = dev_out ? vals_out : bvals.as<double>();
   const bool c64 = prec == NT_C64;
   // zero-fired trajectories of one-tile circuits are not simulated (fidelity
@@ -1188,7 +1259,11 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
       const size_t base = gbase[gi++];
       const size_t ng = g.second.size();
       int64_t smax = 1;
-      for (size_t k : g.second) smax = std::max<int64_t>(smax, cs[i0 + k]->S);
+      bool fused = false;
+      for (size_t k : g.second) {
+        smax = std::max<int64_t>(smax, cs[i0 + k]->S);
+        fused = fused || dps[k]->plan.n_fused > 0;
+      }
       // trajectories per circuit per launch: bounded work-group count and event memory
       uint64_t bc = std::min<uint64_t>(n, std::max<uint64_t>(1, ((uint64_t)1 << 20) / ng));
       bc = std::min<uint64_t>(bc, std::max<uint64_t>(1, (((uint64_t)512 << 20) / (4 * (uint64_t)smax)) / ng));
@@ -1234,7 +1309,7 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
           a.target = (uint32_t)target;
           a.multi = multi_items.as<ntk::MultiItem<float>>() + base;
           a.per_item = per;
-          check_hip(ntk::launch_pass<float>(a, R, nthreads, stream), "k_pass launch");
+          check_hip(ntk::launch_pass<float>(a, R, nthreads, fused, stream), "k_pass launch");
         } else {
           ntk::PassArgs<double> a;
           std::memset(&a, 0, sizeof a);
@@ -1249,7 +1324,7 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
           a.target = (uint32_t)target;
           a.multi = multi_items.as<ntk::MultiItem<double>>() + base;
           a.per_item = per;
-          check_hip(ntk::launch_pass<double>(a, R, nthreads, stream), "k_pass launch");
+          check_hip(ntk::launch_pass<double>(a, R, nthreads, fused, stream), "k_pass launch");
         }
         if (timing) {
           // a scoring pass over one tile reads the reference once per trajectory
@@ -1258,7 +1333,7 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
           for (size_t k : g.second) {
             const double dim = (double)((uint64_t)1 << cs[i0 + k]->n);
             by += dim * (double)amp_bytes(prec);
-            up += dim * (double)dps[k]->plan.ops.size();
+            up += dim * (double)cs[i0 + k]->gates.size();
             fl += dim * (dps[k]->pass_flops_per_amp[0] + 8.0);
           }
           ev_pending.emplace_back(e0, e1);

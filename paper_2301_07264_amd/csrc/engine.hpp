@@ -13,9 +13,19 @@
 
 namespace nt {
 
+// A bump allocator over caller-provided device memory (the static scratch
+// array of the allocation-free entry point): regions are 256-byte aligned and
+// only handed out, never freed; running out is an error, not an allocation.
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0, off = 0;
+  void *take(size_t n);
+};
+
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  Arena *arena = nullptr;      // when set, space comes from the arena (no hipMalloc)
   ~DevBuf();
   void ensure(size_t n);       // grows (never shrinks); contents not kept
   void release();
@@ -40,6 +50,7 @@ struct DevPlan {
   std::map<std::pair<int, uint64_t>, double> ref_value;
   std::vector<int> pass_of_op;
   std::vector<double> pass_flops_per_amp;   // algorithmic flops per amplitude, per pass
+  std::vector<int> pass_gates;              // circuit gates applied by each pass
   uint64_t last_use = 0;       // plan cache: least recently used goes first
   int pins = 0;                // > 0 while a batched run holds it
   size_t footprint() const { return ref.bytes + ckpt.bytes + ckpt_partials.bytes + ref_partials.bytes; }
@@ -71,7 +82,7 @@ enum : int { SC_ZERO_FIRED = 1, SC_CHECKPOINT = 2, SC_LAST_ERROR = 4, SC_REUSE =
 struct ReuseKey {
   uint64_t serial = 0, cid = 0, seed = 0, target = 0, c_x = 0, c_xy = 0;
   uint32_t always_types = 0;
-  int prec = 0, crit = 0, flags = 0, tile = 0;   // tile: the plan's tile-width override (sets the reduction order)
+  int prec = 0, crit = 0, flags = 0, tile = 0;   // tile: the plan's tile-width and fusion overrides (set the reduction order)
   bool operator==(const ReuseKey &o) const {
     return serial == o.serial && cid == o.cid && seed == o.seed && target == o.target && c_x == o.c_x &&
            c_xy == o.c_xy && always_types == o.always_types && prec == o.prec && crit == o.crit &&
@@ -114,6 +125,7 @@ struct Ctx {
   ~Ctx();
 
   DevPlan &plan_for(const Circuit &c, int prec);
+  void upload_plan(const Circuit &c, DevPlan &dp);
   void ensure_reference(const Circuit &c, DevPlan &dp);
   uint64_t batch_size(const Circuit &c, const DevPlan &dp, uint64_t n_traj);
 

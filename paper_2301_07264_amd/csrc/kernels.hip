@@ -304,33 +304,59 @@ DEV void cx_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], bool take_lane, 
   }
 }
 
-// Header and the first four complex matrix entries of an op: everything a
-// register-segment op needs (read with scalar loads, one op ahead).
-template <typename T>
+// Fused block on register bits BT (target) and BC (control): the 2x2 t on
+// the target, the 2x2 c on the control, then the controlled X with control
+// value 1, a compile-time swap of the target's two slots where the control
+// bit is set.  The arithmetic is that of the two general 2x2 ops one after
+// the other (the same FMA sequence).
+template <int BT, int BC, int R, typename T>
+DEV void ucx_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> t00, cx<T> t01, cx<T> t10, cx<T> t11,
+                   cx<T> c00, cx<T> c01, cx<T> c10, cx<T> c11) {
+  constexpr int TB = 1 << BT, CB = 1 << BC;
+#pragma unroll
+  for (int r = 0; r < (1 << R); ++r) {
+    if (r & (TB | CB)) continue;
+    const cx<T> x0 = v[r], x1 = v[r | TB], x2 = v[r | CB], x3 = v[r | TB | CB];
+    const cx<T> y0 = mac2(t00, x0, t01, x1), y1 = mac2(t10, x0, t11, x1);
+    const cx<T> y2 = mac2(t00, x2, t01, x3), y3 = mac2(t10, x2, t11, x3);
+    w[r] = mac2(c00, y0, c01, y2);
+    w[r | TB] = mac2(c00, y1, c01, y3);
+    w[r | CB] = mac2(c10, y1, c11, y3);
+    w[r | TB | CB] = mac2(c10, y0, c11, y2);
+  }
+}
+
+// Header and the first four complex matrix entries of an op: what a
+// register-segment op other than a fused block needs, read with scalar loads
+// one op ahead.
+// NM = 8 reals: the first four complex entries; NM = 16 (complex64 plans
+// with fused blocks): eight, so that a block's second matrix arrives with
+// its descriptor.
+template <typename T, int NM = 8>
 struct OpLite {
   int32_t code, qa, qb, rsel;
-  T m[8];
+  T m[NM];
 };
 
-template <typename T>
-DEV OpLite<T> load_lite(const DevOp<T> *ops, int o) {
-  OpLite<T> h;
+template <typename T, int NM>
+DEV OpLite<T, NM> load_lite(const DevOp<T> *ops, int o) {
+  OpLite<T, NM> h;
   if constexpr (sizeof(T) == 4) {
-    // header and the four entries: the first 12 dwords of the descriptor
-    struct W12 {
-      uint32_t w[12];
+    // header and the entries: the first 4 + NM dwords of the descriptor
+    struct Wn {
+      uint32_t w[4 + NM];
     };
-    const NT_CONST W12 &q = *reinterpret_cast<const NT_CONST W12 *>(
+    const NT_CONST Wn &q = *reinterpret_cast<const NT_CONST Wn *>(
         reinterpret_cast<const NT_CONST char *>(cptr(ops)) + ((uint32_t)o << 8));
-    uint32_t w[12];
+    uint32_t w[4 + NM];
 #pragma unroll
-    for (int i = 0; i < 12; ++i) w[i] = q.w[i];
+    for (int i = 0; i < 4 + NM; ++i) w[i] = q.w[i];
     h.code = (int32_t)w[0];
     h.qa = (int32_t)w[1];
     h.qb = (int32_t)w[2];
     h.rsel = (int32_t)w[3];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) h.m[i] = __builtin_bit_cast(T, w[4 + i]);
+    for (int i = 0; i < NM; ++i) h.m[i] = __builtin_bit_cast(T, w[4 + i]);
   } else {
     const NT_CONST DevOp<T> &op = cptr(ops)[o];
     h.code = op.cls;
@@ -338,7 +364,7 @@ DEV OpLite<T> load_lite(const DevOp<T> *ops, int o) {
     h.qb = op.qb;
     h.rsel = op.rsel;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) h.m[i] = op.m[i];
+    for (int i = 0; i < NM; ++i) h.m[i] = op.m[i];
   }
   return h;
 }
@@ -349,22 +375,22 @@ DEV OpLite<T> load_lite(const DevOp<T> *ops, int o) {
 // op about to run come before this load is issued, which then has a whole op
 // to arrive.  The opaque index also keeps loop strength reduction from
 // splitting the load into one pointer per field.
-template <typename T>
-DEV OpLite<T> load_lite_after(const DevOp<T> *ops, int o, const OpLite<T> &prev) {
+template <typename T, int NM>
+DEV OpLite<T, NM> load_lite_after(const DevOp<T> *ops, int o, const OpLite<T, NM> &prev) {
   asm volatile("" : "+s"(o) : "s"(prev.code));
-  return load_lite(ops, o);
+  return load_lite<T, NM>(ops, o);
 }
 
-template <typename T>
-DEV cx<T> lent(const OpLite<T> &h, int i) {
+template <typename T, int NM>
+DEV cx<T> lent(const OpLite<T, NM> &h, int i) {
   return cx<T>{h.m[2 * i], h.m[2 * i + 1]};
 }
 
 // Entries e[i] = entry i ^ xm of a 4-entry list, xm uniform in 0..3: two
 // rounds of conditional swaps (bit 0 of xm swaps within pairs, bit 1 swaps
 // the pairs), eight scalar selects instead of a select chain per entry.
-template <typename T>
-DEV void perm4(const OpLite<T> &h, uint32_t xm, cx<T> &e0, cx<T> &e1, cx<T> &e2, cx<T> &e3) {
+template <typename T, int NM>
+DEV void perm4(const OpLite<T, NM> &h, uint32_t xm, cx<T> &e0, cx<T> &e1, cx<T> &e2, cx<T> &e3) {
   const cx<T> a0 = lent(h, 0), a1 = lent(h, 1), a2 = lent(h, 2), a3 = lent(h, 3);
   const bool s0 = (xm & 1u) != 0u, s1 = (xm & 2u) != 0u;
   const cx<T> b0 = s0 ? a1 : a0, b1 = s0 ? a0 : a1, b2 = s0 ? a3 : a2, b3 = s0 ? a2 : a3;
@@ -423,14 +449,42 @@ DEV void cx_frame(uint32_t zt, uint32_t qc, uint32_t qt, uint32_t cv, uint32_t &
   fx = __builtin_amdgcn_readfirstlane(fx ^ ((cv ^ 1u) << qt));
 }
 
+// A 2x2 conjugated by the frame's X^x Z^z on its qubit: rows and columns
+// permuted by x, the off-diagonal entries negated by z.
+template <typename T>
+DEV void conj2(cx<T> m00, cx<T> m01, cx<T> m10, cx<T> m11, uint32_t x, uint32_t z, cx<T> &c00, cx<T> &c01,
+               cx<T> &c10, cx<T> &c11) {
+  if constexpr (sizeof(T) == 4) {
+    // complex64 entries as 64-bit words: one scalar select per entry, one
+    // XOR of both sign bits per negated entry
+    auto u = [](cx<T> c) { return __builtin_bit_cast(uint64_t, c); };
+    auto f = [](uint64_t q) { return __builtin_bit_cast(cx<T>, q); };
+    const uint64_t sgn = z ? 0x8000000080000000ull : 0ull;
+    c00 = f(x ? u(m11) : u(m00));
+    c01 = f((x ? u(m10) : u(m01)) ^ sgn);
+    c10 = f((x ? u(m01) : u(m10)) ^ sgn);
+    c11 = f(x ? u(m00) : u(m11));
+  } else {
+    c00 = x ? m11 : m00;
+    c01 = x ? m10 : m01;
+    c10 = x ? m01 : m10;
+    c11 = x ? m00 : m11;
+    if (z) {
+      c01 = cneg(c01);
+      c10 = cneg(c10);
+    }
+  }
+}
+
 // Apply one register-segment op, conjugated by the current Pauli frame, to
 // the register slots.  gb: the thread's global index with all register bits
 // zero.  Index bit q of slot r is ((gb >> q) & 1) | (r & mask(q) != 0), where
 // mask(q) is the register bit holding q (0 if none).  Conjugation by X^x Z^z of a 2x2
 // M gives entries (i, j) = (-1)^{z(i+j)} M[i^x][j^x].
-template <int R, typename T>
-DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], uint32_t gb,
-                      uint32_t &fx, uint32_t &fz, uint32_t &fc) {
+template <int R, bool FUSED, typename T, int NM, typename TI>
+DEV void apply_reg_op(const OpLite<T, NM> &op, const NT_CONST DevOp<T> *opd, const cx<T> (&v)[1 << R],
+                      cx<T> (&w)[1 << R], uint32_t gb, uint32_t &fx, uint32_t &fz, uint32_t &fc,
+                      TI &&take_interior) {
   const int code = op.code;
   const uint32_t qa = (uint32_t)op.qa;
   const uint32_t xa = (fx >> qa) & 1u, za = (fz >> qa) & 1u;
@@ -438,37 +492,57 @@ DEV void apply_reg_op(const OpLite<T> &op, const cx<T> (&v)[1 << R], cx<T> (&w)[
   // op's segment (0 when the qubit is not a register qubit), from the host.
   const uint32_t bm = ((uint32_t)op.rsel >> 4) & 15u;
   const cx<T> m00 = lent(op, 0), m01 = lent(op, 1), m10 = lent(op, 2), m11 = lent(op, 3);
-  // the frame-conjugated dense 2x2 (rows and columns permuted by x_a, the
-  // off-diagonal entries negated by z_a)
-  auto conj = [&](cx<T> &c00, cx<T> &c01, cx<T> &c10, cx<T> &c11) {
-    if constexpr (sizeof(T) == 4) {
-      // complex64 entries as 64-bit words: one scalar select per entry, one
-      // XOR of both sign bits per negated entry
-      auto u = [](cx<T> c) { return __builtin_bit_cast(uint64_t, c); };
-      auto f = [](uint64_t x) { return __builtin_bit_cast(cx<T>, x); };
-      const uint64_t sgn = za ? 0x8000000080000000ull : 0ull;
-      c00 = f(xa ? u(m11) : u(m00));
-      c01 = f((xa ? u(m10) : u(m01)) ^ sgn);
-      c10 = f((xa ? u(m01) : u(m10)) ^ sgn);
-      c11 = f(xa ? u(m00) : u(m11));
-    } else {
-      c00 = xa ? m11 : m00;
-      c01 = xa ? m10 : m01;
-      c10 = xa ? m01 : m10;
-      c11 = xa ? m00 : m11;
-      if (za) {
-        c01 = cneg(c01);
-        c10 = cneg(c10);
-      }
-    }
-  };
+  // the frame-conjugated dense 2x2 on qa
+  auto conj = [&](cx<T> &c00, cx<T> &c01, cx<T> &c10, cx<T> &c11) { conj2(m00, m01, m10, m11, xa, za, c00, c01, c10, c11); };
   // controlled X (control qb)
   const uint32_t qc = (uint32_t)op.qb;
   const uint32_t xc = (fx >> qc) & 1u;   // frame X on qb
   const uint32_t cv = 1u ^ xc;
-  // The two most frequent kinds are tested first, each followed by a
-  // four-way branch on the register bit; everything else goes through one
+  // Fused blocks (the most frequent op of random-layer circuits), then the
+  // dense one-qubit and controlled-X kinds, are tested first, each followed
+  // by a branch on the register bits; everything else goes through one
   // switch on the full code.
+  const uint32_t uk = (uint32_t)(code - OPK_UCX * 4);
+  if (FUSED && uk < 16u) {
+    // U_t on qa and U_c on qb, conjugated by the frame at the block's start;
+    // the errors after U_t and U_c then enter the frame; then the CNOT: its
+    // register work (CX_1) does not depend on the frame, and its frame rule
+    // reads the frame as the errors left it
+    const uint32_t zc = (fz >> qc) & 1u;
+    cx<T> t00, t01, t10, t11, c00, c01, c10, c11;
+    conj(t00, t01, t10, t11);
+    if constexpr (NM >= 16) {
+      // the control's 2x2 came with the descriptor
+      conj2(lent(op, 4), lent(op, 5), lent(op, 6), lent(op, 7), xc, zc, c00, c01, c10, c11);
+    } else {
+      // the control's 2x2 under this frame, from the table's variants
+      const uint32_t vc = 4u + 4u * (xc | (zc << 1));
+      c00 = ment(*opd, vc);
+      c01 = ment(*opd, vc + 1u);
+      c10 = ment(*opd, vc + 2u);
+      c11 = ment(*opd, vc + 3u);
+    }
+    t00 = vpin(t00); t01 = vpin(t01); t10 = vpin(t10); t11 = vpin(t11);
+    c00 = vpin(c00); c01 = vpin(c01); c10 = vpin(c10); c11 = vpin(c11);
+    switch (uk) {
+#define NT_UCX(bt, bc)                                                                \
+  case (bt) * 4 + (bc):                                                               \
+    if constexpr ((bt) < R && (bc) < R && (bt) != (bc))                               \
+      ucx_apply<bt, bc, R>(v, w, t00, t01, t10, t11, c00, c01, c10, c11);             \
+    break;
+      NT_UCX(0, 1) NT_UCX(0, 2) NT_UCX(0, 3)
+      NT_UCX(1, 0) NT_UCX(1, 2) NT_UCX(1, 3)
+      NT_UCX(2, 0) NT_UCX(2, 1) NT_UCX(2, 3)
+      NT_UCX(3, 0) NT_UCX(3, 1)
+      default:
+        if constexpr (R > 3) ucx_apply<3, 2, R>(v, w, t00, t01, t10, t11, c00, c01, c10, c11);
+        break;
+#undef NT_UCX
+    }
+    take_interior();
+    cx_frame((fz >> qa) & 1u, qc, qa, 1u ^ ((fx >> qc) & 1u), fx, fz);
+    return;
+  }
   const int kind = code >> 2;
   if (kind == OPK_G1) {
     cx<T> c00, c01, c10, c11;
@@ -653,7 +727,9 @@ DEV void block_reduce(double (&v)[NPART], double *out, unsigned char *smem) {
 // MAXT: largest work-group this instantiation serves; WPE: waves per SIMD
 // it must fit (bounds the register budget so two work-groups share a CU);
 // SLDS: the work-group is exactly MAXT threads and its tile is static LDS.
-template <typename T, int R, int MAXT, int WPE, bool SLDS>
+// FUSED: the plan holds fused two-qubit blocks (their bodies are compiled
+// only into these instances, so plans without blocks keep the smaller code).
+template <typename T, int R, int MAXT, int WPE, bool SLDS, bool FUSED>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))) k_pass(const PassArgs<T> a) {
   constexpr int NS = 1 << R;
   // SLDS: the tile of exactly MAXT threads (MAXT * 2^R amplitudes) as a
@@ -700,6 +776,13 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     op_begin = m.op_begin;
     heavy_med = m.heavy_med;
   }
+  // The table pointers become values of their own: loaded from the kernel
+  // arguments they belong to one wide scalar register group, which the
+  // register allocator would otherwise spill and reload whole in the op loop.
+  // (measured on the instruction listings: it removes the op loop's spills
+  // of every variant but the complex128 one without fused blocks, which has
+  // fewer spills without it)
+  if constexpr (sizeof(T) == 4 || FUSED) asm volatile("" : "+s"(ops), "+s"(segs));
 
   // Pass layout as dwords.  Thread-id bits at and above lt = L - R are zero
   // (NT = 2^lt <= MAXT), and so are tile-id bits at and above ntile_bits;
@@ -793,6 +876,20 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
       }
     }
   };
+  // errors after a fused block's one-qubit gates (they come first among the
+  // block's events)
+  auto take_interior = [&](int o) {
+    while (next_op == (uint32_t)o && (next_e & EV_INTERIOR) != 0u) {
+      frame_apply(next_e, fx, fz, fc);
+      ++ep;
+      if (ep < ne) {
+        next_e = __builtin_amdgcn_readfirstlane(ev[ep]);
+        next_op = next_e >> 8;
+      } else {
+        next_op = 0xffffffffu;
+      }
+    }
+  };
 
   for (int s = seg_begin; s < seg_end; ++s) {
     // segment table: scalar loads of whole dwords only (header, the widened
@@ -828,14 +925,15 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     int o = sg_op_begin;
     const int oe = sg_op_end;
     if (o < oe) {
-      OpLite<T> a_op = load_lite(ops, o), b_op;
+      constexpr int NM = (FUSED && sizeof(T) == 4) ? 16 : 8;
+      OpLite<T, NM> a_op = load_lite<T, NM>(ops, o), b_op;
       for (; o < oe; o += 2) {
         b_op = load_lite_after(ops, o + 1, a_op);
-        apply_reg_op<R, T>(a_op, v, w, gb, fx, fz, fc);
+        apply_reg_op<R, FUSED, T>(a_op, cptr(ops) + o, v, w, gb, fx, fz, fc, [&] { take_interior(o); });
         take_events(o);
         if (o + 1 < oe) {
           a_op = load_lite_after(ops, o + 2, b_op);
-          apply_reg_op<R, T>(b_op, w, v, gb, fx, fz, fc);
+          apply_reg_op<R, FUSED, T>(b_op, cptr(ops) + o + 1, w, v, gb, fx, fz, fc, [&] { take_interior(o + 1); });
           take_events(o + 1);
         } else {
           // odd op count: the last result is in w
@@ -844,14 +942,31 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
         }
       }
     }
+    // the slot offsets are read again from the segment table (scalar cache)
+    // instead of being kept in 2^R scalar registers across the op loop
+    const DevSeg *sg_again = segs + s;
+    asm volatile("" : "+s"(sg_again));
+    const NT_CONST DevSeg &sg2 = *cptr(sg_again);
 #pragma unroll
-    for (int r = 0; r < NS; ++r) slot(r) = v[r];
+    for (int r = 0; r < NS; ++r) *reinterpret_cast<cx<T> *>(smem_raw + (sjb ^ sg2.slot_off[r])) = v[r];
     __syncthreads();
   }
 
   // The epilogue recomputes its addresses instead of keeping 2^R of them
-  // live across the segment loop.
+  // live across the segment loop, and reads the register-bit words of the
+  // pass table again rather than holding them in scalar registers.
   asm volatile("" : "+v"(dlo));
+  {
+    const DevPass *pp = passp;
+    asm volatile("" : "+s"(pp));
+    uint32_t pw2[13];
+    cwords(pp, pw2);
+#pragma unroll
+    for (int bb = 0; bb < R; ++bb) {
+      hbit[bb] = 1u << wbyte(pw2, 48 + bb);
+      lbit[bb] = swz<T>(NT << bb) * (uint32_t)sizeof(cx<T>);
+    }
+  }
   uint32_t dk[NS], lk[NS];
   xor_span(hbit, dk);
   xor_span(lbit, lk);
@@ -904,8 +1019,8 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   }
 }
 
-template <typename T>
-hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, hipStream_t s) {
+template <typename T, bool FUSED>
+static hipError_t launch_pass_k(const PassArgs<T> &a, int R, int nthreads, hipStream_t s) {
   const size_t ntiles = (size_t)1 << a.ntile_bits;
   const size_t blocks = ntiles * (size_t)a.B;
   size_t lds = ((size_t)1 << a.L) * sizeof(cx<T>);
@@ -921,29 +1036,34 @@ hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, hipStream_t s)
   if (nthreads > (R == 4 ? MAXT4 : 1024)) return hipErrorInvalidValue;
   const dim3 grid((uint32_t)blocks), blk(nthreads);
   switch (R) {
-    case 1: hipLaunchKernelGGL((k_pass<T, 1, 1024, 1, false>), grid, blk, lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pass<T, 2, 1024, 1, false>), grid, blk, lds, s, a); break;
-    case 3: hipLaunchKernelGGL((k_pass<T, 3, 1024, 1, false>), grid, blk, lds, s, a); break;
+    case 1: hipLaunchKernelGGL((k_pass<T, 1, 1024, 1, false, FUSED>), grid, blk, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pass<T, 2, 1024, 1, false, FUSED>), grid, blk, lds, s, a); break;
+    case 3: hipLaunchKernelGGL((k_pass<T, 3, 1024, 1, false, FUSED>), grid, blk, lds, s, a); break;
     case 4:
       if constexpr (sizeof(T) == 4) {
         if (nthreads == 512 && a.L == 13) {
-          hipLaunchKernelGGL((k_pass<T, 4, 512, WPE4, true>), grid, blk, 0, s, a);
+          hipLaunchKernelGGL((k_pass<T, 4, 512, WPE4, true, FUSED>), grid, blk, 0, s, a);
           break;
         }
         if (nthreads == 256 && a.L == 12) {
-          hipLaunchKernelGGL((k_pass<T, 4, 256, WPE4, true>), grid, blk, 0, s, a);
+          hipLaunchKernelGGL((k_pass<T, 4, 256, WPE4, true, FUSED>), grid, blk, 0, s, a);
           break;
         }
       }
-      hipLaunchKernelGGL((k_pass<T, 4, MAXT4, WPE4, false>), grid, blk, lds, s, a);
+      hipLaunchKernelGGL((k_pass<T, 4, MAXT4, WPE4, false, FUSED>), grid, blk, lds, s, a);
       break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template hipError_t launch_pass<float>(const PassArgs<float> &, int, int, hipStream_t);
-template hipError_t launch_pass<double>(const PassArgs<double> &, int, int, hipStream_t);
+template <typename T>
+hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, bool fused, hipStream_t s) {
+  return fused ? launch_pass_k<T, true>(a, R, nthreads, s) : launch_pass_k<T, false>(a, R, nthreads, s);
+}
+
+template hipError_t launch_pass<float>(const PassArgs<float> &, int, int, bool, hipStream_t);
+template hipError_t launch_pass<double>(const PassArgs<double> &, int, int, bool, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Fixed-order FP64 sum over tiles of component `comp` of the partials of
@@ -1101,5 +1221,17 @@ hipError_t launch_unframe(const cx<T> *st, cx<T> *out, uint64_t dim, const uint3
 template hipError_t launch_unframe<float>(const cx<float> *, cx<float> *, uint64_t, const uint32_t *, hipStream_t);
 template hipError_t launch_unframe<double>(const cx<double> *, cx<double> *, uint64_t, const uint32_t *,
                                            hipStream_t);
+
+__global__ void __launch_bounds__(256) k_zero_words(uint32_t *p, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero_words(uint32_t *p, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (n > ((uint64_t)1 << 30)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_zero_words, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
 
 }  // namespace ntk

@@ -18,15 +18,18 @@ struct alignas(2 * sizeof(T)) cx {
 //          (bits 4..7) in the op's segment, 0 for a non-register qubit;
 //          G2: tile-local bit positions of qa (bits 0..3) and qb (bits 4..7)
 //   m    : matrix data, (re, im) interleaved; G1/C1 2x2 row-major, D1 (d0,d1),
-//          D2 (d0..d3) on local index b_qa + 2 b_qb, G2 4x4 row-major
+//          D2 (d0..d3) on local index b_qa + 2 b_qb, G2 4x4 row-major; UCX
+//          the 2x2 on qa (entries 0..3), then the 2x2 on qb conjugated by
+//          each frame X^x Z^z on qb, variant x + 2 z at entries 4 + 4 (x + 2 z)
+//          (the block reads the one its frame needs, with no selects)
 template <typename T>
 struct DevOp {
   int32_t cls, qa, qb, rsel;
-  T m[32];
+  T m[40];
   // padding to a power of two (256 bytes for complex64 tables, 512 for
   // complex128): the gate kernel addresses op o as base + (o << 8) with one
   // shift instead of a 64-bit multiply
-  int32_t pad[sizeof(T) == 4 ? 28 : 60];
+  int32_t pad[sizeof(T) == 4 ? 20 : 44];
 };
 static_assert(sizeof(DevOp<float>) == 256 && sizeof(DevOp<double>) == 512, "op table stride");
 
@@ -47,7 +50,15 @@ enum : int32_t {
   // Diagonal on two qubits, both in the registers: code OPK_D2RR * 4 + k
   // for the register-bit pair D2RR_PAIRS[k] (lower bit first), k = 0..5.
   OPK_D2RR = 10,
+  // Fused block (U_t on target qa, U_c on control qb, then CNOT qb -> qa),
+  // both qubits in the registers: code OPK_UCX * 4 + 4 * bt + bc for target
+  // register bit bt and control register bit bc (bt != bc).
+  OPK_UCX = 12,
 };
+
+// Error-event flag: the error follows one of a fused block's one-qubit gates
+// (it acts before the block's CNOT).
+constexpr uint32_t EV_INTERIOR = 0x80u;
 constexpr int D2RR_PAIRS[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
 
 // One register segment: which local bits / global qubits the thread's
@@ -118,7 +129,7 @@ struct PassArgs {
   const cx<T> *ref;        // reference state (PF_SCORE)
   const DevOp<T> *ops;
   const DevSeg *segs;
-  const uint32_t *events;  // per trajectory, sorted by op: (op << 8) | (qubit << 2) | pauli
+  const uint32_t *events;  // per trajectory, sorted by op: (op << 8) | flag | (qubit << 2) | pauli
   const int32_t *ev_count;
   double *partials;        // [B][ntiles][NPART]
   // Pauli frame (x-mask, z-mask, phase) per trajectory, [B][4]: written at
@@ -181,10 +192,14 @@ struct SampleArgs {
   int32_t per_item;
 };
 
+// p[0..n) = 0 with a kernel (no memset node, so it also records in graphs).
+hipError_t launch_zero_words(uint32_t *p, uint64_t n, hipStream_t s);
+
 // Launch wrappers (kernels.hip).
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
 template <typename T>
-hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, hipStream_t s);
+// fused: the plan holds fused two-qubit blocks (OPK_UCX ops)
+hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, bool fused, hipStream_t s);
 // nref: reference norm (end == NULL) or per-pass reference norms indexed by
 // end[b].
 hipError_t launch_finalize(const double *partials, int ntiles, int B, const double *nref, const int32_t *end,

@@ -29,6 +29,9 @@ enum OpClass : int32_t {
   OPC_C1 = 2,  // 2x2 on target qa when control qb equals the control value
   OPC_D2 = 3,  // diagonal (d00, d10, d01, d11) on local index b_qa + 2 b_qb
   OPC_G2 = 4,  // dense 4x4 on local index b_qa + 2 b_qb
+  // Fused block: the one-qubit gates just before a CNOT on its target qa and
+  // its control qb, then the CNOT: m[0..3] = 2x2 on qa, m[4..7] = 2x2 on qb.
+  OPC_UCX = 5,
 };
 
 struct HostGate {
@@ -44,7 +47,8 @@ struct HostGate {
 struct HostOp {
   int32_t cls = OPC_G1;
   int32_t qa = 0, qb = -1;
-  int32_t gate = 0;        // index in the circuit
+  int32_t gate = 0;        // index in the circuit (a fused block: its CNOT)
+  int32_t pre[2] = {-1, -1};   // fused block: gate indices of the 2x2s on qa and qb
   cd m[16];                // G1/C1: 4 entries; D1: 2; D2: 4; G2: 16
   // qubits that must be in the work-group tile / in registers
   uint32_t need_mask() const;
@@ -67,6 +71,12 @@ struct Pass {
   int op_begin = 0, op_end = 0;
 };
 
+// A plan's op list holds, in application order, ops of one gate each and
+// fused blocks of three gates (Plan::ops[o].pre).  The error sites of a
+// block's one-qubit gates carry the flag SITE_INTERIOR: the gate kernel
+// applies them to the Pauli frame after the block's one-qubit gates and
+// before its CNOT, exactly where the gates put them.
+constexpr uint32_t SITE_INTERIOR = 0x80u;
 struct Plan {
   int n = 0;
   int L = 0;          // tile qubits (<= n)
@@ -79,6 +89,7 @@ struct Plan {
   std::vector<int32_t> app_site;
   std::vector<uint32_t> app_tag;        // (op << 8) | (qubit << 2)
   std::vector<int> op_of_gate;          // gate -> application position
+  int n_fused = 0;                      // fused blocks
 };
 
 struct Circuit {
@@ -88,6 +99,7 @@ struct Circuit {
   uint64_t cid = 0;
   uint64_t serial = 0;                  // unique per loaded circuit
   int tile_override[3] = {0, 0, 0};     // per precision (NT_C64, NT_C128): tile qubits, 0 = automatic
+  int fuse_width[3] = {0, 0, 0};        // per precision: 0 = automatic (2), 1 = no fusion, 2 = two-qubit blocks
 };
 
 // circuit.cpp
@@ -102,7 +114,7 @@ std::vector<HostOp> classify(const Circuit &c);
 double gate_flops(const HostGate &g);   // algorithmic flops per amplitude
 
 // plan.cpp
-Plan make_plan(const Circuit &c, int max_tile_qubits, int max_reg, int cfix);
+Plan make_plan(const Circuit &c, int max_tile_qubits, int max_reg, int cfix, bool fuse = true);
 void plan_for_precision(const Circuit &c, int prec, int *L, int *R, int *cfix);
 // The plan the library runs for a precision (tile shape chosen per circuit,
 // or the circuit's override).

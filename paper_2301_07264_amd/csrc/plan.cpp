@@ -159,6 +159,63 @@ uint64_t improve_set(Sched &s, uint64_t set, uint64_t fixed, uint64_t pool, int 
   return set;
 }
 
+// Fusion into two-qubit blocks, among the ops of one pass (so the passes stay
+// those of the unfused schedule; the segments are then planned over the
+// blocks).  A CNOT whose target and control were each last touched, in the
+// pass's order, by a one-qubit gate of the same pass takes both gates into
+// one block: U_t on the target and U_c on the control, then the CNOT.
+// Moving U_t and U_c to the CNOT keeps the gate order on every qubit (each is
+// the gate right before the CNOT on its qubit, and they act on different
+// qubits), so the block is the circuit's product of unitaries.
+std::vector<HostOp> fuse_pass(const std::vector<HostOp> &ops, const std::vector<int> &order, int n, int *n_fused) {
+  const int K = (int)order.size();
+  std::vector<int> last(n, -1), into(K, -1), jt(K, -1), jc(K, -1);
+  auto one_qubit = [&](int k) {
+    const HostOp &h = ops[order[k]];
+    return k >= 0 && (h.cls == OPC_G1 || h.cls == OPC_D1) && into[k] < 0;
+  };
+  for (int k = 0; k < K; ++k) {
+    const HostOp &op = ops[order[k]];
+    if (op.cls == OPC_C1 && last[op.qa] >= 0 && last[op.qb] >= 0 && one_qubit(last[op.qa]) &&
+        one_qubit(last[op.qb])) {
+      jt[k] = last[op.qa];
+      jc[k] = last[op.qb];
+      into[jt[k]] = into[jc[k]] = k;
+    }
+    last[op.qa] = k;
+    if (op.qb >= 0) last[op.qb] = k;
+  }
+  auto as_2x2 = [](const HostOp &h, cd *m) {
+    if (h.cls == OPC_D1) {
+      m[0] = h.m[0]; m[1] = 0; m[2] = 0; m[3] = h.m[1];
+    } else {
+      for (int t = 0; t < 4; ++t) m[t] = h.m[t];
+    }
+  };
+  std::vector<HostOp> units;
+  for (int k = 0; k < K; ++k) {
+    if (into[k] >= 0) continue;          // moved into its CNOT's block
+    const HostOp &op = ops[order[k]];
+    if (jt[k] < 0) {
+      units.push_back(op);
+      continue;
+    }
+    HostOp b;
+    b.cls = OPC_UCX;
+    b.qa = op.qa;
+    b.qb = op.qb;
+    b.gate = op.gate;
+    b.pre[0] = ops[order[jt[k]]].gate;
+    b.pre[1] = ops[order[jc[k]]].gate;
+    for (int t = 0; t < 16; ++t) b.m[t] = 0;
+    as_2x2(ops[order[jt[k]]], b.m);
+    as_2x2(ops[order[jc[k]]], b.m + 4);
+    units.push_back(b);
+    ++*n_fused;
+  }
+  return units;
+}
+
 }  // namespace
 
 void plan_for_precision(const Circuit &c, int prec, int *L, int *R, int *cfix) {
@@ -189,28 +246,29 @@ Plan choose_plan(const Circuit &c, int prec) {
   int L, R, cfix;
   plan_for_precision(c, prec, &L, &R, &cfix);
   const int ov = c.tile_override[prec == NT_C64 ? 1 : 2];
+  const bool fuse = c.fuse_width[prec == NT_C64 ? 1 : 2] != 1;
   if (ov > 0) {
     const int Lo = std::min(ov, L);
     const int Ro = std::max(2, std::min(4, Lo - 6));
-    return make_plan(c, Lo, std::min(Ro, Lo), cfix);
+    return make_plan(c, Lo, std::min(Ro, Lo), cfix, fuse);
   }
-  Plan p = make_plan(c, L, R, cfix);
+  Plan p = make_plan(c, L, R, cfix, fuse);
   if (prec == NT_C64 && L == 13 && p.passes.size() > 1) {
     const int L2 = 12, R2 = std::max(2, std::min(4, L2 - 6));
-    Plan q = make_plan(c, L2, R2, cfix);
+    Plan q = make_plan(c, L2, R2, cfix, fuse);
     if ((double)q.passes.size() * 0.74 < (double)p.passes.size() * 0.95) return q;
   }
   return p;
 }
 
-Plan make_plan(const Circuit &c, int L, int R, int cfix) {
+Plan make_plan(const Circuit &c, int L, int R, int cfix, bool fuse) {
   Plan P;
   P.n = c.n;
   P.L = L;
   P.R = R;
   P.cfix = cfix;
-  std::vector<HostOp> ops = classify(c);
   const int n = c.n;
+  const std::vector<HostOp> ops = classify(c);
   const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
   for (const HostOp &op : ops)
     if (op.cls != OPC_G2 && __builtin_popcount(op.need_mask()) > R)
@@ -242,7 +300,21 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix) {
     ps.local_mask = pass_mask[p];
     ps.seg_begin = (int)P.segs.size();
     ps.op_begin = (int)P.ops.size();
-    Sched in(ops, n, pass_ops[p]);
+    // the pass's ops, with two-qubit blocks formed among them
+    // (in circuit order, a valid order of any subset, which also keeps the
+    // segment planner's ties as they are without fusion)
+    std::vector<int> sorted_ops = pass_ops[p];
+    std::sort(sorted_ops.begin(), sorted_ops.end());
+    std::vector<HostOp> pu;
+    if (fuse) {
+      pu = fuse_pass(ops, sorted_ops, n, &P.n_fused);
+    } else {
+      for (int i : sorted_ops) pu.push_back(ops[i]);
+    }
+    std::vector<int> pall(pu.size());
+    std::iota(pall.begin(), pall.end(), 0);
+    Sched in(pu, n, pall);
+    auto emit = [&](int i) { P.ops.push_back(pu[i]); };
     if (pass_ops[p].empty()) {
       Segment sg;
       sg.op_begin = sg.op_end = (int)P.ops.size();
@@ -257,7 +329,7 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix) {
         Segment sg;
         sg.kind = SEG_QUAD;
         sg.op_begin = (int)P.ops.size();
-        P.ops.push_back(ops[g2]);
+        emit(g2);
         sg.op_end = (int)P.ops.size();
         for (int q = 0; q < n && (int)sg.reg_q.size() < R; ++q)
           if ((ps.local_mask >> q) & 1) sg.reg_q.push_back(q);
@@ -271,7 +343,7 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix) {
       if (sched.empty()) throw Error(NT_ERR_UNSUPPORTED, "segment planner made no progress");
       Segment sg;
       sg.op_begin = (int)P.ops.size();
-      for (int i : sched) P.ops.push_back(ops[i]);
+      for (int i : sched) emit(i);
       sg.op_end = (int)P.ops.size();
       for (int q = 0; q < n; ++q)
         if ((rset >> q) & 1) sg.reg_q.push_back(q);
@@ -295,7 +367,16 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix) {
   }
   P.op_of_gate.assign(c.gates.size(), -1);
   for (size_t o = 0; o < P.ops.size(); ++o) {
-    int g = P.ops[o].gate;
+    const HostOp &op = P.ops[o];
+    // a fused block's one-qubit gates first (interior sites), then its CNOT
+    for (int k = 0; k < 2; ++k) {
+      const int g = op.pre[k];
+      if (g < 0) continue;
+      P.op_of_gate[g] = (int)o;
+      P.app_site.push_back((int32_t)site_base[g]);
+      P.app_tag.push_back(((uint32_t)o << 8) | ((uint32_t)c.gates[g].q[0] << 2) | SITE_INTERIOR);
+    }
+    const int g = op.gate;
     P.op_of_gate[g] = (int)o;
     const HostGate &hg = c.gates[g];
     for (int j = 0; j < hg.nq; ++j) {

@@ -196,3 +196,41 @@ def test_heavy_output_quantum_volume_vs_oracle(P, ctx, orc, prec):
         assert np.abs(v - want).max() <= tol
         P.nt_circuit_free(h)
     P.nt_set_criterion(ctx, P.NT_CRIT_FIDELITY, 0)
+
+
+def _magic_pair_circuit(n):
+    """Every qubit prepared with Bloch vector (1, 1, 1)/sqrt(3), then three
+    identity rotations: a Pauli on k qubits leaves F = 3^-k."""
+    th = math.acos(1 / math.sqrt(3))
+    g = []
+    for q in range(n):
+        g.append(W.Gate("U", (q,), (math.pi / 4, th, 0.0)))
+        g += [W.Gate("RZ", (q,), (0.0,)) for _ in range(3)]
+    return W.Circuit(n, g)
+
+
+@pytest.mark.parametrize("case", ["eq5", "monte_carlo"])
+def test_tolerable_rate_fig3_vs_oracle(P, ctx, orc, case):
+    """The paper's steps (Sec. IV-D, Fig. 3): exhaustive simulation, then
+    Eq. 5 when at most one error is tolerable, else Monte Carlo at
+    increasing rates and the search.  complex128 on identical seeds: the
+    single-error success probabilities, the branch, the probe count and the
+    rate equal the oracle's."""
+    if case == "eq5":
+        c, tau, N = W.random_layers(6, 4, np.random.default_rng(91)), 0.9, 2000
+    else:
+        c, tau, N = _magic_pair_circuit(2), 0.3, 4000
+    h = P.nt_circuit_load(None, c)
+    P.nt_set_precision(ctx, P.NT_C128)
+    P.nt_set_criterion(ctx, P.NT_CRIT_FIDELITY, 0)
+    _say(f"tolerable rate by the paper's steps: {case}, n={c.n}, S={c.S}")
+    p, method, probes, p4 = P.nt_tolerable_rate_fig3(ctx, h, 0.66, 0.01, 3, N, tau)
+    rc, p_o, method_o, probes_o, p4_o = orc.tolerable_rate_fig3(c, 0.66, 0.01, 3, N, tau)
+    assert rc == 0
+    np.testing.assert_array_equal(p4, p4_o)
+    assert method == method_o == (0 if case == "eq5" else 1)
+    assert probes == probes_o
+    assert p == p_o
+    if case == "eq5":
+        assert p == orc.eq5(0.66, p4_o[:3], p4_o[3], c.S) and p <= 1.0 / c.S
+    P.nt_circuit_free(h)
