@@ -224,6 +224,25 @@ nt_status nt_run(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_
                  uint64_t n_traj, double tau, double *fid_out, uint64_t *count_out,
                  double *p_out);
 
+/* nt_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same trajectories, scoring and outputs as nt_run with the short-cuts off
+ * (short-cut flags are ignored here), but no hipMalloc, hipFree or other
+ * allocating routine is called.  Every device buffer of the call (the
+ * circuit's plan tables and error-free reference state, rebuilt on every
+ * call, and the per-trajectory events, states, partials and frames) lives in
+ * one static scratch array of 64 MiB per device, held until the process
+ * ends.  Limit: the plan tables, the reference state and one trajectory's
+ * buffers must fit in it (complex64 states up to about 2^21 amplitudes);
+ * larger requests fail with NT_ERR_UNSUPPORTED before any launch.
+ * Trajectories run in chunks that fit.  All calls on one device share its
+ * array and the last call's contents stay in it: calls that overlap on one
+ * device (several contexts or threads) race.  Arguments and outputs as in
+ * nt_run. */
+nt_status nt_run_noalloc(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_begin,
+                         uint64_t n_traj, double tau, double *fid_out, uint64_t *count_out,
+                         double *p_out);
+
 /* Batched Monte Carlo over many independent circuits (instances of
  * different sizes): for each circuit i, trajectories [traj_begin,
  * traj_begin + n_traj) under the context's error model, precision and

@@ -42,7 +42,7 @@ GATE_KIND = {
 EXPORTED = [
     "nt_create", "nt_destroy", "nt_set_error_model", "nt_set_precision", "nt_set_max_batch",
     "nt_circuit_load", "nt_circuit_load_text", "nt_circuit_free", "nt_circuit_info",
-    "nt_circuit_set_id", "nt_plan_info", "nt_plan_export", "nt_run", "nt_sweep", "nt_tolerable_rate",
+    "nt_circuit_set_id", "nt_plan_info", "nt_plan_export", "nt_run", "nt_run_noalloc", "nt_sweep", "nt_tolerable_rate",
     "nt_tolerable_rate_auto", "nt_tolerable_rate_fig3",
     "nt_sample_sites", "nt_final_state", "nt_reference_state", "nt_timing_enable",
     "nt_timing_reset", "nt_timing_read", "nt_last_error", "nt_version",
@@ -110,6 +110,7 @@ def lib() -> C.CDLL:
         "nt_plan_info": ([P, i32, P, P, P], i32),
         "nt_plan_export": ([P, i32, P, P, P, P, P], i32),
         "nt_run": ([P, P, u64, u64, u64, dbl, P, P, P], i32),
+        "nt_run_noalloc": ([P, P, u64, u64, u64, dbl, P, P, P], i32),
         "nt_sweep": ([P, P, P, i32, u64, u64, dbl, P], i32),
         "nt_tolerable_rate": ([P, P, dbl, dbl, dbl, dbl, u64, u64, dbl, P, P], i32),
         "nt_tolerable_rate_auto": ([P, P, dbl, dbl, u64, u64, dbl, P, P, P, P], i32),
@@ -288,6 +289,22 @@ def nt_run(ctx, circ, seed: int, traj_begin: int, n_traj: int, tau: float,
     return cnt.value, p.value
 
 
+
+def nt_run_noalloc(ctx, circ, seed: int, traj_begin: int, n_traj: int, tau: float,
+           fid_out: Optional[np.ndarray] = None, fid_out_ptr: Optional[int] = None):
+    """nt_run without device allocation (static scratch array).  Returns (count, p).  fid_out: host float64 array of n_traj, or
+    fid_out_ptr: a device pointer (e.g. torch tensor data_ptr())."""
+    cnt = C.c_uint64()
+    p = C.c_double()
+    if fid_out is not None:
+        assert fid_out.dtype == np.float64 and fid_out.size >= n_traj and fid_out.flags.c_contiguous
+        fp = _ptr(fid_out)
+    elif fid_out_ptr is not None:
+        fp = C.c_void_p(fid_out_ptr)
+    else:
+        fp = None
+    _check(lib().nt_run_noalloc(ctx, circ, seed, traj_begin, n_traj, tau, fp, C.byref(cnt), C.byref(p)))
+    return cnt.value, p.value
 
 def nt_run_batch(ctx, circs, seed: int, traj_begin: int, n_traj: int, tau: float,
                  vals_out: Optional[np.ndarray] = None, vals_out_ptr: Optional[int] = None):

@@ -274,6 +274,22 @@ nt_status nt_run(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_
   });
 }
 
+nt_status nt_run_noalloc(nt_ctx *ctx, const nt_circuit *c, uint64_t seed, uint64_t traj_begin, uint64_t n_traj,
+                         double tau, double *fid_out, uint64_t *count_out, double *p_out) {
+  nt_status s = check_run_args(ctx, c, tau);
+  if (s) return s;
+  if (n_traj == 0) return fail(NT_ERR_INVALID_ARG, "n_traj must be > 0");
+  return guard([&] {
+    nt::Ctx &cx = *ctx->impl;
+    uint64_t cnt = 0;
+    double sum = 0;
+    const bool fidc = cx.crit == NT_CRIT_FIDELITY;
+    cx.run_noalloc(*c->impl, seed, traj_begin, n_traj, tau, fid_out, &cnt, (p_out && !fidc) ? &sum : nullptr);
+    if (count_out) *count_out = cnt;
+    if (p_out) *p_out = fidc ? (double)cnt / (double)n_traj : sum / (double)n_traj;
+  });
+}
+
 nt_status nt_run_batch(nt_ctx *ctx, const nt_circuit *const *circuits, int n_circ, uint64_t seed,
                        uint64_t traj_begin, uint64_t n_traj, double tau, double *vals_out, uint64_t *count_out,
                        double *p_out) {

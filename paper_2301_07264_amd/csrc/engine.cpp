@@ -87,6 +87,8 @@ Ctx::Ctx(int dev, void *s) : device(dev) {
   }
   if (dev < 0 || dev >= count) throw Error(NT_ERR_INVALID_ARG, "device index out of range");
   check_hip(hipSetDevice(dev), "hipSetDevice");
+  // device address of this device's scratch array (allocation-free runs)
+  check_hip(ntk::scratch_address(dev, &scratch), "hipGetSymbolAddress(scratch)");
   if (s) {
     stream = static_cast<hipStream_t>(s);
   } else {
@@ -657,6 +659,100 @@ void Ctx::run(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double t
   check_hip(ntk::launch_zero_words(count.as<uint32_t>(), 2, stream), "k_zero_words launch");
   if (!dev_out) fid.ensure((size_t)bs * sizeof(double));
   // host copy of the values when their sum is asked for and fid_out is not on the host
+  std::vector<double> hv(sum_out && (!fid_out || dev_out) ? n : 0);
+  double *host_vals = sum_out ? (fid_out && !dev_out ? fid_out : hv.data()) : (dev_out ? nullptr : fid_out);
+  for (uint64_t off = 0; off < n; off += bs) {
+    const int B = (int)std::min<uint64_t>(bs, n - off);
+    double *fd = dev_out ? fid_out + off : fid.as<double>();
+    simulate_batch(c, dp, seed, t0 + off, B, 0, tau, fd, count.as<uint64_t>(), th);
+    if (host_vals)
+      check_hip(hipMemcpyAsync(host_vals + off, fd, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, stream),
+                "copy fidelities");
+  }
+  uint64_t cnt = 0;
+  check_hip(hipMemcpyAsync(&cnt, count.p, sizeof cnt, hipMemcpyDeviceToHost, stream), "copy count");
+  sync();
+  if (count_out) *count_out = cnt;
+  if (sum_out) {
+    double sum = 0;
+    for (uint64_t i = 0; i < n; ++i) sum += host_vals[i];
+    *sum_out = sum;
+  }
+}
+
+// nt_run without device allocation: the plan tables, the reference state and
+// every per-trajectory buffer of the call are carved out of this device's
+// static scratch array (ntk::SCRATCH_BYTES), rebuilt on every call.  The
+// short-cuts are not used (every trajectory is simulated in full); values are
+// those of nt_run with the short-cuts off.
+void Ctx::run_noalloc(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
+                      uint64_t *count_out, double *sum_out) {
+  check_hip(hipSetDevice(device), "hipSetDevice");
+  check_target(c);
+  if (!scratch) throw Error(NT_ERR_DEVICE, "no scratch array address for this device");
+  Arena ar;
+  ar.base = static_cast<char *>(scratch);
+  ar.cap = ntk::SCRATCH_BYTES;
+  // the context's working buffers point into the arena for the call
+  DevBuf *work[] = {&events, &ev_count, &partials, &frames, &states, &fid, &count, &hist, &tmp};
+  struct Held {
+    DevBuf *b;
+    void *p;
+    size_t bytes;
+    Arena *arena;
+  };
+  std::vector<Held> held;
+  for (DevBuf *b : work) {
+    held.push_back({b, b->p, b->bytes, b->arena});
+    b->p = nullptr;
+    b->bytes = 0;
+    b->arena = &ar;
+  }
+  const bool was_timing = timing;
+  timing = false;
+  struct Restore {
+    std::vector<Held> &h;
+    bool &timing;
+    bool was;
+    ~Restore() {
+      for (Held &x : h) {
+        x.b->p = x.p;
+        x.b->bytes = x.bytes;
+        x.b->arena = x.arena;
+      }
+      timing = was;
+    }
+  } restore{held, timing, was_timing};
+
+  DevPlan dp;
+  for (DevBuf *b : {&dp.ops, &dp.segs, &dp.passes, &dp.app_order, &dp.app_tag, &dp.site_order, &dp.site_tag, &dp.ref,
+                    &dp.nref, &dp.ref_partials, &dp.ckpt, &dp.ckpt_partials, &dp.nref_pass})
+    b->arena = &ar;
+  dp.prec = prec;
+  dp.plan = choose_plan(c, prec);
+  upload_plan(c, dp);
+  ensure_reference(c, dp);
+  PassRun probe;
+  if (crit != NT_CRIT_FIDELITY) criterion_args(c, dp, probe);   // heavy-set median before the chunks
+  const Thresholds th = make_thresholds(px, py, pz);
+  const Plan &P = dp.plan;
+  const size_t dim = (size_t)1 << c.n;
+  const size_t ntiles = (size_t)1 << (c.n - P.L);
+  const size_t S = (size_t)std::max<int64_t>(c.S, 1);
+  const bool dev_out = is_device_pointer(fid_out);
+  count.ensure(sizeof(uint64_t));
+  // bytes per trajectory of a chunk, 256-byte alignment of each buffer included
+  const size_t per = S * 4 + 4 + ntiles * ntk::NPART * sizeof(double) + 2 * 4 * sizeof(uint32_t) +
+                     (P.passes.size() > 1 ? dim * amp_bytes(prec) : 0) + (dev_out ? 0 : sizeof(double));
+  const size_t slack = 8 * 256;
+  const size_t left = ar.cap - std::min(ar.cap, ((ar.off + 255) & ~(size_t)255) + slack);
+  const uint64_t bs = std::min<uint64_t>(n, left / per);
+  if (bs == 0)
+    throw Error(NT_ERR_UNSUPPORTED, "one trajectory of this circuit does not fit in the " +
+                                        std::to_string(ntk::SCRATCH_BYTES >> 20) +
+                                        " MiB scratch array of the allocation-free entry point");
+  check_hip(ntk::launch_zero_words(count.as<uint32_t>(), 2, stream), "k_zero_words launch");
+  if (!dev_out) fid.ensure((size_t)bs * sizeof(double));
   std::vector<double> hv(sum_out && (!fid_out || dev_out) ? n : 0);
   double *host_vals = sum_out ? (fid_out && !dev_out ? fid_out : hv.data()) : (dev_out ? nullptr : fid_out);
   for (uint64_t off = 0; off < n; off += bs) {

@@ -92,6 +92,7 @@ struct ReuseKey {
 
 struct Ctx {
   int device = 0;
+  void *scratch = nullptr;     // device address of this device's scratch array
   hipStream_t stream = nullptr;
   bool own_stream = false;
   double px = 0, py = 0, pz = 0;
@@ -142,6 +143,10 @@ struct Ctx {
            uint64_t *count_out, double *sum_out = nullptr);
   void run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
                     uint64_t *count_out, double *sum_out);
+  // run() without device allocation: every device buffer of the call lives
+  // in this device's static scratch array (no short-cuts)
+  void run_noalloc(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau, double *fid_out,
+                   uint64_t *count_out, double *sum_out);
   // Success probability of n trajectories: the fraction with F >= tau for
   // the fidelity criterion, the mean measurement probability otherwise.
   double success(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, double tau);

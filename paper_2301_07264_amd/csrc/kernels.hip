@@ -22,6 +22,8 @@
 // <R|psi> = i^c sum_j conj(R[j ^ x]) (-1)^{popcount(z & j)} s[j].
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace ntk {
@@ -1221,6 +1223,35 @@ hipError_t launch_unframe(const cx<T> *st, cx<T> *out, uint64_t dim, const uint3
 template hipError_t launch_unframe<float>(const cx<float> *, cx<float> *, uint64_t, const uint32_t *, hipStream_t);
 template hipError_t launch_unframe<double>(const cx<double> *, cx<double> *, uint64_t, const uint32_t *,
                                            hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Scratch memory of the allocation-free entry point: one static array per
+// device, held until the process ends.  Host code never uses the array's
+// name as an address; it uses the device address looked up once per device
+// (scratch_address), with that device current.
+
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+hipError_t scratch_address(int device, void **out) {
+  static std::mutex mu;
+  static void *addr[64] = {};
+  static bool have[64] = {};
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!have[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;   // the caller makes `device` current
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = ptr;
+    have[device] = true;
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
 
 __global__ void __launch_bounds__(256) k_zero_words(uint32_t *p, uint64_t n) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

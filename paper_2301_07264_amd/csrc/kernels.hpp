@@ -192,6 +192,12 @@ struct SampleArgs {
   int32_t per_item;
 };
 
+// Size of the static scratch array of the allocation-free entry point (one
+// per device).
+constexpr size_t SCRATCH_BYTES = (size_t)64 << 20;
+// Device address of that array on `device`, which must be the current
+// device; looked up once per device (hipGetSymbolAddress), then cached.
+hipError_t scratch_address(int device, void **out);
 // p[0..n) = 0 with a kernel (no memset node, so it also records in graphs).
 hipError_t launch_zero_words(uint32_t *p, uint64_t n, hipStream_t s);
 
