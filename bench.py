@@ -86,6 +86,10 @@ def main():
                          "exact short-cuts on); default on for the 24-qubit workload")
     ap.add_argument("--no-ttr", dest="ttr", action="store_false", help="skip the tolerable-rate search")
     ap.add_argument("--ttr-traj", type=int, default=10000)
+    ap.add_argument("--sweep-traj", type=int, default=1000,
+                    help="trajectories of the timed 13-point sweep baseline (0: skip)")
+    ap.add_argument("--no-sub", action="store_true",
+                    help="skip the 30-qubit sub-record of the default run")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device copy of this many bytes (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -117,16 +121,35 @@ def main():
         return bench_batch(args, P, W)
     if args.workload == "surrogate":
         return bench_surrogate(args, P, W)
-    if args.workload == "ghz_qft_layers24":
+    out = bench_single(args, P, W, args.workload, False)
+    if args.workload == "ghz_qft_layers24" and not args.no_sub:
+        # the 30-qubit workload beside it (8 GiB states, HBM-bound): its own
+        # amplitude-update rate and roofline, no search and no CPU leg
+        print("bench: 30-qubit workload (sub-record) ...", file=sys.stderr, flush=True)
+        sub = bench_single(args, P, W, "qaoa3reg30", True)
+        out["sub_records"] = {"qaoa3reg30": {k: sub[k] for k in ("value", "unit", "ms_per_step", "steps", "warmup",
+                                                               "config", "roofline")}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_single(args, P, W, workload, sub):
+    """One gate-pass workload: `steps` timed batches of trajectories after
+    `warmup` untimed ones; sub: a sub-record (5 steps, 1 warmup, default
+    batch, no search and no CPU leg)."""
+    import numpy as np
+    import torch
+
+    steps, warmup = (5, 1) if sub else (args.steps, args.warmup)
+    if workload == "ghz_qft_layers24":
         circ = W.config1()
         rates = W.rates_config1()
         wl = "ghz+qft+50 random layers, 24 qubits, G=2136, S=3047, 13 rates 1e-5..1e-2 cycled per step"
-        B = args.batch or 32
+        B = (0 if sub else args.batch) or 32
     else:
         circ = W.config4()
         rates = W.rates_config4()
         wl = "alternating layers on a random 3-regular graph, 30 qubits, G=330, S=510, 7 rates 1e-5..1e-3 cycled per step"
-        B = args.batch or 4
+        B = (0 if sub else args.batch) or 4
     n, G, S = circ.n, circ.G, circ.S
     prec = P.NT_C64 if args.prec == "c64" else P.NT_C128
     tau = 0.9
@@ -155,7 +178,7 @@ def main():
     # resident inputs: plan upload + reference state happen here
     P.nt_set_error_model(ctx, 0, 0, 0)
     P.nt_run(ctx, h, 0, 0, 1, tau)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
 
@@ -166,7 +189,7 @@ def main():
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     e1.record(stream)
     torch.cuda.synchronize()
@@ -174,7 +197,7 @@ def main():
     launches, pass_ms, pass_bytes, pass_updates, pass_flops = P.nt_timing_read(ctx)
     P.nt_timing_enable(ctx, False)
 
-    n_traj = args.steps * B
+    n_traj = steps * B
     updates = float(n_traj) * G * (1 << n)
     value = updates / (ms / 1e3)
     amp = 8 if prec == P.NT_C64 else 16
@@ -189,22 +212,20 @@ def main():
         with open(args.traffic) as f:
             traffic = json.load(f).get("bytes_per_launch")
     else:
-        m = MEASURED_TRAFFIC.get((args.workload, args.prec, B))
+        m = MEASURED_TRAFFIC.get((workload, args.prec, B))
         if m and m["kernel_sha256"] == kernel_sha256() and m["passes"] == n_pass:
             traffic = m["bytes_per_launch"]
 
     ttr = None
-    if args.ttr:
-        # Time-to-tolerable-rate: regula falsi (Illinois) in log10 p with the
-        # same trajectories at every probe.  Zero-fired trajectories and
-        # error-free prefixes are not simulated (bit-identical results), and a
-        # trajectory is scored after its last error against the error-free
-        # state there (the common unitary suffix keeps the overlap: exact in
-        # arithmetic, equal to the full run up to rounding).  A trajectory
-        # whose fired set at a probe equals one it had at an earlier probe
-        # (same count: the sets are nested across rates) reuses that value.
-        P.nt_set_shortcuts(ctx, P.NT_SHORTCUT_ZERO_FIRED | P.NT_SHORTCUT_CHECKPOINT | P.NT_SHORTCUT_LAST_ERROR
-                           | P.NT_SHORTCUT_REUSE)
+    sweep = None
+    if args.ttr and not sub:
+        # Time-to-tolerable-rate with the bit-identical short-cuts: zero-fired
+        # trajectories are not simulated, a trajectory starts at the error-free
+        # checkpoint before its first error, and a trajectory whose fired set
+        # at a probe equals one it had at an earlier probe (same count: the
+        # sets are nested across rates) reuses that value.
+        flags = P.NT_SHORTCUT_ZERO_FIRED | P.NT_SHORTCUT_CHECKPOINT | P.NT_SHORTCUT_REUSE
+        P.nt_set_shortcuts(ctx, flags)
         P.nt_set_max_batch(ctx, 0)
         print("bench: timing the tolerable-rate search ...", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
@@ -222,18 +243,49 @@ def main():
         probes = k_c + k_f
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        P.nt_set_shortcuts(ctx, 0)
         ttr = {"seconds": dt, "p_star": p_star, "probes": probes,
                "probes_by_stage": {f"{N_coarse} trajectories": k_c, f"{N_full} trajectories": k_f},
                "P_target": 0.66, "tol": 0.01, "trajectories_per_probe": N_full, "bracket": bracket,
                "search": "Illinois in log10 p; N/5 trajectories, then all N from the coarse answer",
-               "shortcuts": "zero-fired skipped and start at the first-error checkpoint (bit-identical); "
-                            "scored after the last error (exact in arithmetic); values of trajectories whose "
-                            "fired set was already simulated at an earlier probe reused (bit-identical)",
+               "shortcuts": "bit-identical only: zero-fired trajectories skipped, start at the first-error "
+                            "checkpoint, values of fired sets already simulated at an earlier probe reused",
                "one_over_G": 1.0 / G, "zero_error_bound": p0}
+        # The baseline beside it: the plain 13-point Monte Carlo sweep with the
+        # same short-cuts (store emptied first), crossing interpolated in
+        # log10 p.  Timed on the first args.sweep_traj trajectories; every
+        # trajectory costs the same in expectation, so the time at N_full
+        # trajectories is that time scaled by N_full / args.sweep_traj.
+        if args.sweep_traj > 0:
+            P.nt_set_shortcuts(ctx, flags)          # empties the reuse store
+            print(f"bench: timing the 13-point sweep on {args.sweep_traj} trajectories ...", file=sys.stderr,
+                  flush=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Psw, p_sw = P.nt_sweep_crossing(ctx, h, rates, 0, args.sweep_traj, tau, 0.66)
+            torch.cuda.synchronize()
+            dts = time.perf_counter() - t0
+            sweep = {"seconds_measured": dts, "trajectories_measured": args.sweep_traj,
+                     "seconds_at_ttr_trajectories": dts * N_full / args.sweep_traj,
+                     "scaled": args.sweep_traj != N_full, "rates": len(rates),
+                     "p_star_interpolated": p_sw, "P": [float(x) for x in Psw],
+                     "ttr_speedup": (dts * N_full / args.sweep_traj) / dt if dt > 0 else None}
+        # The same search with the last-error short-cut added (a trajectory
+        # is scored right after the pass of its last error, against the
+        # error-free state there): exact in arithmetic, not bit for bit, so
+        # it is reported apart from the number above.
+        P.nt_set_shortcuts(ctx, flags | P.NT_SHORTCUT_LAST_ERROR)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p_le, kc_le, kf_le, _ = P.nt_tolerable_rate_auto(ctx, h, 0.66, 0.01, 0, N_full, tau)
+        torch.cuda.synchronize()
+        ttr["with_last_error_shortcut"] = {"seconds": time.perf_counter() - t0, "p_star": p_le,
+                                           "probes": kc_le + kf_le,
+                                           "note": "exact in arithmetic only: fidelities differ from the full "
+                                                   "run by rounding"}
+        P.nt_set_shortcuts(ctx, 0)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not sub:
         import oracle
         p = float(rates[len(rates) // 2])
         if n <= 26:
@@ -278,9 +330,9 @@ def main():
         "value": value,
         "unit": "amplitude-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": ms / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -294,12 +346,13 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_tolerable_rate": ttr,
+        "sweep_baseline": sweep,
         "successes": state["count"],
         "trajectories": n_traj,
     }
-    print(json.dumps(out), flush=True)
     P.nt_circuit_free(h)
     P.nt_destroy(ctx)
+    return out
 
 
 def bench_surrogate(args, P, W):

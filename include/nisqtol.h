@@ -269,6 +269,14 @@ nt_status nt_run_batch(nt_ctx *ctx, const nt_circuit *const *circuits, int n_cir
 nt_status nt_sweep(nt_ctx *ctx, const nt_circuit *c, const double *rates, int R, uint64_t seed,
                    uint64_t n_traj, double tau, double *p_out);
 
+/* The plain sweep route to the tolerable rate: nt_sweep at the ascending
+ * rates[0..R), then the rate where the success curve, linear in log10 p
+ * between grid points, first falls below P_target (rates[0] if it starts
+ * below, rates[R-1] if it never does).  p_out: R doubles (host, may be
+ * NULL). */
+nt_status nt_sweep_crossing(nt_ctx *ctx, const nt_circuit *c, const double *rates, int R, uint64_t seed,
+                            uint64_t n_traj, double tau, double P_target, double *p_out, double *p_star);
+
 /* Tolerable uniform rate (Sec. IV-D, Monte Carlo branch, Fig. 3).  The paper
  * names Powell's method without its settings; here: a safeguarded regula
  * falsi (Illinois) in x = log10(p) on f = P(10^x) - P_target over the

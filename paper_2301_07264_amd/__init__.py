@@ -42,7 +42,7 @@ GATE_KIND = {
 EXPORTED = [
     "nt_create", "nt_destroy", "nt_set_error_model", "nt_set_precision", "nt_set_max_batch",
     "nt_circuit_load", "nt_circuit_load_text", "nt_circuit_free", "nt_circuit_info",
-    "nt_circuit_set_id", "nt_plan_info", "nt_plan_export", "nt_run", "nt_run_noalloc", "nt_sweep", "nt_tolerable_rate",
+    "nt_circuit_set_id", "nt_plan_info", "nt_plan_export", "nt_run", "nt_run_noalloc", "nt_sweep", "nt_sweep_crossing", "nt_tolerable_rate",
     "nt_tolerable_rate_auto", "nt_tolerable_rate_fig3",
     "nt_sample_sites", "nt_final_state", "nt_reference_state", "nt_timing_enable",
     "nt_timing_reset", "nt_timing_read", "nt_last_error", "nt_version",
@@ -112,6 +112,7 @@ def lib() -> C.CDLL:
         "nt_run": ([P, P, u64, u64, u64, dbl, P, P, P], i32),
         "nt_run_noalloc": ([P, P, u64, u64, u64, dbl, P, P, P], i32),
         "nt_sweep": ([P, P, P, i32, u64, u64, dbl, P], i32),
+        "nt_sweep_crossing": ([P, P, P, i32, u64, u64, dbl, dbl, P, P], i32),
         "nt_tolerable_rate": ([P, P, dbl, dbl, dbl, dbl, u64, u64, dbl, P, P], i32),
         "nt_tolerable_rate_auto": ([P, P, dbl, dbl, u64, u64, dbl, P, P, P, P], i32),
         "nt_tolerable_rate_fig3": ([P, P, dbl, dbl, u64, u64, dbl, P, P, P, P], i32),
@@ -328,6 +329,17 @@ def nt_sweep(ctx, circ, rates: Sequence[float], seed: int, n_traj: int, tau: flo
     out = np.zeros(len(r), np.float64)
     _check(lib().nt_sweep(ctx, circ, _ptr(r), len(r), seed, n_traj, tau, _ptr(out)))
     return out
+
+
+def nt_sweep_crossing(ctx, circ, rates: Sequence[float], seed: int, n_traj: int, tau: float, P_target: float):
+    """The sweep route: (success probabilities at the rates, the rate where the
+    curve, linear in log10 p, first falls below P_target)."""
+    r = np.ascontiguousarray(rates, np.float64)
+    out = np.zeros(len(r), np.float64)
+    ps = C.c_double()
+    _check(lib().nt_sweep_crossing(ctx, circ, _ptr(r), len(r), seed, n_traj, tau, P_target, _ptr(out),
+                                   C.byref(ps)))
+    return out, ps.value
 
 
 def nt_tolerable_rate(ctx, circ, P_target: float, tol: float, p_lo: float, p_hi: float, seed: int,

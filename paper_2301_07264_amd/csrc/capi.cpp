@@ -340,6 +340,30 @@ nt_status nt_sweep(nt_ctx *ctx, const nt_circuit *c, const double *rates, int R,
   });
 }
 
+nt_status nt_sweep_crossing(nt_ctx *ctx, const nt_circuit *c, const double *rates, int R, uint64_t seed,
+                           uint64_t n_traj, double tau, double P_target, double *p_out, double *p_star) {
+  if (R < 1 || !rates || !p_star) return fail(NT_ERR_INVALID_ARG, "need R >= 1 rates and p_star");
+  for (int r = 1; r < R; ++r)
+    if (!(rates[r] > rates[r - 1])) return fail(NT_ERR_INVALID_ARG, "rates must be ascending");
+  if (!(rates[0] > 0)) return fail(NT_ERR_INVALID_ARG, "rates must be > 0");
+  std::vector<double> P(R, 0.0);
+  nt_status s = nt_sweep(ctx, c, rates, R, seed, n_traj, tau, P.data());
+  if (s) return s;
+  if (p_out) std::copy(P.begin(), P.end(), p_out);
+  // the rate where the curve, linear in log10 p between grid points, first
+  // falls below the target
+  *p_star = P[0] < P_target ? rates[0] : rates[R - 1];
+  for (int k = 0; k + 1 < R; ++k) {
+    if (P[k] >= P_target && P_target > P[k + 1]) {
+      const double x0 = std::log10(rates[k]), x1 = std::log10(rates[k + 1]);
+      const double t = (P[k] - P_target) / (P[k] - P[k + 1]);
+      *p_star = std::pow(10.0, x0 + t * (x1 - x0));
+      break;
+    }
+  }
+  return NT_OK;
+}
+
 nt_status nt_tolerable_rate(nt_ctx *ctx, const nt_circuit *c, double P_target, double tol, double p_lo,
                             double p_hi, uint64_t seed, uint64_t n_traj, double tau, double *p_star,
                             int *n_probes) {
