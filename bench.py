@@ -75,8 +75,12 @@ def main():
     ap.add_argument("--eval-circuits", type=int, default=16)
     ap.add_argument("--batch", type=int, default=0, help="trajectories per step (0: 32 for 24 qubits, 4 for 30)")
     ap.add_argument("--prec", choices=["c64", "c128"], default="c64")
-    ap.add_argument("--fusion", type=int, choices=[0, 1, 2], default=0,
-                    help="gate fusion of the plan: 0 automatic, 1 none, 2 two-qubit blocks")
+    ap.add_argument("--fusion", type=int, choices=[0, 1, 2, 3, 4], default=0,
+                    help="gate fusion of the plan: 0 automatic, 1 none, 2 two-qubit blocks and diagonal "
+                         "runs, 3 blocks only, 4 diagonal runs only")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="with --fusion 0: keep the library's default plan instead of the plan autotuner's "
+                         "choice of tile width and fusion (nt_autotune_plan, run before the timed region)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-traj", type=int, default=1, help="oracle trajectories timed on the host")
     ap.add_argument("--traffic", type=str, default=None,
@@ -161,6 +165,17 @@ def bench_single(args, P, W, workload, sub):
     P.nt_circuit_set_fusion(h, prec, args.fusion)
     P.nt_set_precision(ctx, prec)
     P.nt_set_max_batch(ctx, B)
+    tuned = None
+    if args.fusion == 0 and not args.no_autotune:
+        # the plan autotuner picks tile width and fusion on one batch at the
+        # middle rate (untimed set-up, like the plan upload)
+        pm = float(rates[len(rates) // 2])
+        P.nt_set_error_model(ctx, pm / 3, pm / 3, pm / 3)
+        tL, tf, tms = P.nt_autotune_plan(ctx, h, 0, B)
+        tuned = {"tile_qubits": tL, "fusion": tf, "rate": pm, "trajectories": B,
+                 "ms_per_candidate": [round(float(x), 3) for x in tms],
+                 "candidates": "tile widths from the largest down, each with fusion 2, 3, 4, 1"}
+        print(f"bench: plan autotuner chose tile {tL}, fusion {tf}", file=sys.stderr, flush=True)
     n_pass, n_seg, L = P.nt_plan_info(h, prec)
     n_ops, n_blocks = P.nt_plan_ops(h, prec)
 
@@ -341,7 +356,8 @@ def bench_single(args, P, W, workload, sub):
         "config": {"workload": wl,
                    "trajectories_per_step": B, "n_qubits": n, "gates": G, "sites": S,
                    "amplitudes": args.prec, "passes_per_trajectory": n_pass, "segments": n_seg,
-                   "tile_qubits": L, "ops_per_trajectory": n_ops, "fused_blocks": n_blocks,
+                   "tile_qubits": L, "ops_per_trajectory": n_ops, "fused_ops": n_blocks,
+                   "plan_autotune": tuned,
                    "parallelism": "single GPU, trajectory batch"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -122,8 +122,8 @@ nt_status nt_set_max_batch(nt_ctx *ctx, uint64_t max_batch);
 
 /* Copies gates[0..n_gates) after validating qubits (0 <= q < n, distinct for
  * two-qubit kinds), kinds, arity and matrices.  1 <= n_qubits <= 32.
- * 0 <= n_gates <= 2^22 (NT_ERR_UNSUPPORTED above: the device event words
- * hold an op index in 24 bits, and sites in 32-bit integers). */
+ * 0 <= n_gates <= 2^19 (NT_ERR_UNSUPPORTED above: the device event words
+ * hold an op index in 20 bits, and a plan may add one no-op per gate). */
 nt_status nt_circuit_load(nt_ctx *ctx, int n_qubits, const nt_gate *gates, int64_t n_gates,
                           nt_circuit **out);
 
@@ -151,13 +151,19 @@ nt_status nt_circuit_set_id(nt_circuit *c, uint64_t circuit_id);
 nt_status nt_circuit_set_tile(nt_circuit *c, int prec, int tile_qubits);
 
 /* Gate fusion of the circuit's plan at precision `prec`: 0 = automatic
- * (currently two-qubit blocks), 1 = none (one op per gate), 2 = two-qubit
- * blocks: a CNOT takes the one-qubit gate just before it on its target and
- * on its control into one op (both qubits then sit in registers).  An error
- * after one of the block's one-qubit gates still acts right after that gate
- * (Sec. IV-B): it enters the Pauli frame before the block's CNOT is applied
- * to the frame.  Results change at rounding level only.
- * NT_ERR_INVALID_ARG for other widths. */
+ * (currently 2), 1 = none (one op per gate), 2 = two-qubit blocks and
+ * diagonal runs, 3 = two-qubit blocks only, 4 = diagonal runs only.  Within
+ * a pass, a two-qubit gate takes the runs of
+ * one-qubit gates right before it on its qubits (not already taken) and,
+ * when it took any, the runs right after it, and the block is applied as one
+ * dense 4x4 (both qubits then sit in registers) when a cost model prices it
+ * below its gates.  Within a register segment, runs of at least three
+ * diagonal gates (each with at most one qubit in the registers) multiply
+ * every amplitude once by the product of their phases.  An error inside a
+ * block or run still acts right after its gate (Sec. IV-B): a trajectory
+ * with such an error applies that block gate by gate, and a run takes each
+ * gate's phase under the errors before it.  Results change at rounding
+ * level only.  NT_ERR_INVALID_ARG for other widths. */
 nt_status nt_circuit_set_fusion(nt_circuit *c, int prec, int width);
 
 /* Autotuner: runs n_traj trajectories (seed, current error model) with each
@@ -167,6 +173,17 @@ nt_status nt_circuit_set_fusion(nt_circuit *c, int prec, int width);
  * (up to 3 entries). */
 nt_status nt_autotune(nt_ctx *ctx, nt_circuit *c, uint64_t seed, uint64_t n_traj, int *tile_out,
                       double *ms_out);
+
+/* Autotuner over the plan: tile width and gate fusion together.  Runs n_traj
+ * trajectories (seed, current error model and precision) for each tile
+ * width from the largest down to two below it and each fusion width in
+ * {2, 3, 4, 1} (nt_circuit_set_fusion), keeps the fastest pair as the
+ * circuit's tile width and fusion width at the context's precision and
+ * returns it.  ms_out (may be NULL): milliseconds per candidate, tile-major in
+ * the order tried, at most ms_cap entries written.  Values are those of the
+ * chosen plan (plans differ at rounding level only). */
+nt_status nt_autotune_plan(nt_ctx *ctx, nt_circuit *c, uint64_t seed, uint64_t n_traj, int *tile_out,
+                           int *fusion_out, double *ms_out, int ms_cap);
 
 /* Host-only view of the gate-pass plan used for precision `prec`: number of
  * HBM passes over a state vector per trajectory, LDS segments, and the
@@ -183,8 +200,10 @@ nt_status nt_plan_info(const nt_circuit *c, int prec, int *n_passes, int *n_segm
 nt_status nt_plan_export(const nt_circuit *c, int prec, int32_t *op_gate, int32_t *op_pass,
                          int32_t *op_segment, uint64_t *pass_local_mask, uint64_t *segment_reg_mask);
 
-/* Host-only: ops the plan runs per trajectory (a fused block counts once)
- * and the number of fused blocks. */
+/* Host-only: ops the plan runs per trajectory (a fused op counts once;
+ * no-op pads that keep fused ops at even positions of their segments
+ * included) and the number of fused ops (two-qubit blocks and diagonal
+ * runs). */
 nt_status nt_plan_ops(const nt_circuit *c, int prec, int64_t *n_ops, int64_t *n_fused);
 
 /* ---- success criterion (Sec. II, Sec. V) ----------------------------------- */

@@ -50,7 +50,7 @@ EXPORTED = [
     "nt_set_criterion", "nt_run_batch",
     "nt_gnn_create", "nt_gnn_destroy", "nt_gnn_graph", "nt_gnn_params", "nt_gnn_set_params",
     "nt_gnn_set_data", "nt_gnn_loss_grad", "nt_gnn_train", "nt_gnn_predict", "nt_tolerable_rate_guided",
-    "nt_circuit_set_tile", "nt_circuit_set_fusion", "nt_autotune", "nt_plan_ops",
+    "nt_circuit_set_tile", "nt_circuit_set_fusion", "nt_autotune", "nt_autotune_plan", "nt_plan_ops",
 ]
 
 GNN_RATES = [10.0 ** (-5.0 + j / 4.0) for j in range(13)]
@@ -139,6 +139,7 @@ def lib() -> C.CDLL:
         "nt_circuit_set_fusion": ([P, i32, i32], i32),
         "nt_plan_ops": ([P, i32, P, P], i32),
         "nt_autotune": ([P, P, u64, u64, P, P], i32),
+        "nt_autotune_plan": ([P, P, u64, u64, P, P, P, i32], i32),
         "nt_exhaustive": ([P, P, dbl, P, P, P], i32),
         "nt_eq4": ([P, dbl, P, P], i32),
         "nt_eq5": ([dbl, P, dbl, dbl, P], i32),
@@ -572,3 +573,13 @@ def nt_autotune(ctx, circ, seed: int, n_traj: int):
     ms = np.zeros(3, np.float64)
     _check(lib().nt_autotune(ctx, circ, seed, n_traj, C.byref(t), _ptr(ms)))
     return t.value, ms
+
+
+def nt_autotune_plan(ctx, circ, seed: int, n_traj: int):
+    """Returns (chosen tile width, chosen fusion width, milliseconds per
+    candidate, tile-major over fusion widths 2, 3, 4, 1)."""
+    t = C.c_int()
+    f = C.c_int()
+    ms = np.zeros(12, np.float64)
+    _check(lib().nt_autotune_plan(ctx, circ, seed, n_traj, C.byref(t), C.byref(f), _ptr(ms), 12))
+    return t.value, f.value, ms

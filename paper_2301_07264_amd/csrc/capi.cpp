@@ -159,7 +159,7 @@ nt_status nt_circuit_set_tile(nt_circuit *c, int prec, int tile_qubits) {
 nt_status nt_circuit_set_fusion(nt_circuit *c, int prec, int width) {
   if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
   if (prec != NT_C64 && prec != NT_C128) return fail(NT_ERR_INVALID_ARG, "precision must be NT_C64 or NT_C128");
-  if (width < 0 || width > 2) return fail(NT_ERR_INVALID_ARG, "fusion width must be 0, 1 or 2");
+  if (width < 0 || width > 4) return fail(NT_ERR_INVALID_ARG, "fusion width must be in 0..4");
   c->impl->fuse_width[prec == NT_C64 ? 1 : 2] = width;
   g_last_error.clear();
   return NT_OK;
@@ -200,6 +200,50 @@ nt_status nt_autotune(nt_ctx *ctx, nt_circuit *c, uint64_t seed, uint64_t n_traj
   return NT_OK;
 }
 
+nt_status nt_autotune_plan(nt_ctx *ctx, nt_circuit *c, uint64_t seed, uint64_t n_traj, int *tile_out,
+                           int *fusion_out, double *ms_out, int ms_cap) {
+  nt_status s = check_run_args(ctx, c, 0.9);
+  if (s) return s;
+  if (n_traj == 0) return fail(NT_ERR_INVALID_ARG, "n_traj must be > 0");
+  if (ms_out && ms_cap < 0) return fail(NT_ERR_INVALID_ARG, "ms_cap must be >= 0");
+  const int slot = ctx->impl->prec == NT_C64 ? 1 : 2;
+  const int saved_tile = c->impl->tile_override[slot], saved_fuse = c->impl->fuse_width[slot];
+  int best_tile = 0, best_fuse = 0;
+  nt_status st = guard([&] {
+    nt::Ctx &cx = *ctx->impl;
+    int lo = 0, hi = 0;
+    nt::tile_range(*c->impl, cx.prec, &lo, &hi);
+    double best_ms = 0;
+    int k = 0;
+    for (int L = hi; L >= std::max(lo, hi - 2); --L)
+      for (int fw : {2, 3, 4, 1}) {
+        c->impl->tile_override[slot] = L;
+        c->impl->fuse_width[slot] = fw;
+        cx.run(*c->impl, seed, 0, std::min<uint64_t>(n_traj, 4), 0.9, nullptr, nullptr);   // plan, reference, warm-up
+        const auto t0 = std::chrono::steady_clock::now();
+        cx.run(*c->impl, seed, 0, n_traj, 0.9, nullptr, nullptr);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (ms_out && k < ms_cap) ms_out[k] = ms;
+        ++k;
+        if (best_tile == 0 || ms < best_ms) {
+          best_tile = L;
+          best_fuse = fw;
+          best_ms = ms;
+        }
+      }
+    c->impl->tile_override[slot] = best_tile;
+    c->impl->fuse_width[slot] = best_fuse;
+  });
+  if (st) {
+    c->impl->tile_override[slot] = saved_tile;
+    c->impl->fuse_width[slot] = saved_fuse;
+    return st;
+  }
+  if (tile_out) *tile_out = best_tile;
+  if (fusion_out) *fusion_out = best_fuse;
+  return NT_OK;
+}
+
 nt_status nt_plan_info(const nt_circuit *c, int prec, int *n_passes, int *n_segments, int *tile_qubits) {
   if (!c) return fail(NT_ERR_INVALID_ARG, "circuit is NULL");
   if (prec != NT_C64 && prec != NT_C128) return fail(NT_ERR_INVALID_ARG, "precision must be NT_C64 or NT_C128");
@@ -217,7 +261,7 @@ nt_status nt_plan_ops(const nt_circuit *c, int prec, int64_t *n_ops, int64_t *n_
   return guard([&] {
     nt::Plan P = nt::choose_plan(*c->impl, prec);
     if (n_ops) *n_ops = (int64_t)P.ops.size();
-    if (n_fused) *n_fused = P.n_fused;
+    if (n_fused) *n_fused = P.n_fused + P.n_diag;
   });
 }
 
@@ -238,8 +282,7 @@ nt_status nt_plan_export(const nt_circuit *c, int prec, int32_t *op_gate, int32_
         if (segment_reg_mask) segment_reg_mask[s] = m;
         for (int o = sg.op_begin; o < sg.op_end; ++o) {
           const nt::HostOp &h = P.ops[o];
-          for (int g : {h.pre[0], h.pre[1], h.gate}) {   // a fused block: its three gates
-            if (g < 0) continue;
+          for (int g : h.gates()) {   // a fused block: its gates in order
             if (op_gate) op_gate[k] = g;
             if (op_pass) op_pass[k] = (int32_t)p;
             if (op_segment) op_segment[k] = s;

@@ -99,7 +99,7 @@ static void validate_and_fill(Circuit *c, int n, const nt_gate *gates, int64_t G
   if (n < 1 || n > 32) throw Error(NT_ERR_INVALID_ARG, "n_qubits must be in [1, 32]");
   if (G < 0) throw Error(NT_ERR_INVALID_ARG, "n_gates must be >= 0");
   if (G > 0 && !gates) throw Error(NT_ERR_INVALID_ARG, "gates is NULL");
-  if (G > (int64_t(1) << 22)) throw Error(NT_ERR_UNSUPPORTED, "more than 2^22 gates");
+  if (G > (int64_t(1) << 19)) throw Error(NT_ERR_UNSUPPORTED, "more than 2^19 gates");
   c->n = n;
   c->gates.resize((size_t)G);
   c->S = 0;
@@ -292,7 +292,7 @@ double gate_flops(const HostGate &g) {
 uint32_t HostOp::need_mask() const {
   switch (cls) {
     case OPC_G1: case OPC_C1: return 1u << qa;
-    case OPC_G2: case OPC_UCX: return (1u << qa) | (1u << qb);
+    case OPC_G2: case OPC_G4: return (1u << qa) | (1u << qb);
     default: return 0u;
   }
 }

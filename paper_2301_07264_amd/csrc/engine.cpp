@@ -18,7 +18,8 @@
 
 namespace nt {
 
-static_assert(SITE_INTERIOR == ntk::EV_INTERIOR, "interior-site flag of the planner and the gate kernel");
+static_assert(SITE_OP_SHIFT == ntk::EV_OP_SHIFT && SITE_STAGE_END == ntk::EV_STAGE_END,
+              "event word layout of the planner and the gate kernel");
 
 void check_hip(hipError_t e, const char *what) {
   if (e != hipSuccess) {
@@ -163,20 +164,102 @@ static int32_t op_code(const HostOp &h, int rbit) {
       return ntk::OPK_CX * 4 + rbit;
     case OPC_D1: return ntk::OPK_D1 * 4;
     case OPC_D2: return ntk::OPK_D2 * 4;
+    case OPC_NOP: return ntk::OPK_NOP * 4;
     default: return ntk::OPK_G2 * 4;
   }
 }
 
+// Rounded entries of the 16 frame variants of a 4x4 (local index b_qa +
+// 2 b_qb): conjugated by X^x Z^z on the two qubits, entry (i, j) is
+// (-1)^popcount(z & (i ^ j)) M[i ^ x][j ^ x]; variant x + 4 z, 16 entries
+// each (rounded once, then permuted and negated exactly).
+template <typename T>
+static void push_variants(const cd *M, bool swap_ab, std::vector<ntk::cx<T>> &out) {
+  auto sw = [](int i) { return ((i & 1) << 1) | (i >> 1); };
+  for (int z = 0; z < 4; ++z)
+    for (int x = 0; x < 4; ++x)
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          const int si = swap_ab ? sw(i ^ x) : (i ^ x), sj = swap_ab ? sw(j ^ x) : (j ^ x);
+          ntk::cx<T> e{(T)M[4 * si + sj].real(), (T)M[4 * si + sj].imag()};
+          if (__builtin_popcount((unsigned)(z & (i ^ j))) & 1) e = ntk::cx<T>{-e.x, -e.y};
+          out.push_back(e);
+        }
+}
+
 // rsel / code per op are computed with the pass layouts (register bit of the
 // dense qubit for register-segment ops, tile-local positions for quad ops).
+// Fused blocks keep their matrices in the plan's aux table: the block's
+// product, then one 4x4 per gate (the stages its interior errors split it
+// into), each as its 16 frame variants; rsel holds the block's first matrix
+// index and its stage count.
+// Fused diagonal runs keep one DfRec per gate in the aux table (16-byte
+// aligned).
 template <typename T>
-static void upload_ops(DevPlan &dp, const std::vector<int32_t> &code, const std::vector<int32_t> &rsel,
-                       const std::vector<char> &swap_ab, hipStream_t s) {
+static void push_diag_record(const HostGate &g, int rb0, int rb1, std::vector<ntk::cx<T>> &out) {
+  cd d[4];
+  if (g.nq == 1) {
+    d[0] = g.m[0];
+    d[1] = g.m[3];
+  } else {
+    for (int i = 0; i < 4; ++i) d[i] = g.m[5 * i];
+  }
+  ntk::DfRec<T> r;
+  std::memset(&r, 0, sizeof r);
+  cd e[4];
+  if (g.nq == 1 && rb0 < 0) {
+    r.sa = r.sb = (uint32_t)g.q[0];
+    e[0] = e[1] = d[0];
+    e[2] = e[3] = d[1];     // b_a + 2 b_a is 0 or 3
+  } else if (g.nq == 2 && rb0 < 0 && rb1 < 0) {
+    r.sa = (uint32_t)g.q[0];
+    r.sb = (uint32_t)g.q[1];
+    for (int i = 0; i < 4; ++i) e[i] = d[i];
+  } else {
+    // register qubit on bit rb, the other qubit a (a one-qubit gate: none;
+    // its bit is then read from the register qubit's frame word, and both
+    // entries are equal)
+    const bool r_is_1 = g.nq == 2 && rb1 >= 0;
+    const int rb = r_is_1 ? rb1 : rb0;
+    r.kr = 1u | ((uint32_t)rb << 4);
+    r.rq = (uint32_t)(r_is_1 ? g.q[1] : g.q[0]);
+    r.sa = r.sb = (uint32_t)(g.nq == 1 ? g.q[0] : (r_is_1 ? g.q[0] : g.q[1]));
+    for (int ba = 0; ba < 2; ++ba) {
+      cd lo, hi;   // register bit 0 / 1
+      if (g.nq == 1) {
+        lo = d[0];
+        hi = d[1];
+      } else if (r_is_1) {
+        lo = d[ba];
+        hi = d[ba + 2];
+      } else {
+        lo = d[2 * ba];
+        hi = d[1 + 2 * ba];
+      }
+      e[ba] = lo;
+      e[2 + ba] = hi / lo;
+    }
+  }
+  for (int i = 0; i < 4; ++i) {
+    r.p[2 * i] = (T)e[i].real();
+    r.p[2 * i + 1] = (T)e[i].imag();
+  }
+  static_assert(sizeof(ntk::DfRec<T>) % sizeof(ntk::cx<T>) == 0, "record size");
+  ntk::cx<T> w[sizeof(ntk::DfRec<T>) / sizeof(ntk::cx<T>)];
+  std::memcpy(w, &r, sizeof r);
+  for (const auto &x : w) out.push_back(x);
+}
+
+template <typename T>
+static void upload_ops(const Circuit &c, DevPlan &dp, const std::vector<int32_t> &code,
+                       const std::vector<int32_t> &rsel, const std::vector<char> &swap_ab,
+                       const std::vector<std::vector<int>> &reg_of_op, hipStream_t s) {
   const Plan &P = dp.plan;
   // two zero padding entries: the gate kernel loads the descriptor one past
   // a segment's last op
   std::vector<ntk::DevOp<T>> ops(P.ops.size() + 2);
   std::memset(ops.data(), 0, ops.size() * sizeof(ntk::DevOp<T>));
+  std::vector<ntk::cx<T>> aux;
   for (size_t o = 0; o < P.ops.size(); ++o) {
     const HostOp &h = P.ops[o];
     ntk::DevOp<T> &d = ops[o];
@@ -189,32 +272,43 @@ static void upload_ops(DevPlan &dp, const std::vector<int32_t> &code, const std:
       case OPC_G1: case OPC_C1: case OPC_D2: nent = 4; break;
       case OPC_D1: nent = 2; break;
       case OPC_G2: nent = 16; break;
-      case OPC_UCX: nent = 4; break;
+      default: break;
     }
     for (int i = 0; i < nent; ++i) {
       d.m[2 * i] = (T)h.m[i].real();
       d.m[2 * i + 1] = (T)h.m[i].imag();
     }
-    if (h.cls == OPC_UCX) {
-      // the control's 2x2 under each frame X^x Z^z on the control: rows and
-      // columns permuted by x, off-diagonal entries negated by z (rounded
-      // once, then permuted and negated exactly, as the kernel's own
-      // conjugation of a 2x2 does)
-      T r[8];
-      for (int i = 0; i < 4; ++i) {
-        r[2 * i] = (T)h.m[4 + i].real();
-        r[2 * i + 1] = (T)h.m[4 + i].imag();
+    if (h.cls == OPC_G4) {
+      // matrix sets are addressed in units of 256 entries
+      while (aux.size() % 256) aux.push_back(ntk::cx<T>{0, 0});
+      const size_t first = aux.size() / 256;
+      if (first + h.sub.size() + 1 >= ((size_t)1 << 24) || h.sub.size() > 15)
+        throw Error(NT_ERR_UNSUPPORTED, "internal: fused-block table too large");
+      push_variants<T>(h.m, swap_ab[o] != 0, aux);
+      for (int g : h.sub) {
+        cd E[16];
+        embed_gate(c.gates[(size_t)g], h.qa, h.qb, E);
+        push_variants<T>(E, swap_ab[o] != 0, aux);
       }
-      for (int x = 0; x < 2; ++x)
-        for (int z = 0; z < 2; ++z) {
-          T *e = d.m + 8 + 8 * (x + 2 * z);
-          const int src[4] = {x ? 3 : 0, x ? 2 : 1, x ? 1 : 2, x ? 0 : 3};
-          for (int i = 0; i < 4; ++i) {
-            const bool neg = z && (i == 1 || i == 2);
-            e[2 * i] = neg ? -r[2 * src[i]] : r[2 * src[i]];
-            e[2 * i + 1] = neg ? -r[2 * src[i] + 1] : r[2 * src[i] + 1];
-          }
-        }
+      d.rsel = (int32_t)((uint32_t)first | ((uint32_t)h.sub.size() << 24));
+      if (swap_ab[o]) {
+        d.qa = h.qb;
+        d.qb = h.qa;
+      }
+      continue;
+    }
+    if (h.cls == OPC_DF) {
+      while ((aux.size() * sizeof(ntk::cx<T>)) % 16) aux.push_back(ntk::cx<T>{0, 0});
+      const size_t first = aux.size() * sizeof(ntk::cx<T>) / 16;
+      if (first >= ((size_t)1 << 24) || h.sub.size() > 15)
+        throw Error(NT_ERR_UNSUPPORTED, "internal: diagonal-run table too large");
+      const std::vector<int> &rb = reg_of_op[o];   // register bit per qubit id (-1: none)
+      for (int g : h.sub) {
+        const HostGate &hg = c.gates[(size_t)g];
+        push_diag_record<T>(hg, rb[hg.q[0]], hg.nq == 2 ? rb[hg.q[1]] : -1, aux);
+      }
+      d.rsel = (int32_t)((uint32_t)first | ((uint32_t)h.sub.size() << 24));
+      continue;
     }
     if (swap_ab[o]) {
       // two-qubit diagonal with qa on the higher register bit: the qubits
@@ -229,6 +323,10 @@ static void upload_ops(DevPlan &dp, const std::vector<int32_t> &code, const std:
   dp.ops.ensure(ops.size() * sizeof(ntk::DevOp<T>));
   check_hip(hipMemcpyAsync(dp.ops.p, ops.data(), ops.size() * sizeof(ntk::DevOp<T>), hipMemcpyHostToDevice, s),
             "upload ops");
+  dp.aux.ensure(std::max<size_t>(aux.size(), 1) * sizeof(ntk::cx<T>));
+  if (!aux.empty())
+    check_hip(hipMemcpyAsync(dp.aux.p, aux.data(), aux.size() * sizeof(ntk::cx<T>), hipMemcpyHostToDevice, s),
+              "upload block matrices");
 }
 
 // Device tables of a plan (ops, segments, passes, site order and tags), in
@@ -246,8 +344,7 @@ void Ctx::upload_plan(const Circuit &c, DevPlan &dp) {
     int ng = 0;
     for (int o = ps.op_begin; o < ps.op_end; ++o) {
       const HostOp &h = P.ops[o];
-      for (int g : {h.pre[0], h.pre[1], h.gate}) {
-        if (g < 0) continue;
+      for (int g : h.gates()) {
         f += gate_flops(c.gates[(size_t)g]);
         ++ng;
       }
@@ -265,6 +362,7 @@ void Ctx::upload_plan(const Circuit &c, DevPlan &dp) {
   std::memset(dpass.data(), 0, dpass.size() * sizeof(ntk::DevPass));
   std::vector<int32_t> rsel(P.ops.size(), 0), code(P.ops.size(), 0);
   std::vector<char> swap_ab(P.ops.size(), 0);
+  std::vector<std::vector<int>> reg_of_op(P.ops.size());
   for (size_t p = 0; p < P.passes.size(); ++p) {
     const Pass &ps = P.passes[p];
     std::vector<int> loc, nl;
@@ -290,17 +388,33 @@ void Ctx::upload_plan(const Circuit &c, DevPlan &dp) {
           if (pa >= L || pb >= L) throw Error(NT_ERR_UNSUPPORTED, "internal: quad op qubit not local");
           rsel[o] = pa | (pb << 4);
           code[o] = op_code(h, 0);
-        } else if (h.cls == OPC_UCX) {
-          // fused block: both qubits in the registers; the dispatch code
-          // names the register bits of the target and the control
+        } else if (h.cls == OPC_G4) {
+          // fused block: its qubits on register bits (0, 1) or (2, 3); the
+          // kernel takes qa on the lower bit
           auto rbit = [&](int q) {
             auto it = std::find(sg.reg_q.begin(), sg.reg_q.end(), q);
             if (it == sg.reg_q.end()) throw Error(NT_ERR_UNSUPPORTED, "internal: fused block outside the registers");
             return (int)(it - sg.reg_q.begin());
           };
-          const int bt = rbit(h.qa), bc = rbit(h.qb);
-          rsel[o] = (1 << bt) | ((1 << bc) << 4);
-          code[o] = ntk::OPK_UCX * 4 + bt * 4 + bc;
+          const int ba = rbit(h.qa), bb = rbit(h.qb);
+          const int lo = std::min(ba, bb), hi = std::max(ba, bb);
+          if (!(hi == lo + 1 && (lo & 1) == 0)) throw Error(NT_ERR_UNSUPPORTED, "internal: fused block off its register pair");
+          if (((o - sg.op_begin) & 1) != (lo >> 1))
+            throw Error(NT_ERR_UNSUPPORTED, "internal: fused block at the wrong segment offset parity");
+          swap_ab[o] = ba > bb;
+          code[o] = ntk::OPK_G4 * 4 + (lo >> 1);
+        } else if (h.cls == OPC_NOP) {
+          code[o] = ntk::OPK_NOP * 4;
+        } else if (h.cls == OPC_DF) {
+          if ((o - sg.op_begin) & 1) throw Error(NT_ERR_UNSUPPORTED, "internal: diagonal run at an odd segment offset");
+          code[o] = ntk::OPK_DF * 4;
+          reg_of_op[o].assign((size_t)c.n, -1);
+          for (int b = 0; b < R; ++b) reg_of_op[o][(size_t)sg.reg_q[b]] = b;
+          for (int g : h.sub) {
+            const HostGate &hg = c.gates[(size_t)g];
+            if (hg.nq == 2 && reg_of_op[o][(size_t)hg.q[0]] >= 0 && reg_of_op[o][(size_t)hg.q[1]] >= 0)
+              throw Error(NT_ERR_UNSUPPORTED, "internal: diagonal run gate with both qubits in the registers");
+          }
         } else if (h.cls == OPC_G1 || h.cls == OPC_C1 || h.cls == OPC_D1 || h.cls == OPC_D2) {
           auto rmask = [&](int q) -> int32_t {
             if (q < 0) return 0;
@@ -368,8 +482,8 @@ void Ctx::upload_plan(const Circuit &c, DevPlan &dp) {
   dp.segs.ensure(segs.size() * sizeof(ntk::DevSeg));
   check_hip(hipMemcpyAsync(dp.segs.p, segs.data(), segs.size() * sizeof(ntk::DevSeg), hipMemcpyHostToDevice, stream),
             "upload segments");
-  if (pr == NT_C64) upload_ops<float>(dp, code, rsel, swap_ab, stream);
-  else upload_ops<double>(dp, code, rsel, swap_ab, stream);
+  if (pr == NT_C64) upload_ops<float>(c, dp, code, rsel, swap_ab, reg_of_op, stream);
+  else upload_ops<double>(c, dp, code, rsel, swap_ab, reg_of_op, stream);
 
   const size_t S = std::max<size_t>(P.app_site.size(), 1);
   std::vector<int32_t> ident(S);
@@ -480,6 +594,11 @@ void Ctx::timing_flush() {
   ev_flops.clear();
 }
 
+// Gate-kernel instance a plan needs (the fused ops it holds).
+static int plan_features(const Plan &P) {
+  return (P.n_fused > 0 ? ntk::FEAT_G4 : 0) | (P.n_diag > 0 ? ntk::FEAT_DF : 0);
+}
+
 // One launch of every pass of the plan over a batch.  With `start`, batch
 // entries are sorted by their first pass and pass p runs the prefix
 // active[p] of them; entries starting at p > 0 load the error-free checkpoint
@@ -500,6 +619,7 @@ static void run_passes(Ctx &cx, const Circuit &c, DevPlan &dp, ntk::cx<T> *state
     a.state = state;
     a.ref = static_cast<const ntk::cx<T> *>(dp.ref.p);
     a.ops = static_cast<const ntk::DevOp<T> *>(dp.ops.p);
+    a.aux = static_cast<const ntk::cx<T> *>(dp.aux.p);
     a.segs = static_cast<const ntk::DevSeg *>(dp.segs.p);
     a.events = r.events;
     a.ev_count = r.ev_count;
@@ -538,7 +658,7 @@ static void run_passes(Ctx &cx, const Circuit &c, DevPlan &dp, ntk::cx<T> *state
       e1 = take_event(cx.ev_pool);
       check_hip(hipEventRecord(e0, cx.stream), "hipEventRecord");
     }
-    check_hip(ntk::launch_pass<T>(a, P.R, dp.nthreads, P.n_fused > 0, cx.stream), "k_pass launch");
+    check_hip(ntk::launch_pass<T>(a, P.R, dp.nthreads, plan_features(P), cx.stream), "k_pass launch");
     if (cx.timing) {
       check_hip(hipEventRecord(e1, cx.stream), "hipEventRecord");
       // algorithmic HBM bytes: every pass reads and writes each state once,
@@ -725,7 +845,7 @@ void Ctx::run_noalloc(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n, 
   } restore{held, timing, was_timing};
 
   DevPlan dp;
-  for (DevBuf *b : {&dp.ops, &dp.segs, &dp.passes, &dp.app_order, &dp.app_tag, &dp.site_order, &dp.site_tag, &dp.ref,
+  for (DevBuf *b : {&dp.ops, &dp.aux, &dp.segs, &dp.passes, &dp.app_order, &dp.app_tag, &dp.site_order, &dp.site_tag, &dp.ref,
                     &dp.nref, &dp.ref_partials, &dp.ckpt, &dp.ckpt_partials, &dp.nref_pass})
     b->arena = &ar;
   dp.prec = prec;
@@ -1047,8 +1167,8 @@ void Ctx::run_shortcut(const Circuit &c, uint64_t seed, uint64_t t0, uint64_t n,
         if (hit) continue;
       }
       int32_t sp = 0, ep = np - 1;
-      if (have_ckpt) sp = hcnt[b] ? dp.pass_of_op[hfirst[2 * b] >> 8] : np - 1;
-      if (early_end) ep = hcnt[b] ? dp.pass_of_op[hfirst[2 * b + 1] >> 8] : np - 1;
+      if (have_ckpt) sp = hcnt[b] ? dp.pass_of_op[hfirst[2 * b] >> ntk::EV_OP_SHIFT] : np - 1;
+      if (early_end) ep = hcnt[b] ? dp.pass_of_op[hfirst[2 * b + 1] >> ntk::EV_OP_SHIFT] : np - 1;
       act.emplace_back(sp, b, ep);
     }
     std::stable_sort(act.begin(), act.end());
@@ -1128,7 +1248,7 @@ void Ctx::exhaustive(const Circuit &c, double tau, double *fid_out, double P_e[3
     for (int j = 0; j < B; ++j) {
       const int64_t i = off + j, k = i / 3;
       ev[j] = P.app_tag[(size_t)k] | (uint32_t)(i % 3 + 1);
-      st[j] = have_ckpt ? dp.pass_of_op[P.app_tag[(size_t)k] >> 8] : 0;
+      st[j] = have_ckpt ? dp.pass_of_op[P.app_tag[(size_t)k] >> ntk::EV_OP_SHIFT] : 0;
     }
     score_entries(c, dp, B, ev, 1, cnt, st, tau, fsub.data());
     for (int j = 0; j < B; ++j) {
@@ -1308,6 +1428,8 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
         std::memset(&b, 0, sizeof b);
         a.ops = static_cast<const ntk::DevOp<float> *>(dp.ops.p);
         b.ops = static_cast<const ntk::DevOp<double> *>(dp.ops.p);
+        a.aux = static_cast<const ntk::cx<float> *>(dp.aux.p);
+        b.aux = static_cast<const ntk::cx<double> *>(dp.aux.p);
         a.segs = b.segs = static_cast<const ntk::DevSeg *>(dp.segs.p);
         a.pass = b.pass = static_cast<const ntk::DevPass *>(dp.passes.p);
         a.ref = static_cast<const ntk::cx<float> *>(dp.ref.p);
@@ -1355,10 +1477,10 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
       const size_t base = gbase[gi++];
       const size_t ng = g.second.size();
       int64_t smax = 1;
-      bool fused = false;
+      int feat = 0;
       for (size_t k : g.second) {
         smax = std::max<int64_t>(smax, cs[i0 + k]->S);
-        fused = fused || dps[k]->plan.n_fused > 0;
+        feat |= plan_features(dps[k]->plan);
       }
       // trajectories per circuit per launch: bounded work-group count and event memory
       uint64_t bc = std::min<uint64_t>(n, std::max<uint64_t>(1, ((uint64_t)1 << 20) / ng));
@@ -1405,7 +1527,7 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
           a.target = (uint32_t)target;
           a.multi = multi_items.as<ntk::MultiItem<float>>() + base;
           a.per_item = per;
-          check_hip(ntk::launch_pass<float>(a, R, nthreads, fused, stream), "k_pass launch");
+          check_hip(ntk::launch_pass<float>(a, R, nthreads, feat, stream), "k_pass launch");
         } else {
           ntk::PassArgs<double> a;
           std::memset(&a, 0, sizeof a);
@@ -1420,7 +1542,7 @@ void Ctx::run_batch(const std::vector<const Circuit *> &cs, uint64_t seed, uint6
           a.target = (uint32_t)target;
           a.multi = multi_items.as<ntk::MultiItem<double>>() + base;
           a.per_item = per;
-          check_hip(ntk::launch_pass<double>(a, R, nthreads, fused, stream), "k_pass launch");
+          check_hip(ntk::launch_pass<double>(a, R, nthreads, feat, stream), "k_pass launch");
         }
         if (timing) {
           // a scoring pass over one tile reads the reference once per trajectory

@@ -37,7 +37,7 @@ struct DevPlan {
   int prec = 0;
   Plan plan;
   int nthreads = 0;            // threads per work-group = 2^(L - R)
-  DevBuf ops, segs, passes, app_order, app_tag, site_order, site_tag;
+  DevBuf ops, aux, segs, passes, app_order, app_tag, site_order, site_tag;
   DevBuf ref, nref, ref_partials;
   bool ref_ready = false;
   DevBuf ckpt;                 // error-free state before passes 1..np-1

@@ -306,34 +306,39 @@ DEV void cx_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], bool take_lane, 
   }
 }
 
-// Fused block on register bits BT (target) and BC (control): the 2x2 t on
-// the target, the 2x2 c on the control, then the controlled X with control
-// value 1, a compile-time swap of the target's two slots where the control
-// bit is set.  The arithmetic is that of the two general 2x2 ops one after
-// the other (the same FMA sequence).
-template <int BT, int BC, int R, typename T>
-DEV void ucx_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> t00, cx<T> t01, cx<T> t10, cx<T> t11,
-                   cx<T> c00, cx<T> c01, cx<T> c10, cx<T> c11) {
-  constexpr int TB = 1 << BT, CB = 1 << BC;
+// Dense 4x4 on register bits LO and LO + 1 (local index b_LO + 2 b_LO+1):
+// each slot group holds x0..x3 at r, r | 1 << LO, r | 2 << LO, r | 3 << LO;
+// 16 FMA per output amplitude.  Group by group, so each group's inputs die
+// as its outputs are formed (the two register banks together hold about one
+// bank's worth next to the 16 matrix entries).
+template <int LO, int R, typename T>
+DEV void g4_apply(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], const cx<T> (&m)[16]) {
+  constexpr int A = 1 << LO, B = 2 << LO;
 #pragma unroll
   for (int r = 0; r < (1 << R); ++r) {
-    if (r & (TB | CB)) continue;
-    const cx<T> x0 = v[r], x1 = v[r | TB], x2 = v[r | CB], x3 = v[r | TB | CB];
-    const cx<T> y0 = mac2(t00, x0, t01, x1), y1 = mac2(t10, x0, t11, x1);
-    const cx<T> y2 = mac2(t00, x2, t01, x3), y3 = mac2(t10, x2, t11, x3);
-    w[r] = mac2(c00, y0, c01, y2);
-    w[r | TB] = mac2(c00, y1, c01, y3);
-    w[r | CB] = mac2(c10, y1, c11, y3);
-    w[r | TB | CB] = mac2(c10, y0, c11, y2);
+    if (r & (A | B)) continue;
+    const cx<T> x[4] = {v[r], v[r | A], v[r | B], v[r | A | B]};
+    const int at[4] = {r, r | A, r | B, r | A | B};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      T re = m[4 * i].x * x[0].x, im = m[4 * i].x * x[0].y;
+      re = fmat(-m[4 * i].y, x[0].y, re);
+      im = fmat(m[4 * i].y, x[0].x, im);
+#pragma unroll
+      for (int j = 1; j < 4; ++j) {
+        re = fmat(m[4 * i + j].x, x[j].x, re);
+        re = fmat(-m[4 * i + j].y, x[j].y, re);
+        im = fmat(m[4 * i + j].x, x[j].y, im);
+        im = fmat(m[4 * i + j].y, x[j].x, im);
+      }
+      w[at[i]] = cx<T>{re, im};
+    }
   }
 }
 
 // Header and the first four complex matrix entries of an op: what a
-// register-segment op other than a fused block needs, read with scalar loads
-// one op ahead.
-// NM = 8 reals: the first four complex entries; NM = 16 (complex64 plans
-// with fused blocks): eight, so that a block's second matrix arrives with
-// its descriptor.
+// register-segment op needs (a fused block reads its matrix from the aux
+// table), read with scalar loads one op ahead (NM = 8 reals).
 template <typename T, int NM = 8>
 struct OpLite {
   int32_t code, qa, qb, rsel;
@@ -377,8 +382,8 @@ DEV OpLite<T, NM> load_lite(const DevOp<T> *ops, int o) {
 // op about to run come before this load is issued, which then has a whole op
 // to arrive.  The opaque index also keeps loop strength reduction from
 // splitting the load into one pointer per field.
-template <typename T, int NM>
-DEV OpLite<T, NM> load_lite_after(const DevOp<T> *ops, int o, const OpLite<T, NM> &prev) {
+template <typename T, int NM, int NP>
+DEV OpLite<T, NM> load_lite_after(const DevOp<T> *ops, int o, const OpLite<T, NP> &prev) {
   asm volatile("" : "+s"(o) : "s"(prev.code));
   return load_lite<T, NM>(ops, o);
 }
@@ -483,10 +488,9 @@ DEV void conj2(cx<T> m00, cx<T> m01, cx<T> m10, cx<T> m11, uint32_t x, uint32_t 
 // zero.  Index bit q of slot r is ((gb >> q) & 1) | (r & mask(q) != 0), where
 // mask(q) is the register bit holding q (0 if none).  Conjugation by X^x Z^z of a 2x2
 // M gives entries (i, j) = (-1)^{z(i+j)} M[i^x][j^x].
-template <int R, bool FUSED, typename T, int NM, typename TI>
-DEV void apply_reg_op(const OpLite<T, NM> &op, const NT_CONST DevOp<T> *opd, const cx<T> (&v)[1 << R],
-                      cx<T> (&w)[1 << R], uint32_t gb, uint32_t &fx, uint32_t &fz, uint32_t &fc,
-                      TI &&take_interior) {
+template <int R, int SLOT, int FEAT, typename T, int NM, typename TI, typename TS>
+DEV void apply_reg_op(const OpLite<T, NM> &op, const cx<T> *aux, cx<T> (&v)[1 << R], cx<T> (&w)[1 << R],
+                      uint32_t gb, uint32_t &fx, uint32_t &fz, uint32_t &fc, TI &&interior, TS &&take_stage) {
   const int code = op.code;
   const uint32_t qa = (uint32_t)op.qa;
   const uint32_t xa = (fx >> qa) & 1u, za = (fz >> qa) & 1u;
@@ -500,50 +504,103 @@ DEV void apply_reg_op(const OpLite<T, NM> &op, const NT_CONST DevOp<T> *opd, con
   const uint32_t qc = (uint32_t)op.qb;
   const uint32_t xc = (fx >> qc) & 1u;   // frame X on qb
   const uint32_t cv = 1u ^ xc;
-  // Fused blocks (the most frequent op of random-layer circuits), then the
-  // dense one-qubit and controlled-X kinds, are tested first, each followed
-  // by a branch on the register bits; everything else goes through one
-  // switch on the full code.
-  const uint32_t uk = (uint32_t)(code - OPK_UCX * 4);
-  if (FUSED && uk < 16u) {
-    // U_t on qa and U_c on qb, conjugated by the frame at the block's start;
-    // the errors after U_t and U_c then enter the frame; then the CNOT: its
-    // register work (CX_1) does not depend on the frame, and its frame rule
-    // reads the frame as the errors left it
-    const uint32_t zc = (fz >> qc) & 1u;
-    cx<T> t00, t01, t10, t11, c00, c01, c10, c11;
-    conj(t00, t01, t10, t11);
-    if constexpr (NM >= 16) {
-      // the control's 2x2 came with the descriptor
-      conj2(lent(op, 4), lent(op, 5), lent(op, 6), lent(op, 7), xc, zc, c00, c01, c10, c11);
-    } else {
-      // the control's 2x2 under this frame, from the table's variants
-      const uint32_t vc = 4u + 4u * (xc | (zc << 1));
-      c00 = ment(*opd, vc);
-      c01 = ment(*opd, vc + 1u);
-      c10 = ment(*opd, vc + 2u);
-      c11 = ment(*opd, vc + 3u);
+  // Fused ops, then the dense one-qubit and controlled-X kinds, are tested
+  // first, each followed by a branch on the register bits; everything else
+  // goes through one switch on the full code.  The op loop applies ops in
+  // pairs; the host puts blocks on register bits (0, 1) and diagonal runs at
+  // even offsets of their segment (SLOT 1) and blocks on bits (2, 3) at odd
+  // ones (SLOT 2), so each slot holds one block body (two bodies in one slot
+  // need more registers than the kernel's budget).
+  if constexpr (FEAT != 0) {
+    if ((FEAT & FEAT_G4) && code == OPK_G4 * 4 + (SLOT - 1)) {
+      // F^dag B F for the frame F = X^x Z^z at the block's start is the
+      // table's variant x + 4 z of B (exact permutation and signs), and F
+      // stays the frame after the block.  An error inside the block (a
+      // later gate of the block acts on its qubit) splits it: its gates are
+      // applied one by one, each conjugated by the frame as the errors
+      // before it left it.
+      const uint32_t rs = (uint32_t)op.rsel;
+      const uint32_t first = rs & 0xffffffu, nst = rs >> 24;
+      const bool split = interior();
+      const uint32_t kend = split ? nst : 1u;
+      for (uint32_t k = 0;;) {
+        const uint32_t xm = ((fx >> qa) & 1u) | (((fx >> qc) & 1u) << 1);
+        const uint32_t zm = ((fz >> qa) & 1u) | (((fz >> qc) & 1u) << 1);
+        const uint32_t mi = ((first + (split ? 1u + k : 0u)) << 4) + xm + 4u * zm;
+        const NT_CONST cx<T> *mp = cptr(aux) + ((size_t)mi << 4);
+        cx<T> m[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) m[i] = vpin(cx<T>{mp[i].x, mp[i].y});
+        if constexpr (SLOT == 1) g4_apply<0, R>(v, w, m);
+        if constexpr (SLOT == 2 && R > 3) g4_apply<2, R>(v, w, m);
+        if (++k >= kend) break;
+        take_stage(k - 1u);
+#pragma unroll
+        for (int r = 0; r < (1 << R); ++r) v[r] = w[r];
+      }
+      return;
     }
-    t00 = vpin(t00); t01 = vpin(t01); t10 = vpin(t10); t11 = vpin(t11);
-    c00 = vpin(c00); c01 = vpin(c01); c10 = vpin(c10); c11 = vpin(c11);
-    switch (uk) {
-#define NT_UCX(bt, bc)                                                                \
-  case (bt) * 4 + (bc):                                                               \
-    if constexpr ((bt) < R && (bc) < R && (bt) != (bc))                               \
-      ucx_apply<bt, bc, R>(v, w, t00, t01, t10, t11, c00, c01, c10, c11);             \
-    break;
-      NT_UCX(0, 1) NT_UCX(0, 2) NT_UCX(0, 3)
-      NT_UCX(1, 0) NT_UCX(1, 2) NT_UCX(1, 3)
-      NT_UCX(2, 0) NT_UCX(2, 1) NT_UCX(2, 3)
-      NT_UCX(3, 0) NT_UCX(3, 1)
-      default:
-        if constexpr (R > 3) ucx_apply<3, 2, R>(v, w, t00, t01, t10, t11, c00, c01, c10, c11);
-        break;
-#undef NT_UCX
+    if ((FEAT & FEAT_DF) && SLOT == 1 && code == OPK_DF * 4) {
+      // Run of diagonal gates: each gate's phase is taken under the frame as
+      // the errors before it left it (F^dag D F = D(j ^ x)), per lane for
+      // its qubits outside the registers and as a factor per register bit
+      // for a register qubit; the product multiplies each amplitude once.
+      // Gate records are read one ahead of the gate being evaluated.
+      const uint32_t rs = (uint32_t)op.rsel;
+      const uint32_t ng = rs >> 24;
+      const DfRec<T> *recs = reinterpret_cast<const DfRec<T> *>(reinterpret_cast<const char *>(aux) +
+                                                                 ((size_t)(rs & 0xffffffu) << 4));
+      cx<T> base{T(1), T(0)}, rt0{T(1), T(0)}, rt1{T(1), T(0)}, rt2{T(1), T(0)}, rt3{T(1), T(0)};
+      auto load = [&](uint32_t k) {
+        const NT_CONST DfRec<T> &q = cptr(recs)[k];
+        DfRec<T> r;
+        r.sa = q.sa;
+        r.sb = q.sb;
+        r.kr = q.kr;
+        r.rq = q.rq;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) r.p[i] = q.p[i];
+        return r;
+      };
+      DfRec<T> cur = load(0u), nxt;
+      for (uint32_t k = 0; k < ng; ++k) {
+        uint32_t kn = k + 1u < ng ? k + 1u : k;
+        asm volatile("" : "+s"(kn) : "s"(cur.kr));
+        nxt = load(kn);
+        const uint32_t gx = gb ^ fx;
+        const uint32_t ia = (gx >> cur.sa) & 1u;
+        const cx<T> e0{cur.p[0], cur.p[1]}, e1{cur.p[2], cur.p[3]}, e2{cur.p[4], cur.p[5]}, e3{cur.p[6], cur.p[7]};
+        if ((cur.kr & 15u) == 0u) {
+          const uint32_t ib = (gx >> cur.sb) & 1u;
+          base = cmul(ib ? (ia ? e3 : e2) : (ia ? e1 : e0), base);
+        } else {
+          // the frame's X on the register qubit swaps the phases of its two
+          // values: base * ratio for bit 0, 1 / ratio = conj(ratio) for bit 1
+          const bool xr = ((fx >> cur.rq) & 1u) != 0u;
+          const cx<T> q = ia ? e1 : e0, r = ia ? e3 : e2;
+          base = cmul(xr ? cmul(r, q) : q, base);
+          const cx<T> rr{r.x, xr ? -r.y : r.y};
+          switch ((cur.kr >> 4) & 3u) {
+            case 0: rt0 = cmul(rr, rt0); break;
+            case 1: rt1 = cmul(rr, rt1); break;
+            case 2: rt2 = cmul(rr, rt2); break;
+            default: rt3 = cmul(rr, rt3); break;
+          }
+        }
+        take_stage(k);
+        cur = nxt;
+      }
+      // phase of slot r: base times the factors of its set register bits,
+      // each slot's phase used as soon as it is formed (few live at once)
+      const cx<T> rt[4] = {rt0, rt1, rt2, rt3};
+      cx<T> ph[1 << R];
+#pragma unroll
+      for (int r = 0; r < (1 << R); ++r) {
+        ph[r] = r == 0 ? base : cmul(rt[__builtin_ctz((unsigned)r)], ph[r & (r - 1)]);
+        w[r] = cmul(ph[r], v[r]);
+      }
+      return;
     }
-    take_interior();
-    cx_frame((fz >> qa) & 1u, qc, qa, 1u ^ ((fx >> qc) & 1u), fx, fz);
-    return;
   }
   const int kind = code >> 2;
   if (kind == OPK_G1) {
@@ -652,6 +709,11 @@ DEV void apply_reg_op(const OpLite<T, NM> &op, const NT_CONST DevOp<T> *opd, con
       d2_apply<R>(v, w, e0, e1, e2, e3, (gb >> qa) & 1u, (gb >> qc) & 1u);
       break;
     }
+    case OPK_NOP * 4: {
+#pragma unroll
+      for (int r = 0; r < (1 << R); ++r) w[r] = v[r];
+      break;
+    }
     default:
       // the host only emits the codes above (it rejects anything else when
       // it builds the plan); no identity copy here, which the compiler would
@@ -729,9 +791,10 @@ DEV void block_reduce(double (&v)[NPART], double *out, unsigned char *smem) {
 // MAXT: largest work-group this instantiation serves; WPE: waves per SIMD
 // it must fit (bounds the register budget so two work-groups share a CU);
 // SLDS: the work-group is exactly MAXT threads and its tile is static LDS.
-// FUSED: the plan holds fused two-qubit blocks (their bodies are compiled
-// only into these instances, so plans without blocks keep the smaller code).
-template <typename T, int R, int MAXT, int WPE, bool SLDS, bool FUSED>
+// FEAT: the fused ops the plan holds (FEAT_G4 blocks, FEAT_DF diagonal
+// runs; their bodies are compiled only into these instances: each body in the
+// op loop costs registers and instructions on every other op's path too)
+template <typename T, int R, int MAXT, int WPE, bool SLDS, int FEAT>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))) k_pass(const PassArgs<T> a) {
   constexpr int NS = 1 << R;
   // SLDS: the tile of exactly MAXT threads (MAXT * 2^R amplitudes) as a
@@ -752,6 +815,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   const bool score_here = a.end ? (cptr(a.end)[b] == a.pass_index) : ((a.flags & PF_SCORE) != 0);
   const cx<T> *refp = a.end ? a.ref_here : a.ref;
   const DevOp<T> *ops = a.ops;
+  const cx<T> *aux = a.aux;
   const DevSeg *segs = a.segs;
   const DevPass *passp = a.pass;
   int seg_begin = a.seg_begin, seg_end = a.seg_end, op_begin = a.op_begin;
@@ -770,6 +834,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
       return;
     }
     ops = m.ops;
+    aux = m.aux;
     segs = m.segs;
     passp = m.pass;
     refp = m.ref;
@@ -784,7 +849,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   // (measured on the instruction listings: it removes the op loop's spills
   // of every variant but the complex128 one without fused blocks, which has
   // fewer spills without it)
-  if constexpr (sizeof(T) == 4 || FUSED) asm volatile("" : "+s"(ops), "+s"(segs));
+  if constexpr (sizeof(T) == 4 || FEAT != 0) asm volatile("" : "+s"(ops), "+s"(segs));
 
   // Pass layout as dwords.  Thread-id bits at and above lt = L - R are zero
   // (NT = 2^lt <= MAXT), and so are tile-id bits at and above ntile_bits;
@@ -855,7 +920,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   uint32_t next_e = 0, next_op = 0xffffffffu;
   while (ep < ne) {
     next_e = __builtin_amdgcn_readfirstlane(ev[ep]);
-    if ((int)(next_e >> 8) >= op_begin) break;
+    if ((int)(next_e >> EV_OP_SHIFT) >= op_begin) break;
     if (!carried) frame_apply(next_e, fx, fz, fc);
     ++ep;
   }
@@ -865,32 +930,26 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     fz = __builtin_amdgcn_readfirstlane(fin[1]);
     fc = __builtin_amdgcn_readfirstlane(fin[2]);
   }
-  if (ep < ne) next_op = next_e >> 8;
-  auto take_events = [&](int o) {
-    while (next_op == (uint32_t)o) {
-      frame_apply(next_e, fx, fz, fc);
-      ++ep;
-      if (ep < ne) {
-        next_e = __builtin_amdgcn_readfirstlane(ev[ep]);
-        next_op = next_e >> 8;
-      } else {
-        next_op = 0xffffffffu;
-      }
+  if (ep < ne) next_op = next_e >> EV_OP_SHIFT;
+  auto advance = [&]() {
+    frame_apply(next_e, fx, fz, fc);
+    ++ep;
+    if (ep < ne) {
+      next_e = __builtin_amdgcn_readfirstlane(ev[ep]);
+      next_op = next_e >> EV_OP_SHIFT;
+    } else {
+      next_op = 0xffffffffu;
     }
   };
-  // errors after a fused block's one-qubit gates (they come first among the
-  // block's events)
-  auto take_interior = [&](int o) {
-    while (next_op == (uint32_t)o && (next_e & EV_INTERIOR) != 0u) {
-      frame_apply(next_e, fx, fz, fc);
-      ++ep;
-      if (ep < ne) {
-        next_e = __builtin_amdgcn_readfirstlane(ev[ep]);
-        next_op = next_e >> 8;
-      } else {
-        next_op = 0xffffffffu;
-      }
-    }
+  auto take_events = [&](int o) {
+    while (next_op == (uint32_t)o) advance();
+  };
+  // A fused block's interior errors come first among its events, in stage
+  // order: whether op o has any, and those that follow its stage k.
+  auto stage_of = [&]() { return (next_e >> 8) & 15u; };
+  auto has_interior = [&](int o) { return next_op == (uint32_t)o && stage_of() != EV_STAGE_END; };
+  auto take_stage = [&](int o, uint32_t k) {
+    while (next_op == (uint32_t)o && stage_of() == k) advance();
   };
 
   for (int s = seg_begin; s < seg_end; ++s) {
@@ -927,15 +986,18 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     int o = sg_op_begin;
     const int oe = sg_op_end;
     if (o < oe) {
-      constexpr int NM = (FUSED && sizeof(T) == 4) ? 16 : 8;
-      OpLite<T, NM> a_op = load_lite<T, NM>(ops, o), b_op;
+      constexpr int NMA = 8;
+      OpLite<T, NMA> a_op = load_lite<T, NMA>(ops, o);
+      OpLite<T, 8> b_op;
       for (; o < oe; o += 2) {
-        b_op = load_lite_after(ops, o + 1, a_op);
-        apply_reg_op<R, FUSED, T>(a_op, cptr(ops) + o, v, w, gb, fx, fz, fc, [&] { take_interior(o); });
+        b_op = load_lite_after<T, 8>(ops, o + 1, a_op);
+        apply_reg_op<R, 1, FEAT, T>(a_op, aux, v, w, gb, fx, fz, fc, [&] { return has_interior(o); },
+                                          [&](uint32_t k) { take_stage(o, k); });
         take_events(o);
         if (o + 1 < oe) {
-          a_op = load_lite_after(ops, o + 2, b_op);
-          apply_reg_op<R, FUSED, T>(b_op, cptr(ops) + o + 1, w, v, gb, fx, fz, fc, [&] { take_interior(o + 1); });
+          a_op = load_lite_after<T, NMA>(ops, o + 2, b_op);
+          apply_reg_op<R, 2, FEAT, T>(b_op, aux, w, v, gb, fx, fz, fc, [&] { return has_interior(o + 1); },
+                                            [&](uint32_t k) { take_stage(o + 1, k); });
           take_events(o + 1);
         } else {
           // odd op count: the last result is in w
@@ -1021,7 +1083,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   }
 }
 
-template <typename T, bool FUSED>
+template <typename T, int FEAT>
 static hipError_t launch_pass_k(const PassArgs<T> &a, int R, int nthreads, hipStream_t s) {
   const size_t ntiles = (size_t)1 << a.ntile_bits;
   const size_t blocks = ntiles * (size_t)a.B;
@@ -1038,21 +1100,21 @@ static hipError_t launch_pass_k(const PassArgs<T> &a, int R, int nthreads, hipSt
   if (nthreads > (R == 4 ? MAXT4 : 1024)) return hipErrorInvalidValue;
   const dim3 grid((uint32_t)blocks), blk(nthreads);
   switch (R) {
-    case 1: hipLaunchKernelGGL((k_pass<T, 1, 1024, 1, false, FUSED>), grid, blk, lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pass<T, 2, 1024, 1, false, FUSED>), grid, blk, lds, s, a); break;
-    case 3: hipLaunchKernelGGL((k_pass<T, 3, 1024, 1, false, FUSED>), grid, blk, lds, s, a); break;
+    case 1: hipLaunchKernelGGL((k_pass<T, 1, 1024, 1, false, FEAT>), grid, blk, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pass<T, 2, 1024, 1, false, FEAT>), grid, blk, lds, s, a); break;
+    case 3: hipLaunchKernelGGL((k_pass<T, 3, 1024, 1, false, FEAT>), grid, blk, lds, s, a); break;
     case 4:
       if constexpr (sizeof(T) == 4) {
         if (nthreads == 512 && a.L == 13) {
-          hipLaunchKernelGGL((k_pass<T, 4, 512, WPE4, true, FUSED>), grid, blk, 0, s, a);
+          hipLaunchKernelGGL((k_pass<T, 4, 512, WPE4, true, FEAT>), grid, blk, 0, s, a);
           break;
         }
         if (nthreads == 256 && a.L == 12) {
-          hipLaunchKernelGGL((k_pass<T, 4, 256, WPE4, true, FUSED>), grid, blk, 0, s, a);
+          hipLaunchKernelGGL((k_pass<T, 4, 256, WPE4, true, FEAT>), grid, blk, 0, s, a);
           break;
         }
       }
-      hipLaunchKernelGGL((k_pass<T, 4, MAXT4, WPE4, false, FUSED>), grid, blk, lds, s, a);
+      hipLaunchKernelGGL((k_pass<T, 4, MAXT4, WPE4, false, FEAT>), grid, blk, lds, s, a);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -1060,12 +1122,18 @@ static hipError_t launch_pass_k(const PassArgs<T> &a, int R, int nthreads, hipSt
 }
 
 template <typename T>
-hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, bool fused, hipStream_t s) {
-  return fused ? launch_pass_k<T, true>(a, R, nthreads, s) : launch_pass_k<T, false>(a, R, nthreads, s);
+hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, int feat, hipStream_t s) {
+  switch (feat) {
+    case 0: return launch_pass_k<T, 0>(a, R, nthreads, s);
+    case FEAT_G4: return launch_pass_k<T, FEAT_G4>(a, R, nthreads, s);
+    case FEAT_DF: return launch_pass_k<T, FEAT_DF>(a, R, nthreads, s);
+    case FEAT_G4 | FEAT_DF: return launch_pass_k<T, FEAT_G4 | FEAT_DF>(a, R, nthreads, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-template hipError_t launch_pass<float>(const PassArgs<float> &, int, int, bool, hipStream_t);
-template hipError_t launch_pass<double>(const PassArgs<double> &, int, int, bool, hipStream_t);
+template hipError_t launch_pass<float>(const PassArgs<float> &, int, int, int, hipStream_t);
+template hipError_t launch_pass<double>(const PassArgs<double> &, int, int, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Fixed-order FP64 sum over tiles of component `comp` of the partials of

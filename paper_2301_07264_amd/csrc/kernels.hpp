@@ -18,10 +18,11 @@ struct alignas(2 * sizeof(T)) cx {
 //          (bits 4..7) in the op's segment, 0 for a non-register qubit;
 //          G2: tile-local bit positions of qa (bits 0..3) and qb (bits 4..7)
 //   m    : matrix data, (re, im) interleaved; G1/C1 2x2 row-major, D1 (d0,d1),
-//          D2 (d0..d3) on local index b_qa + 2 b_qb, G2 4x4 row-major; UCX
-//          the 2x2 on qa (entries 0..3), then the 2x2 on qb conjugated by
-//          each frame X^x Z^z on qb, variant x + 2 z at entries 4 + 4 (x + 2 z)
-//          (the block reads the one its frame needs, with no selects)
+//          D2 (d0..d3) on local index b_qa + 2 b_qb, G2 4x4 row-major.
+//   G4 (fused block, qa on the lower register bit): rsel = index of the
+//          block's first matrix in the plan's aux table | (stages << 24);
+//          the table holds the block's product, then one 4x4 per gate, each
+//          as its 16 frame variants (x + 4 z) of 16 entries.
 template <typename T>
 struct DevOp {
   int32_t cls, qa, qb, rsel;
@@ -50,15 +51,35 @@ enum : int32_t {
   // Diagonal on two qubits, both in the registers: code OPK_D2RR * 4 + k
   // for the register-bit pair D2RR_PAIRS[k] (lower bit first), k = 0..5.
   OPK_D2RR = 10,
-  // Fused block (U_t on target qa, U_c on control qb, then CNOT qb -> qa),
-  // both qubits in the registers: code OPK_UCX * 4 + 4 * bt + bc for target
-  // register bit bt and control register bit bc (bt != bc).
-  OPK_UCX = 12,
+  // Fused two-qubit block, dense 4x4 on register bits (0, 1) (code
+  // OPK_G4 * 4, at even offsets of its segment) or (2, 3) (code
+  // OPK_G4 * 4 + 1, at odd offsets).
+  OPK_G4 = 12,
+  OPK_NOP = 13,  // no operation (pads a segment so fused ops sit at their offset parity)
+  // Fused run of diagonal gates: rsel = byte offset / 16 of its first record
+  // (DfRec) in the aux table | (gates << 24).
+  OPK_DF = 14,
 };
 
-// Error-event flag: the error follows one of a fused block's one-qubit gates
-// (it acts before the block's CNOT).
-constexpr uint32_t EV_INTERIOR = 0x80u;
+// One gate of a fused diagonal run.  kind 0 (no qubit in the registers):
+// p[b_a + 2 b_b] are the gate's phases by the bits of qubits sa, sb (a
+// one-qubit gate has sa = sb and uses p[0], p[3]).  kind 1 (qubit rq on
+// register bit rbit, the other qubit sa outside the registers, or none):
+// p[b_a] is the phase with the register qubit's bit 0 and p[2 + b_a] the
+// ratio of the phase with bit 1 to it.  kr = kind | rbit << 4.
+template <typename T>
+struct DfRec {
+  uint32_t sa, sb, kr, rq;
+  T p[8];
+};
+
+
+// Event words: (op << EV_OP_SHIFT) | (stage << 8) | (qubit << 2) | pauli.
+// stage: for an error inside a fused block, the block gate it follows (the
+// next gate of the block on its qubit comes after it); EV_STAGE_END for an
+// error that acts after the whole op.
+constexpr int EV_OP_SHIFT = 12;
+constexpr uint32_t EV_STAGE_END = 15u;
 constexpr int D2RR_PAIRS[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
 
 // One register segment: which local bits / global qubits the thread's
@@ -117,6 +138,7 @@ struct MultiItem {
   const DevSeg *segs;
   const DevPass *pass;
   const cx<T> *ref;
+  const cx<T> *aux;        // fused-block matrices
   int32_t seg_begin, seg_end, op_begin, pad;
   double heavy_med;
   double nref;             // <R|R>
@@ -128,8 +150,9 @@ struct PassArgs {
   cx<T> *state;            // B state vectors, state_stride amplitudes apart
   const cx<T> *ref;        // reference state (PF_SCORE)
   const DevOp<T> *ops;
+  const cx<T> *aux;        // fused-block matrices (see DevOp)
   const DevSeg *segs;
-  const uint32_t *events;  // per trajectory, sorted by op: (op << 8) | flag | (qubit << 2) | pauli
+  const uint32_t *events;  // per trajectory, in plan order: event words (EV_OP_SHIFT)
   const int32_t *ev_count;
   double *partials;        // [B][ntiles][NPART]
   // Pauli frame (x-mask, z-mask, phase) per trajectory, [B][4]: written at
@@ -203,9 +226,10 @@ hipError_t launch_zero_words(uint32_t *p, uint64_t n, hipStream_t s);
 
 // Launch wrappers (kernels.hip).
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
+// Fused ops a plan holds; the gate kernel has an instance per combination.
+enum : int { FEAT_G4 = 1, FEAT_DF = 2 };
 template <typename T>
-// fused: the plan holds fused two-qubit blocks (OPK_UCX ops)
-hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, bool fused, hipStream_t s);
+hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, int feat, hipStream_t s);
 // nref: reference norm (end == NULL) or per-pass reference norms indexed by
 // end[b].
 hipError_t launch_finalize(const double *partials, int ntiles, int B, const double *nref, const int32_t *end,

@@ -29,9 +29,19 @@ enum OpClass : int32_t {
   OPC_C1 = 2,  // 2x2 on target qa when control qb equals the control value
   OPC_D2 = 3,  // diagonal (d00, d10, d01, d11) on local index b_qa + 2 b_qb
   OPC_G2 = 4,  // dense 4x4 on local index b_qa + 2 b_qb
-  // Fused block: the one-qubit gates just before a CNOT on its target qa and
-  // its control qb, then the CNOT: m[0..3] = 2x2 on qa, m[4..7] = 2x2 on qb.
-  OPC_UCX = 5,
+  // Fused two-qubit block: several gates on the qubits qa, qb (a two-qubit
+  // gate with one-qubit gates before and after it on either qubit) applied
+  // as one dense 4x4, m = their product on local index b_qa + 2 b_qb; both
+  // qubits in the registers.  HostOp::sub lists the gates in order.
+  OPC_G4 = 5,
+  // No operation: keeps a fused block at an even position in its segment
+  // (the gate kernel's op loop applies ops in pairs and compiles the block
+  // body into the first of the two slots only).  No gate, no sites.
+  OPC_NOP = 6,
+  // Fused run of diagonal gates (HostOp::sub, in order), each with at most
+  // one qubit in the segment's registers: one multiply per amplitude by the
+  // product of their phases.
+  OPC_DF = 7,
 };
 
 struct HostGate {
@@ -47,11 +57,17 @@ struct HostGate {
 struct HostOp {
   int32_t cls = OPC_G1;
   int32_t qa = 0, qb = -1;
-  int32_t gate = 0;        // index in the circuit (a fused block: its CNOT)
-  int32_t pre[2] = {-1, -1};   // fused block: gate indices of the 2x2s on qa and qb
-  cd m[16];                // G1/C1: 4 entries; D1: 2; D2: 4; G2: 16
+  int32_t gate = 0;        // index in the circuit (a fused block: its two-qubit gate)
+  std::vector<int32_t> sub;    // fused block: its gates in application order (empty otherwise)
+  cd m[16];                // G1/C1: 4 entries; D1: 2; D2: 4; G2, G4: 16
   // qubits that must be in the work-group tile / in registers
   uint32_t need_mask() const;
+  // the circuit gates the op applies, in order
+  std::vector<int32_t> gates() const {
+    if (!sub.empty()) return sub;
+    if (gate >= 0) return {gate};
+    return {};
+  }
 };
 
 // Segment kinds: a register segment applies one-qubit, controlled-X and
@@ -72,11 +88,15 @@ struct Pass {
 };
 
 // A plan's op list holds, in application order, ops of one gate each and
-// fused blocks of three gates (Plan::ops[o].pre).  The error sites of a
-// block's one-qubit gates carry the flag SITE_INTERIOR: the gate kernel
-// applies them to the Pauli frame after the block's one-qubit gates and
-// before its CNOT, exactly where the gates put them.
-constexpr uint32_t SITE_INTERIOR = 0x80u;
+// fused blocks (Plan::ops[o].sub).  The error site of a block's gate g on
+// qubit q is tagged with g's stage in the block when a later gate of the
+// block acts on q (an interior site: the error must act between the two
+// gates), else with SITE_STAGE_END (the error commutes with the rest of the
+// block and acts after it).  Sites of an op are listed interior first, in
+// stage order, then the others.
+constexpr int SITE_OP_SHIFT = 12;       // tag = (op << 12) | (stage << 8) | (qubit << 2)
+constexpr uint32_t SITE_STAGE_END = 15u;
+constexpr int MAX_BLOCK_GATES = 15;     // stages 0..14
 struct Plan {
   int n = 0;
   int L = 0;          // tile qubits (<= n)
@@ -87,9 +107,10 @@ struct Plan {
   std::vector<Segment> segs;
   // sites in application order: Philox site index and kernel tag
   std::vector<int32_t> app_site;
-  std::vector<uint32_t> app_tag;        // (op << 8) | (qubit << 2)
+  std::vector<uint32_t> app_tag;        // (op << 12) | (stage << 8) | (qubit << 2)
   std::vector<int> op_of_gate;          // gate -> application position
   int n_fused = 0;                      // fused blocks
+  int n_diag = 0;                       // fused diagonal runs
 };
 
 struct Circuit {
@@ -99,7 +120,7 @@ struct Circuit {
   uint64_t cid = 0;
   uint64_t serial = 0;                  // unique per loaded circuit
   int tile_override[3] = {0, 0, 0};     // per precision (NT_C64, NT_C128): tile qubits, 0 = automatic
-  int fuse_width[3] = {0, 0, 0};        // per precision: 0 = automatic (2), 1 = no fusion, 2 = two-qubit blocks
+  int fuse_width[3] = {0, 0, 0};        // per precision: nt_circuit_set_fusion's width (0 = automatic)
 };
 
 // circuit.cpp
@@ -114,7 +135,12 @@ std::vector<HostOp> classify(const Circuit &c);
 double gate_flops(const HostGate &g);   // algorithmic flops per amplitude
 
 // plan.cpp
-Plan make_plan(const Circuit &c, int max_tile_qubits, int max_reg, int cfix, bool fuse = true);
+// 4x4 matrix (local index b_qa + 2 b_qb) of gate g, which acts within {qa, qb}.
+void embed_gate(const HostGate &g, int qa, int qb, cd *e);
+// Fusion of a plan: two-qubit blocks, diagonal runs (bit set).
+enum : int { FUSE_BLOCKS = 1, FUSE_DIAG = 2 };
+int fusion_mode(int width);   // nt_circuit_set_fusion width -> FUSE_* bits
+Plan make_plan(const Circuit &c, int max_tile_qubits, int max_reg, int cfix, int fuse = FUSE_BLOCKS | FUSE_DIAG);
 void plan_for_precision(const Circuit &c, int prec, int *L, int *R, int *cfix);
 // The plan the library runs for a precision (tile shape chosen per circuit,
 // or the circuit's override).

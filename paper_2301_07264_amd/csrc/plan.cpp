@@ -21,10 +21,31 @@
 // The plan is the same for every trajectory.
 #include <algorithm>
 #include <numeric>
+#include <tuple>
 
 #include "nt_internal.hpp"
 
 namespace nt {
+
+// 4x4 matrix (local index b_qa + 2 b_qb) of gate g acting within {qa, qb}.
+void embed_gate(const HostGate &g, int qa, int qb, cd *e) {
+  for (int i = 0; i < 16; ++i) e[i] = 0.0;
+  if (g.nq == 1) {
+    const bool on_a = g.q[0] == qa;
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        const int ia = i & 1, ib = i >> 1, ja = j & 1, jb = j >> 1;
+        if (on_a) e[4 * i + j] = ib == jb ? g.m[2 * ia + ja] : cd(0.0);
+        else e[4 * i + j] = ia == ja ? g.m[2 * ib + jb] : cd(0.0);
+      }
+    return;
+  }
+  // the gate's matrix acts on local index b_q0 + 2 b_q1
+  const bool same = g.q[0] == qa;
+  auto sw = [](int i) { return ((i & 1) << 1) | (i >> 1); };
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) e[4 * i + j] = same ? g.m[4 * i + j] : g.m[4 * sw(i) + sw(j)];
+}
 
 namespace {
 
@@ -63,6 +84,10 @@ struct Sched {
     std::vector<int> stack(n);
     std::iota(stack.begin(), stack.end(), 0);
     std::vector<char> instack(n, 1);
+    // register segments: the fused blocks' qubit pairs must be disjoint (the
+    // gate kernel applies a block on register bits 0,1 or 2,3)
+    std::vector<int> pair;
+    if (mode == 1) pair.assign(n, -1);
     while (!stack.empty()) {
       int q = stack.back();
       stack.pop_back();
@@ -74,12 +99,18 @@ struct Sched {
         if (other >= 0 && (head[other] >= (int)queue[other].size() || queue[other][head[other]] != i)) break;
         if ((uint64_t)op.need_mask() & ~allowed) break;
         if (mode == 1 && op.cls == OPC_G2) break;
+        if (mode == 1 && op.cls == OPC_G4) {
+          const bool fresh = pair[op.qa] < 0 && pair[op.qb] < 0;
+          if (!fresh && pair[op.qa] != op.qb) break;
+          pair[op.qa] = op.qb;
+          pair[op.qb] = op.qa;
+        }
         head[q]++;
         if (other >= 0) {
           head[other]++;
           if (!instack[other]) { stack.push_back(other); instack[other] = 1; }
         }
-        ++cnt;
+        cnt += op.sub.empty() ? 1 : (int)op.sub.size();   // gates applied
         if (out) out->push_back(i);
       }
     }
@@ -159,64 +190,206 @@ uint64_t improve_set(Sched &s, uint64_t set, uint64_t fixed, uint64_t pool, int 
   return set;
 }
 
-// Fusion into two-qubit blocks, among the ops of one pass (so the passes stay
-// those of the unfused schedule; the segments are then planned over the
-// blocks).  A CNOT whose target and control were each last touched, in the
-// pass's order, by a one-qubit gate of the same pass takes both gates into
-// one block: U_t on the target and U_c on the control, then the CNOT.
-// Moving U_t and U_c to the CNOT keeps the gate order on every qubit (each is
-// the gate right before the CNOT on its qubit, and they act on different
-// qubits), so the block is the circuit's product of unitaries.
-std::vector<HostOp> fuse_pass(const std::vector<HostOp> &ops, const std::vector<int> &order, int n, int *n_fused) {
+// Rough cost of an op in SIMD cycles per wave (a wave applies an op to
+// 64 x 16 amplitudes): the larger of its vector work (about 2.3 cycles per
+// FP32 instruction) and a floor of about 230 cycles, the scalar work every op
+// costs (descriptor load, frame conjugation, dispatch), as measured per op
+// kind on the pass kernel.
+double op_cost(const HostOp &h) {
+  constexpr double FLOOR = 230.0, CYC = 2.3;
+  auto re = [](cd v) { return v.imag() == 0.0; };
+  double v = 0.0;
+  switch (h.cls) {
+    case OPC_G1: {
+      const bool real = re(h.m[0]) && re(h.m[1]) && re(h.m[2]) && re(h.m[3]);
+      const bool rx = h.m[0] == h.m[3] && re(h.m[0]) && h.m[1] == h.m[2] && h.m[1].real() == 0.0;
+      v = (real || rx ? 64.0 : 128.0) * CYC;
+      break;
+    }
+    case OPC_D1: case OPC_D2: v = 64.0 * CYC; break;
+    case OPC_C1: v = 32.0 * CYC; break;
+    case OPC_G2: v = 256.0 * CYC + 2.0 * FLOOR; break;   // and an LDS round trip of its own
+    case OPC_G4: v = 288.0 * CYC; break;                 // 256 FMA, 32 moves of matrix entries
+    default: break;
+  }
+  return std::max(v, FLOOR);
+}
+
+// Fusion into two-qubit blocks among the ops of one pass (the passes stay
+// those of the unfused schedule; segments are then planned over the units).
+// A two-qubit gate on {a, b} takes the runs of one-qubit gates right before
+// it on a and on b that no earlier block took and, when it took any, also
+// the runs right after it; the block is applied as one dense 4x4.  On every
+// qubit the gates of a block are consecutive, so the block applied at its
+// two-qubit gate's place is the circuit's product of unitaries.  Taking the
+// runs after the gate only together with runs before it makes alternate
+// layers of one-qubit gates and entangling gates form blocks of four
+// one-qubit gates (half the arithmetic of applying them one by one) instead
+// of blocks of two (the same arithmetic).  A block is formed only when the
+// cost model above prices it below its parts.
+std::vector<HostOp> fuse_blocks(const Circuit &c, const std::vector<HostOp> &ops, const std::vector<int> &order,
+                                int n, uint64_t local, int *n_fused) {
   const int K = (int)order.size();
-  std::vector<int> last(n, -1), into(K, -1), jt(K, -1), jc(K, -1);
-  auto one_qubit = [&](int k) {
-    const HostOp &h = ops[order[k]];
-    return k >= 0 && (h.cls == OPC_G1 || h.cls == OPC_D1) && into[k] < 0;
-  };
+  std::vector<std::vector<int>> line(n);
+  std::vector<int> pa(K, -1), pb(K, -1);
   for (int k = 0; k < K; ++k) {
     const HostOp &op = ops[order[k]];
-    if (op.cls == OPC_C1 && last[op.qa] >= 0 && last[op.qb] >= 0 && one_qubit(last[op.qa]) &&
-        one_qubit(last[op.qb])) {
-      jt[k] = last[op.qa];
-      jc[k] = last[op.qb];
-      into[jt[k]] = into[jc[k]] = k;
+    pa[k] = (int)line[op.qa].size();
+    line[op.qa].push_back(k);
+    if (op.qb >= 0) {
+      pb[k] = (int)line[op.qb].size();
+      line[op.qb].push_back(k);
     }
-    last[op.qa] = k;
-    if (op.qb >= 0) last[op.qb] = k;
   }
-  auto as_2x2 = [](const HostOp &h, cd *m) {
-    if (h.cls == OPC_D1) {
-      m[0] = h.m[0]; m[1] = 0; m[2] = 0; m[3] = h.m[1];
-    } else {
-      for (int t = 0; t < 4; ++t) m[t] = h.m[t];
+  std::vector<int> claim(K, -1);
+  std::vector<std::vector<int>> members(K);
+  auto one_qubit = [&](int k) { return ops[order[k]].qb < 0; };
+  HostOp g4proto;
+  g4proto.cls = OPC_G4;
+  const double c4 = op_cost(g4proto);
+  for (int k = 0; k < K; ++k) {
+    const HostOp &op = ops[order[k]];
+    // both qubits must be in the pass's tile (a CNOT's control need not be)
+    if (op.qb < 0 || !((local >> op.qa) & 1) || !((local >> op.qb) & 1)) continue;
+    std::vector<int> pre, post;
+    for (int side = 0; side < 2; ++side) {
+      const int q = side ? op.qb : op.qa, p0 = side ? pb[k] : pa[k];
+      for (int i = p0 - 1; i >= 0; --i) {
+        const int j = line[q][i];
+        if (!one_qubit(j) || claim[j] >= 0) break;
+        pre.push_back(j);
+      }
+      for (int i = p0 + 1; i < (int)line[q].size(); ++i) {
+        const int j = line[q][i];
+        if (!one_qubit(j)) break;
+        post.push_back(j);
+      }
     }
-  };
+    if (pre.empty() || (int)pre.size() + 1 > MAX_BLOCK_GATES) continue;
+    std::vector<int> mem = pre;
+    mem.push_back(k);
+    // the runs after the gate only when the block still has room for them
+    if ((int)(mem.size() + post.size()) <= MAX_BLOCK_GATES) mem.insert(mem.end(), post.begin(), post.end());
+    std::sort(mem.begin(), mem.end());
+    double parts = 0.0;
+    for (int j : mem) parts += op_cost(ops[order[j]]);
+    if (parts <= 1.1 * c4) continue;
+    for (int j : mem) claim[j] = k;
+    members[k] = mem;
+  }
   std::vector<HostOp> units;
   for (int k = 0; k < K; ++k) {
-    if (into[k] >= 0) continue;          // moved into its CNOT's block
+    if (claim[k] >= 0 && claim[k] != k) continue;   // applied by its block
     const HostOp &op = ops[order[k]];
-    if (jt[k] < 0) {
+    if (claim[k] != k) {
       units.push_back(op);
       continue;
     }
     HostOp b;
-    b.cls = OPC_UCX;
+    b.cls = OPC_G4;
     b.qa = op.qa;
     b.qb = op.qb;
     b.gate = op.gate;
-    b.pre[0] = ops[order[jt[k]]].gate;
-    b.pre[1] = ops[order[jc[k]]].gate;
-    for (int t = 0; t < 16; ++t) b.m[t] = 0;
-    as_2x2(ops[order[jt[k]]], b.m);
-    as_2x2(ops[order[jc[k]]], b.m + 4);
+    cd M[16], E[16], T[16];
+    for (int i = 0; i < 16; ++i) M[i] = (i % 5 == 0) ? cd(1.0) : cd(0.0);
+    for (int j : members[k]) {
+      const int g = ops[order[j]].gate;
+      b.sub.push_back(g);
+      embed_gate(c.gates[(size_t)g], b.qa, b.qb, E);
+      for (int r = 0; r < 4; ++r)
+        for (int s2 = 0; s2 < 4; ++s2) {
+          cd acc = 0.0;
+          for (int t = 0; t < 4; ++t) acc += E[4 * r + t] * M[4 * t + s2];
+          T[4 * r + s2] = acc;
+        }
+      for (int i = 0; i < 16; ++i) M[i] = T[i];
+    }
+    for (int i = 0; i < 16; ++i) b.m[i] = M[i];
     units.push_back(b);
     ++*n_fused;
   }
   return units;
 }
 
+// Qubits an op acts on.
+uint64_t op_qubits(const Circuit &c, const HostOp &h) {
+  uint64_t m = 0;
+  if (h.cls == OPC_NOP) return 0;
+  for (int g : h.gates()) {
+    const HostGate &hg = c.gates[(size_t)g];
+    m |= 1ull << hg.q[0];
+    if (hg.nq == 2) m |= 1ull << hg.q[1];
+  }
+  return m;
+}
+
+// Whether two ops of one segment may trade places: only ops on disjoint
+// qubits (two diagonal gates on a shared qubit commute, but an error after
+// the first of them does not commute with the second).
+bool commute(const Circuit &c, const HostOp &x, const HostOp &y) { return (op_qubits(c, x) & op_qubits(c, y)) == 0; }
+
+// Fused diagonal runs.  A diagonal op of a segment may move back to the
+// previous diagonal op past ops on other qubits.  Runs of at
+// least three diagonal gates with at most one qubit in the registers then
+// become one op (OPC_DF, up to MAX_BLOCK_GATES gates) that multiplies each
+// amplitude once by the product of the gates' phases, instead of once per
+// gate.  Errors inside a run (a later gate of the run acts on the qubit)
+// still act right after their gate: the kernel evaluates each gate's phase
+// under the frame as the errors before it left it.
+std::vector<int> fuse_diagonals(const Circuit &c, std::vector<HostOp> &pu, const std::vector<int> &sched,
+                                const std::vector<int> &reg_q, int *n_diag) {
+  auto in_reg = [&](int q) { return q >= 0 && std::find(reg_q.begin(), reg_q.end(), q) != reg_q.end(); };
+  auto eligible = [&](const HostOp &h) {
+    if (h.cls == OPC_D1) return true;
+    if (h.cls == OPC_D2) return !(in_reg(h.qa) && in_reg(h.qb));
+    return false;
+  };
+  // move each eligible diagonal right after the previous one when it commutes
+  // with everything in between
+  std::vector<int> seq(sched);
+  for (size_t i = 1; i < seq.size(); ++i) {
+    if (!eligible(pu[seq[i]])) continue;
+    size_t j = i;
+    while (j > 0 && !eligible(pu[seq[j - 1]]) && commute(c, pu[seq[i]], pu[seq[j - 1]])) --j;
+    if (j > 0 && j < i && eligible(pu[seq[j - 1]])) {
+      const int v = seq[i];
+      seq.erase(seq.begin() + (long)i);
+      seq.insert(seq.begin() + (long)j, v);
+    }
+  }
+  std::vector<int> out;
+  for (size_t i = 0; i < seq.size();) {
+    size_t j = i;
+    while (j < seq.size() && eligible(pu[seq[j]]) && (int)(j - i) < MAX_BLOCK_GATES) ++j;
+    if (j - i >= 3) {
+      HostOp d;
+      d.cls = OPC_DF;
+      d.qa = pu[seq[i]].qa;
+      d.qb = -1;
+      d.gate = pu[seq[i]].gate;
+      for (size_t k = i; k < j; ++k) d.sub.push_back(pu[seq[k]].gate);
+      pu.push_back(d);
+      out.push_back((int)pu.size() - 1);
+      ++*n_diag;
+      i = j;
+    } else {
+      out.push_back(seq[i]);
+      ++i;
+    }
+  }
+  return out;
+}
+
 }  // namespace
+
+int fusion_mode(int width) {
+  switch (width) {
+    case 1: return 0;
+    case 3: return FUSE_BLOCKS;
+    case 4: return FUSE_DIAG;
+    default: return FUSE_BLOCKS | FUSE_DIAG;   // 0 (automatic) and 2
+  }
+}
 
 void plan_for_precision(const Circuit &c, int prec, int *L, int *R, int *cfix) {
   int n = c.n;
@@ -246,7 +419,7 @@ Plan choose_plan(const Circuit &c, int prec) {
   int L, R, cfix;
   plan_for_precision(c, prec, &L, &R, &cfix);
   const int ov = c.tile_override[prec == NT_C64 ? 1 : 2];
-  const bool fuse = c.fuse_width[prec == NT_C64 ? 1 : 2] != 1;
+  const int fuse = fusion_mode(c.fuse_width[prec == NT_C64 ? 1 : 2]);
   if (ov > 0) {
     const int Lo = std::min(ov, L);
     const int Ro = std::max(2, std::min(4, Lo - 6));
@@ -261,7 +434,7 @@ Plan choose_plan(const Circuit &c, int prec) {
   return p;
 }
 
-Plan make_plan(const Circuit &c, int L, int R, int cfix, bool fuse) {
+Plan make_plan(const Circuit &c, int L, int R, int cfix, int fuse) {
   Plan P;
   P.n = c.n;
   P.L = L;
@@ -306,8 +479,8 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix, bool fuse) {
     std::vector<int> sorted_ops = pass_ops[p];
     std::sort(sorted_ops.begin(), sorted_ops.end());
     std::vector<HostOp> pu;
-    if (fuse) {
-      pu = fuse_pass(ops, sorted_ops, n, &P.n_fused);
+    if (fuse & FUSE_BLOCKS) {
+      pu = fuse_blocks(c, ops, sorted_ops, n, ps.local_mask, &P.n_fused);
     } else {
       for (int i : sorted_ops) pu.push_back(ops[i]);
     }
@@ -342,15 +515,85 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix, bool fuse) {
       in.drain(rset, &sched, 1);
       if (sched.empty()) throw Error(NT_ERR_UNSUPPORTED, "segment planner made no progress");
       Segment sg;
-      sg.op_begin = (int)P.ops.size();
-      for (int i : sched) emit(i);
-      sg.op_end = (int)P.ops.size();
+      // register qubits: the blocks' pairs on bits (0, 1) and (2, 3), the
+      // first block on a pair putting its qa on the lower bit, then the
+      // segment's other qubits, then padding with other local qubits
+      for (int i : sched)
+        if (pu[i].cls == OPC_G4 && std::find(sg.reg_q.begin(), sg.reg_q.end(), pu[i].qa) == sg.reg_q.end()) {
+          sg.reg_q.push_back(pu[i].qa);
+          sg.reg_q.push_back(pu[i].qb);
+        }
       for (int q = 0; q < n; ++q)
-        if ((rset >> q) & 1) sg.reg_q.push_back(q);
-      // pad to exactly R register qubits with other local qubits
+        if (((rset >> q) & 1) && std::find(sg.reg_q.begin(), sg.reg_q.end(), q) == sg.reg_q.end())
+          sg.reg_q.push_back(q);
       for (int q = 0; q < n && (int)sg.reg_q.size() < R; ++q)
-        if (((ps.local_mask >> q) & 1) && !((rset >> q) & 1)) sg.reg_q.push_back(q);
-      std::sort(sg.reg_q.begin(), sg.reg_q.end());
+        if (((ps.local_mask >> q) & 1) && std::find(sg.reg_q.begin(), sg.reg_q.end(), q) == sg.reg_q.end())
+          sg.reg_q.push_back(q);
+      if ((int)sg.reg_q.size() != R) throw Error(NT_ERR_UNSUPPORTED, "internal: register set size");
+      if (fuse & FUSE_DIAG) sched = fuse_diagonals(c, pu, sched, sg.reg_q, &P.n_diag);
+      // Offsets in the segment: the gate kernel applies ops in pairs and
+      // holds the block body for register bits (0, 1) and the diagonal-run
+      // body in the first slot of a pair, the block body for bits (2, 3) in
+      // the second.  A later op that commutes with everything it passes
+      // moves in front of a fused op that would land on the wrong parity,
+      // else a no-op fills the place.
+      auto align = [&](const std::vector<int> &rq) {
+        auto parity = [&](int i) -> int {
+          if (pu[i].cls == OPC_DF) return 0;
+          if (pu[i].cls != OPC_G4) return -1;
+          return (int)(std::find(rq.begin(), rq.end(), pu[i].qa) - rq.begin()) / 2;
+        };
+        std::vector<int> pend(sched.begin(), sched.end()), out;
+        while (!pend.empty()) {
+          const int i = pend.front();
+          const int want = parity(i);
+          if (want >= 0 && (int)(out.size() & 1) != want) {
+            int found = -1;
+            for (size_t x = 1; x < pend.size() && found < 0; ++x) {
+              const HostOp &cand = pu[pend[x]];
+              if (parity(pend[x]) >= 0) continue;
+              bool ok = true;
+              for (size_t y = 0; y < x && ok; ++y) ok = commute(c, cand, pu[pend[y]]);
+              if (ok) found = (int)x;
+            }
+            if (found >= 0) {
+              out.push_back(pend[(size_t)found]);
+              pend.erase(pend.begin() + found);
+            } else {
+              out.push_back(-1);
+            }
+            continue;
+          }
+          out.push_back(i);
+          pend.erase(pend.begin());
+        }
+        return out;
+      };
+      std::vector<int> seq = align(sg.reg_q);
+      if (R == 4) {
+        // the two register pairs the other way round, if that needs fewer
+        // no-ops
+        std::vector<int> rq2 = {sg.reg_q[2], sg.reg_q[3], sg.reg_q[0], sg.reg_q[1]};
+        std::vector<int> seq2 = align(rq2);
+        auto nops = [](const std::vector<int> &v) { return std::count(v.begin(), v.end(), -1); };
+        if (nops(seq2) < nops(seq)) {
+          seq = seq2;
+          sg.reg_q = rq2;
+        }
+      }
+      sg.op_begin = (int)P.ops.size();
+      for (int i : seq) {
+        if (i >= 0) {
+          emit(i);
+        } else {
+          HostOp nop;
+          nop.cls = OPC_NOP;
+          nop.gate = -1;
+          nop.qa = sg.reg_q[0];
+          P.ops.push_back(nop);
+        }
+      }
+      sg.op_end = (int)P.ops.size();
       P.segs.push_back(sg);
     }
     ps.seg_end = (int)P.segs.size();
@@ -365,24 +608,33 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix, bool fuse) {
     site_base[g] = s;
     s += c.gates[g].nq;
   }
+  if (P.ops.size() >= ((size_t)1 << (32 - SITE_OP_SHIFT)))
+    throw Error(NT_ERR_UNSUPPORTED, "plan has more ops than the event words can index");
   P.op_of_gate.assign(c.gates.size(), -1);
   for (size_t o = 0; o < P.ops.size(); ++o) {
     const HostOp &op = P.ops[o];
-    // a fused block's one-qubit gates first (interior sites), then its CNOT
-    for (int k = 0; k < 2; ++k) {
-      const int g = op.pre[k];
-      if (g < 0) continue;
+    const std::vector<int32_t> gs = op.gates();
+    // (stage or SITE_STAGE_END, qubit, site): a site is interior when a
+    // later gate of the op acts on its qubit
+    std::vector<std::tuple<uint32_t, int, int64_t>> in, end;
+    for (size_t k = 0; k < gs.size(); ++k) {
+      const int g = gs[k];
       P.op_of_gate[g] = (int)o;
-      P.app_site.push_back((int32_t)site_base[g]);
-      P.app_tag.push_back(((uint32_t)o << 8) | ((uint32_t)c.gates[g].q[0] << 2) | SITE_INTERIOR);
+      const HostGate &hg = c.gates[g];
+      for (int j = 0; j < hg.nq; ++j) {
+        bool later = false;
+        for (size_t k2 = k + 1; k2 < gs.size() && !later; ++k2) {
+          const HostGate &h2 = c.gates[gs[k2]];
+          later = h2.q[0] == hg.q[j] || (h2.nq == 2 && h2.q[1] == hg.q[j]);
+        }
+        (later ? in : end).emplace_back(later ? (uint32_t)k : SITE_STAGE_END, hg.q[j], site_base[g] + j);
+      }
     }
-    const int g = op.gate;
-    P.op_of_gate[g] = (int)o;
-    const HostGate &hg = c.gates[g];
-    for (int j = 0; j < hg.nq; ++j) {
-      P.app_site.push_back((int32_t)(site_base[g] + j));
-      P.app_tag.push_back(((uint32_t)o << 8) | ((uint32_t)hg.q[j] << 2));
-    }
+    for (auto *v : {&in, &end})
+      for (const auto &t : *v) {
+        P.app_site.push_back((int32_t)std::get<2>(t));
+        P.app_tag.push_back(((uint32_t)o << SITE_OP_SHIFT) | (std::get<0>(t) << 8) | ((uint32_t)std::get<1>(t) << 2));
+      }
   }
   return P;
 }

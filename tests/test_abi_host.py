@@ -80,16 +80,16 @@ def test_unknown_kind_and_arity(P):
 
 
 def test_gate_count_limit(P):
-    # event words carry the op index in 24 bits; the loader caps G at 2^22
-    # before it reads any gate
+    # event words carry the op index in 20 bits; the loader caps G at 2^19
+    # (a plan may add up to one no-op per gate) before it reads any gate
     import ctypes as C
     g = (P.nt_gate * 1)()
     g[0].kind = P.GATE_KIND["H"]
     g[0].nq = 1
     h = C.c_void_p()
-    rc = P.lib().nt_circuit_load(None, 2, C.cast(g, C.c_void_p), (1 << 22) + 1, C.byref(h))
+    rc = P.lib().nt_circuit_load(None, 2, C.cast(g, C.c_void_p), (1 << 19) + 1, C.byref(h))
     assert rc == P.NT_ERR_UNSUPPORTED
-    assert "2^22" in P.nt_last_error()
+    assert "2^19" in P.nt_last_error()
 
 
 def test_null_handles(P):
