@@ -39,17 +39,18 @@ ALU_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}
 
 # HBM bytes per gate-pass launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (calibrated against a device copy), per workload, valid for the kernel
-# source they were taken on (profiles/hbm_traffic_*.md).
+# source and the plan (tile width, ops per trajectory, passes) they were
+# taken on (profiles/hbm_traffic_*.md).
 MEASURED_TRAFFIC = {
     ("ghz_qft_layers24", "c64", 32): {
         "bytes_per_launch": 8.416e9,
-        "passes": 43,
-        "kernel_sha256": "1cb2e86e906d1774e4af44faf26818dbf07d692fae89efb85b3d8532068555f3",
+        "passes": 43, "tile_qubits": 12, "ops": 1200,
+        "kernel_sha256": "13dd580668b9ee56b8f39e6c663a8207e82becc010814259e9a0a005e46dc30f",
     },
     ("qaoa3reg30", "c64", 4): {
         "bytes_per_launch": 6.560e10,
-        "passes": 11,
-        "kernel_sha256": "1cb2e86e906d1774e4af44faf26818dbf07d692fae89efb85b3d8532068555f3",
+        "passes": 11, "tile_qubits": 12, "ops": 261,
+        "kernel_sha256": "13dd580668b9ee56b8f39e6c663a8207e82becc010814259e9a0a005e46dc30f",
     },
 }
 
@@ -228,7 +229,8 @@ def bench_single(args, P, W, workload, sub):
             traffic = json.load(f).get("bytes_per_launch")
     else:
         m = MEASURED_TRAFFIC.get((workload, args.prec, B))
-        if m and m["kernel_sha256"] == kernel_sha256() and m["passes"] == n_pass:
+        if (m and m["kernel_sha256"] == kernel_sha256() and m["passes"] == n_pass and m["tile_qubits"] == L
+                and m["ops"] == n_ops):
             traffic = m["bytes_per_launch"]
 
     ttr = None
