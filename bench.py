@@ -74,6 +74,16 @@ def main():
     ap.add_argument("--label-traj", type=int, default=512)
     ap.add_argument("--epochs", type=int, default=80)
     ap.add_argument("--eval-circuits", type=int, default=16)
+    ap.add_argument("--routes", type=str, default="sweep,full,paper,auto,surrogate",
+                    help="surrogate workload: tolerable-rate routes timed on the held-out circuits")
+    ap.add_argument("--labels-out", type=str, default=None,
+                    help="surrogate workload: write the labels (npz) and stop after labelling")
+    ap.add_argument("--labels-in", type=str, default=None,
+                    help="surrogate workload: read labels written by --labels-out instead of labelling "
+                         "(several files, comma-separated, for the parts of --label-part)")
+    ap.add_argument("--label-part", type=str, default=None,
+                    help="surrogate workload with --labels-out: label only part K of M (K/M) of the circuits "
+                         "(training then held-out, in order)")
     ap.add_argument("--batch", type=int, default=0, help="trajectories per step (0: 32 for 24 qubits, 4 for 30)")
     ap.add_argument("--prec", choices=["c64", "c128"], default="c64")
     ap.add_argument("--fusion", type=int, choices=[0, 1, 2, 3, 4], default=0,
@@ -385,16 +395,56 @@ def bench_surrogate(args, P, W):
     ctx = P.nt_create(0)
     P.nt_set_precision(ctx, P.NT_C64)
     ntr, nho = args.train_circuits, args.heldout_circuits
-    train_c = [W.config3_circuit(s) for s in range(ntr)]
-    held_c = [W.config3_circuit(100000 + s) for s in range(nho)]
-    th = [P.nt_circuit_load(ctx, c) for c in train_c]
-    hh = [P.nt_circuit_load(ctx, c) for c in held_c]
-    print(f"bench: labels for {ntr} + {nho} circuits ...", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    lab_tr = SG.make_labels(ctx, th, args.label_traj, seed=1)
-    lab_ho = SG.make_labels(ctx, hh, args.label_traj, seed=1)
-    t_label = time.perf_counter() - t0
+    train_c, held_c, th, hh = [], [], [], []
+    for s in range(ntr + nho):
+        c = W.config3_circuit(s) if s < ntr else W.config3_circuit(100000 + s - ntr)
+        (train_c if s < ntr else held_c).append(c)
+        (th if s < ntr else hh).append(P.nt_circuit_load(ctx, c))
+        if (s + 1) % 2000 == 0:
+            print(f"bench: {s + 1}/{ntr + nho} circuits generated, {time.perf_counter() - t0:.0f} s",
+                  file=sys.stderr, flush=True)
     upd = sum(c.G * (1 << c.n) for c in train_c + held_c) * args.label_traj * 13
+    t_label = None
+    if args.labels_in:
+        lab = np.full((ntr + nho, 13), np.nan, np.float32)
+        t_label = 0.0
+        for path in args.labels_in.split(","):
+            z = np.load(path)
+            assert (int(z["train_circuits"]), int(z["heldout_circuits"]), int(z["label_traj"])) == (
+                ntr, nho, args.label_traj), path
+            a, b = int(z["first"]), int(z["end"])
+            lab[a:b] = z["labels"]
+            t_label += float(z["seconds"])
+        assert not np.isnan(lab).any(), "labels missing for some circuits"
+        lab_tr, lab_ho = lab[:ntr], lab[ntr:]
+        # circuit ids as labelling set them
+        for i, h in enumerate(th + hh):
+            P.nt_circuit_set_id(h, i)
+    else:
+        first, end = 0, ntr + nho
+        if args.label_part:
+            k, m = (int(x) for x in args.label_part.split("/"))
+            first, end = (ntr + nho) * k // m, (ntr + nho) * (k + 1) // m
+        print(f"bench: labels for circuits [{first}, {end}) of {ntr} + {nho} ...", file=sys.stderr, flush=True)
+
+        def prog(done, total):
+            print(f"bench: labelled {done}/{total} circuits, {time.perf_counter() - t0:.0f} s",
+                  file=sys.stderr, flush=True)
+
+        t0 = time.perf_counter()
+        lab = SG.make_labels(ctx, (th + hh)[first:end], args.label_traj, seed=1, id_base=first, progress=prog,
+                             chunk=1024)
+        t_label = time.perf_counter() - t0
+        if args.labels_out:
+            np.savez(args.labels_out, labels=lab, first=first, end=end, seconds=t_label, train_circuits=ntr,
+                     heldout_circuits=nho, label_traj=args.label_traj)
+            print(json.dumps({"labels": args.labels_out, "seconds": t_label, "circuits": [first, end],
+                              "train_circuits": ntr, "heldout_circuits": nho, "label_traj": args.label_traj,
+                              "amplitude_updates_logical": sum(c.G * (1 << c.n) for c in (train_c + held_c)[first:end])
+                              * args.label_traj * 13}), flush=True)
+            return
+        lab_tr, lab_ho = lab[:ntr], lab[ntr:]
     print(f"bench: training ({args.epochs} epochs) ...", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     model, losses = SG.train(ctx, th, lab_tr, epochs=args.epochs)
@@ -405,16 +455,31 @@ def bench_surrogate(args, P, W):
     # evaluation on held-out circuits whose tolerable rate lies inside the grid
     ev = [i for i in range(nho) if lab_ho[i, 0] >= 0.66 > lab_ho[i, -1]][:args.eval_circuits]
     routes = {}
+    routes_on = tuple(args.routes.split(","))
+    t0 = time.perf_counter()
     for k, i in enumerate(ev):
-        print(f"bench: tolerable-rate routes, held-out circuit {k + 1}/{len(ev)}", file=sys.stderr, flush=True)
-        r = SG.tolerable_rate_searches(ctx, hh[i], model, n_traj=2048, seed=3)
+        if k % 25 == 0:
+            print(f"bench: tolerable-rate routes, held-out circuit {k + 1}/{len(ev)}, "
+                  f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+        r = SG.tolerable_rate_searches(ctx, hh[i], model, n_traj=2048, seed=3, routes=routes_on)
         for name, v in r.items():
             routes.setdefault(name, []).append(v)
     summary = {name: {"mean_seconds": float(np.mean([x["seconds"] for x in v])),
                       "mean_probes": float(np.mean([x["probes"] for x in v])),
                       "p_star_median": float(np.median([x["p_star"] for x in v]))}
                for name, v in routes.items()}
+    for name, v in routes.items():
+        summary[name]["mean_work"] = float(np.mean([x["work"] for x in v]))
+        summary[name]["not_bracketed"] = int(sum(1 for x in v if x["probes"] < 0))
+        if name != "sweep" and "sweep" in routes:
+            d = [abs(np.log10(x["p_star"]) - np.log10(y["p_star"])) for x, y in zip(v, routes["sweep"])
+                 if x["p_star"] > 0 and y["p_star"] > 0]
+            summary[name]["median_abs_log10_ratio_to_sweep"] = float(np.median(d)) if d else None
     sp = summary.get("surrogate", {}).get("mean_seconds")
+    if sp:
+        for base in ("sweep", "auto", "full", "paper"):
+            if base in summary:
+                summary["surrogate"][f"speedup_vs_{base}"] = summary[base]["mean_seconds"] / sp
     out = {
         "metric": "time-to-tolerable-error-rate ±0.01 (held-out circuits, mean)",
         "value": sp, "unit": "s", "n_gpus": 1, "steps": len(ev), "warmup": 0,

@@ -3,10 +3,11 @@ tolerable-rate search with and without the surrogate's bracket.  Argument
 marshalling and sequencing only; every step runs in libnisqtol.
 
 Labels: the success probability (fidelity >= tau) at the 13 rates
-10^(-5 + j/4) from n_traj trajectories per circuit and rate, all circuits of
-a rate in one batched call, zero-fired trajectories not simulated (F = 1
-exactly either way).  Circuit i uses circuit id i, so every circuit draws its
-own errors; the rates share trajectories (nested fired sets).
+10^(-5 + j/4) from n_traj trajectories per circuit and rate, a chunk of
+circuits of a rate in one batched call, zero-fired trajectories not simulated
+(F = 1 exactly either way).  Every circuit has its own circuit id, so every
+circuit draws its own errors; the rates share trajectories (nested fired
+sets).
 """
 from __future__ import annotations
 
@@ -23,18 +24,27 @@ from . import (GNN_RATES, NT_CRIT_FIDELITY, NT_ERR_NOT_BRACKETED, NT_SHORTCUT_CH
 GRID_LO, GRID_HI = GNN_RATES[0], GNN_RATES[-1]
 
 
-def make_labels(ctx, handles: Sequence, n_traj: int, seed: int = 0, tau: float = 0.9) -> np.ndarray:
-    """[n, 13] success probabilities at the surrogate's rates."""
+def make_labels(ctx, handles: Sequence, n_traj: int, seed: int = 0, tau: float = 0.9, chunk: int = 2048,
+                id_base: int = 0, progress=None) -> np.ndarray:
+    """[n, 13] success probabilities at the surrogate's rates.  Circuits run
+    in chunks, every rate for one chunk before the next, so each circuit's
+    plan and reference state are built once (the library caches a few
+    thousand plans).  Circuit i draws with circuit id id_base + i.
+    progress(done, total) is called after each chunk."""
     for i, h in enumerate(handles):
-        nt_circuit_set_id(h, i)
+        nt_circuit_set_id(h, id_base + i)
     nt_set_criterion(ctx, NT_CRIT_FIDELITY, 0)
     nt_set_shortcuts(ctx, NT_SHORTCUT_ZERO_FIRED)
     out = np.zeros((len(handles), len(GNN_RATES)), np.float32)
     try:
-        for j, p in enumerate(GNN_RATES):
-            nt_set_error_model(ctx, p / 3, p / 3, p / 3)
-            _, pj = nt_run_batch(ctx, list(handles), seed, 0, n_traj, tau)
-            out[:, j] = pj
+        for c0 in range(0, len(handles), chunk):
+            part = list(handles[c0:c0 + chunk])
+            for j, p in enumerate(GNN_RATES):
+                nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+                _, pj = nt_run_batch(ctx, part, seed, 0, n_traj, tau)
+                out[c0:c0 + len(part), j] = pj
+            if progress:
+                progress(c0 + len(part), len(handles))
     finally:
         nt_set_shortcuts(ctx, 0)
     return out
@@ -49,8 +59,11 @@ def train(ctx, handles: Sequence, labels: np.ndarray, epochs: int = 60, batch_gr
     return m, losses
 
 
+ROUTES = ("sweep", "full", "paper", "auto", "surrogate")
+
+
 def tolerable_rate_searches(ctx, h, model, P_target: float = 0.66, tol: float = 0.01, n_traj: int = 2048,
-                            seed: int = 0, tau: float = 0.9) -> Dict[str, dict]:
+                            seed: int = 0, tau: float = 0.9, routes: Sequence[str] = ROUTES) -> Dict[str, dict]:
     """Time to the tolerable rate of one circuit by five routes, each one
     library call:
     'sweep'     the plain 13-point Monte Carlo sweep, crossing interpolated
@@ -109,11 +122,10 @@ def tolerable_rate_searches(ctx, h, model, P_target: float = 0.66, tol: float = 
             p, k, br = nt_tolerable_rate_guided(ctx, h, model, P_target, tol, seed, n_traj, tau)
             return {"p_star": p, "probes": k, "work": float(k), "bracket": br}
 
-        timed("sweep", sweep)
-        timed("full", full)
-        timed("paper", paper)
-        timed("auto", auto)
-        timed("surrogate", guided)
+        for name, fn in (("sweep", sweep), ("full", full), ("paper", paper), ("auto", auto),
+                         ("surrogate", guided)):
+            if name in routes:
+                timed(name, fn)
     finally:
         nt_set_shortcuts(ctx, 0)
     return res
