@@ -36,9 +36,13 @@
  *   - Fidelity criterion: F = |<R|psi>|^2 / (<R|R><psi|psi>) against the
  *     error-free final state R of the same precision; a trajectory succeeds
  *     iff F >= tau (Sec. II criteria; Sec. IV-C).
- *   - Results are a pure function of (circuit, error model, precision, seed,
- *     trajectory range, tau): batching, tiling and the pass plan never change
- *     which errors a trajectory sees.
+ *   - The errors a trajectory sees are a pure function of (circuit, error
+ *     model, seed, trajectory index): batching, tiling, fusion and the pass
+ *     plan never change them.  Values are a function of those and the plan
+ *     (tile width, fusion width; nt_circuit_set_tile / _set_fusion /
+ *     nt_autotune_plan), which changes them at rounding level only; with a
+ *     fixed plan they are reproducible bit for bit, and batching never
+ *     changes them.
  *
  * Errors: every call returns an nt_status; no C++ exception crosses the ABI.
  * nt_last_error() returns a thread-local message for the last failure.

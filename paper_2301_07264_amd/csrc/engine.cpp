@@ -1057,6 +1057,13 @@ static void run_entries(Ctx &cx, const Circuit &c, DevPlan &dp, int B, int ev_st
   }
   if (dp.prec == NT_C64) run_passes<float>(cx, c, dp, np > 1 ? cx.states.as<ntk::cx<float>>() : nullptr, r);
   else run_passes<double>(cx, c, dp, np > 1 ? cx.states.as<ntk::cx<double>>() : nullptr, r);
+  if (end) {
+    // k_finalize reads the reference norm after pass end[b] from nref_pass:
+    // each end pass must be a pass of the plan whose norm is there
+    for (int32_t e : *end)
+      if (e < 0 || e >= np || (size_t)(e + 1) * sizeof(double) > dp.nref_pass.bytes)
+        throw Error(NT_ERR_UNSUPPORTED, "internal: end pass without a reference norm");
+  }
   check_hip(ntk::launch_finalize(cx.partials.as<double>(), (int)ntiles, B,
                                  end ? dp.nref_pass.as<double>() : dp.nref.as<double>(), r.end, r.crit, tau,
                                  cx.fid.as<double>(), cx.count.as<uint64_t>(), cx.stream),

@@ -1123,6 +1123,15 @@ static hipError_t launch_pass_k(const PassArgs<T> &a, int R, int nthreads, hipSt
 
 template <typename T>
 hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, int feat, hipStream_t s) {
+  // the tables and buffers every launch reads (per-circuit tables come with
+  // the batch items instead), the fused-op table when the instance reads it,
+  // and what the scoring epilogue and the partials need
+  if (!a.multi && (!a.ops || !a.segs || !a.pass)) return hipErrorInvalidValue;
+  if (!a.multi && feat != 0 && !a.aux) return hipErrorInvalidValue;
+  if (!a.events || !a.ev_count) return hipErrorInvalidValue;
+  if ((a.flags & PF_SCORE) && !a.multi && !(a.end ? a.ref_here : a.ref)) return hipErrorInvalidValue;
+  if ((a.flags & (PF_SCORE | PF_NORM)) && !a.partials) return hipErrorInvalidValue;
+  if (a.end && !a.ref_here) return hipErrorInvalidValue;
   switch (feat) {
     case 0: return launch_pass_k<T, 0>(a, R, nthreads, s);
     case FEAT_G4: return launch_pass_k<T, FEAT_G4>(a, R, nthreads, s);
@@ -1191,6 +1200,8 @@ __global__ void __launch_bounds__(256) k_finalize(const double *partials, int nt
 hipError_t launch_finalize(const double *partials, int ntiles, int B, const double *nref, const int32_t *end,
                            int crit, double tau, double *fid, uint64_t *count, hipStream_t s) {
   if (B <= 0) return hipSuccess;
+  // every buffer the kernel reads or writes must exist (end may be NULL)
+  if (!partials || !nref || !fid || !count || ntiles <= 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_finalize, dim3(B), dim3(256), 0, s, partials, ntiles, nref, end, 0, (const int32_t *)nullptr,
                      (int64_t)0, (int64_t)0, crit, tau, fid, count);
   return hipGetLastError();
@@ -1200,7 +1211,7 @@ hipError_t launch_finalize_multi(const double *partials, int ntiles, int B, cons
                                  const int32_t *item_map, int64_t out_stride, int64_t out_off, int crit, double tau,
                                  double *fid, uint64_t *count, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  if (per_item <= 0) return hipErrorInvalidValue;
+  if (per_item <= 0 || !partials || !nref || !item_map || !fid || !count || ntiles <= 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_finalize, dim3(B), dim3(256), 0, s, partials, ntiles, nref, (const int32_t *)nullptr,
                      per_item, item_map, out_stride, out_off, crit, tau, fid, count);
   return hipGetLastError();
