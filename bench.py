@@ -45,12 +45,12 @@ MEASURED_TRAFFIC = {
     ("ghz_qft_layers24", "c64", 32): {
         "bytes_per_launch": 8.416e9,
         "passes": 43, "tile_qubits": 12, "ops": 1200,
-        "kernel_sha256": "13dd580668b9ee56b8f39e6c663a8207e82becc010814259e9a0a005e46dc30f",
+        "kernel_sha256": "cf2da6d25ca31840dd1047a33859c34abd24d27760dc31710cd23934202ccc5a",
     },
     ("qaoa3reg30", "c64", 4): {
         "bytes_per_launch": 6.560e10,
         "passes": 11, "tile_qubits": 12, "ops": 261,
-        "kernel_sha256": "13dd580668b9ee56b8f39e6c663a8207e82becc010814259e9a0a005e46dc30f",
+        "kernel_sha256": "cf2da6d25ca31840dd1047a33859c34abd24d27760dc31710cd23934202ccc5a",
     },
 }
 
