@@ -12,6 +12,7 @@
 #include "engine.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <tuple>
@@ -250,6 +251,98 @@ static void push_diag_record(const HostGate &g, int rb0, int rb1, std::vector<nt
   for (const auto &x : w) out.push_back(x);
 }
 
+// Fixed-point form of a diagonal run (complex64), after its DfRecs: each
+// gate's phase arg d(b) split into a constant per group and terms over the
+// bits outside the registers (the gate kernel sums the terms whose bits are
+// set, mod 2^32, then takes one sine and cosine per group).  local: the
+// qubits held in the pass's tile; a term whose bits are both outside it is
+// the same for the whole work-group.  Not formed (header 0) when a gate's
+// entries are not unit complex numbers or the run has too many terms.
+static void push_diag_fast(const Circuit &c, const HostOp &h, const std::vector<int> &rb, uint64_t local,
+                           std::vector<ntk::cx<float>> &aux) {
+  auto turns = [](double rad) {
+    double t = rad / (2.0 * M_PI);
+    t -= std::floor(t);
+    return (uint32_t)(uint64_t)std::nearbyint(t * 4294967296.0);
+  };
+  std::vector<ntk::DfTerm> lane[5], uni[5];
+  ntk::DfFast f;
+  std::memset(&f, 0, sizeof f);
+  uint32_t used = 0;
+  bool ok = true;
+  auto term = [&](int g, int qa, int qb, double ph0, double ph1) {
+    const uint32_t a = turns(ph0), b = g < 4 ? turns(ph1) : 0u;
+    if (a == 0 && b == 0) return;
+    const bool u = ((local >> qa) & 1u) == 0 && ((local >> qb) & 1u) == 0;
+    (u ? uni : lane)[g].push_back(ntk::DfTerm{(uint32_t)qa | ((uint32_t)qb << 8), a, b, 0u});
+  };
+  for (int gi : h.sub) {
+    const HostGate &g = c.gates[(size_t)gi];
+    cd d[4];
+    const int nd = g.nq == 1 ? 2 : 4;
+    if (g.nq == 1) {
+      d[0] = g.m[0];
+      d[1] = g.m[3];
+    } else {
+      for (int i = 0; i < 4; ++i) d[i] = g.m[5 * i];
+    }
+    double ph[4] = {0, 0, 0, 0};
+    for (int i = 0; i < nd; ++i) {
+      if (std::abs(std::abs(d[i]) - 1.0) > 1e-12) ok = false;
+      ph[i] = std::arg(d[i]);
+    }
+    if (g.nq == 1) {
+      const int q = g.q[0], r = rb[(size_t)q];
+      if (r >= 0) {
+        f.c0[r] += turns(ph[0]);
+        f.c1[r] += turns(ph[1]);
+        used |= 1u << r;
+        f.rq |= (uint32_t)q << (8 * r);
+      } else {
+        f.c0[4] += turns(ph[0]);
+        term(4, q, q, ph[1] - ph[0], 0);
+      }
+      continue;
+    }
+    // phase of (b_q0, b_q1) is ph[b_q0 + 2 b_q1]
+    const int q0 = g.q[0], q1 = g.q[1], r0 = rb[(size_t)q0], r1 = rb[(size_t)q1];
+    if (r0 >= 0 && r1 >= 0) {
+      ok = false;   // the planner keeps such gates out of runs
+    } else if (r0 < 0 && r1 < 0) {
+      f.c0[4] += turns(ph[0]);
+      term(4, q0, q0, ph[1] - ph[0], 0);
+      term(4, q1, q1, ph[2] - ph[0], 0);
+      term(4, q0, q1, ph[3] - ph[1] - ph[2] + ph[0], 0);
+    } else {
+      const bool reg1 = r1 >= 0;
+      const int r = reg1 ? r1 : r0, qr = reg1 ? q1 : q0, qo = reg1 ? q0 : q1;
+      auto phi = [&](int bo, int br) { return reg1 ? ph[bo + 2 * br] : ph[br + 2 * bo]; };
+      f.c0[r] += turns(phi(0, 0));
+      f.c1[r] += turns(phi(0, 1));
+      used |= 1u << r;
+      f.rq = (f.rq & ~(255u << (8 * r))) | ((uint32_t)qr << (8 * r));
+      term(r, qo, qo, phi(1, 0) - phi(0, 0), phi(1, 1) - phi(0, 1));
+    }
+  }
+  for (int g = 0; g < 5; ++g) {
+    if (lane[g].size() > (size_t)ntk::DF_MAX_TERMS || uni[g].size() > (size_t)ntk::DF_MAX_TERMS) ok = false;
+    f.nlane |= (uint32_t)std::min<size_t>(lane[g].size(), 63) << (6 * g);
+    f.nuni |= (uint32_t)std::min<size_t>(uni[g].size(), 63) << (6 * g);
+  }
+  f.hdr = ok ? 1u | (used << 1) : 0u;
+  std::vector<uint32_t> wds(sizeof f / 4);
+  std::memcpy(wds.data(), &f, sizeof f);
+  if (ok)
+    for (int g = 0; g < 5; ++g)
+      for (const auto *v : {&lane[g], &uni[g]})
+        for (const ntk::DfTerm &t : *v) wds.insert(wds.end(), {t.sab, t.q0, t.q1, t.pad});
+  for (size_t i = 0; i < wds.size(); i += 2) {
+    ntk::cx<float> x;
+    std::memcpy(&x, &wds[i], sizeof x);
+    aux.push_back(x);
+  }
+}
+
 template <typename T>
 static void upload_ops(const Circuit &c, DevPlan &dp, const std::vector<int32_t> &code,
                        const std::vector<int32_t> &rsel, const std::vector<char> &swap_ab,
@@ -260,6 +353,9 @@ static void upload_ops(const Circuit &c, DevPlan &dp, const std::vector<int32_t>
   std::vector<ntk::DevOp<T>> ops(P.ops.size() + 2);
   std::memset(ops.data(), 0, ops.size() * sizeof(ntk::DevOp<T>));
   std::vector<ntk::cx<T>> aux;
+  std::vector<uint64_t> local_of_op(P.ops.size(), 0);
+  for (const Pass &ps : P.passes)
+    for (int o = ps.op_begin; o < ps.op_end; ++o) local_of_op[(size_t)o] = ps.local_mask;
   for (size_t o = 0; o < P.ops.size(); ++o) {
     const HostOp &h = P.ops[o];
     ntk::DevOp<T> &d = ops[o];
@@ -307,6 +403,7 @@ static void upload_ops(const Circuit &c, DevPlan &dp, const std::vector<int32_t>
         const HostGate &hg = c.gates[(size_t)g];
         push_diag_record<T>(hg, rb[hg.q[0]], hg.nq == 2 ? rb[hg.q[1]] : -1, aux);
       }
+      if constexpr (sizeof(T) == 4) push_diag_fast(c, h, rb, local_of_op[o], aux);
       d.rsel = (int32_t)((uint32_t)first | ((uint32_t)h.sub.size() << 24));
       continue;
     }

@@ -409,6 +409,20 @@ DEV void perm4(const OpLite<T, NM> &h, uint32_t xm, cx<T> &e0, cx<T> &e1, cx<T> 
 
 // Diagonal whose phase is p1 on the slots with register bit B set and p0
 // on the others (B known at compile time: no per-slot selects).
+// cos + i sin of the angle t / 2^32 turns, single precision.  The nearest
+// quarter turn k comes from the top bits (exact), the rest is an angle x in
+// [-pi/4, pi/4), where the Taylor series of sin to x^9 and of cos to x^10
+// are accurate to 2e-9; then e^{i(x + k pi/2)} = i^k e^{ix}.
+DEV cx<float> phase_turns(uint32_t t) {
+  const uint32_t k = (t + (1u << 29)) >> 30;
+  const float x = (float)(int32_t)(t - (k << 30)) * 1.46291807926715968e-9f;   // 2 pi / 2^32
+  const float x2 = x * x;
+  const float s = x * (1.f + x2 * (-1.f / 6 + x2 * (1.f / 120 + x2 * (-1.f / 5040 + x2 * (1.f / 362880)))));
+  const float c = 1.f + x2 * (-0.5f + x2 * (1.f / 24 + x2 * (-1.f / 720 + x2 * (1.f / 40320 + x2 * (-1.f / 3628800)))));
+  const float re = (k & 1u) ? -s : c, im = (k & 1u) ? c : s;
+  return (k & 2u) ? cx<float>{-re, -im} : cx<float>{re, im};
+}
+
 template <int B, int R, typename T>
 DEV void diag_bit(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> p0, cx<T> p1) {
 #pragma unroll
@@ -550,6 +564,79 @@ DEV void apply_reg_op(const OpLite<T, NM> &op, const cx<T> *aux, cx<T> (&v)[1 <<
       const uint32_t ng = rs >> 24;
       const DfRec<T> *recs = reinterpret_cast<const DfRec<T> *>(reinterpret_cast<const char *>(aux) +
                                                                  ((size_t)(rs & 0xffffffu) << 4));
+      if constexpr (sizeof(T) == 4) {
+        // With no error inside the run the frame is the same for all its
+        // gates, and the run is one phase per amplitude: per group, a sum of
+        // fixed-point angles over the terms whose bits are set (integer adds,
+        // exact mod 2 pi), then one sine and cosine per group.
+        const NT_CONST DfFast &f = *reinterpret_cast<const NT_CONST DfFast *>(cptr(recs) + ng);
+        const uint32_t hdr = f.hdr;
+        if ((hdr & 1u) && !interior()) {
+          const uint32_t nl = f.nlane, nu = f.nuni, rqw = f.rq;
+          const uint32_t gx = gb ^ fx;
+          const uint32_t ux = __builtin_amdgcn_readfirstlane(gb) ^ fx;   // bits outside the tile
+          const NT_CONST DfTerm *tm = reinterpret_cast<const NT_CONST DfTerm *>(&f + 1);
+          uint32_t a0[5], a1[4];
+#pragma unroll
+          for (int g = 0; g < 5; ++g) {
+            uint32_t s0 = 0, s1 = 0, u0 = f.c0[g], u1 = g < 4 ? f.c1[g] : 0u;
+            const uint32_t cl = (nl >> (6 * g)) & 63u, cu = (nu >> (6 * g)) & 63u;
+            for (uint32_t i = 0; i < cl; ++i, ++tm) {
+              const uint32_t sab = tm->sab, q0 = tm->q0, q1 = tm->q1;
+              const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int32_t)gx, sab & 255u, 1) &
+                                 (uint32_t)__builtin_amdgcn_sbfe((int32_t)gx, sab >> 8, 1);
+              s0 += m & q0;
+              if (g < 4) s1 += m & q1;
+            }
+            for (uint32_t i = 0; i < cu; ++i, ++tm) {
+              const uint32_t sab = tm->sab, q0 = tm->q0, q1 = tm->q1;
+              const uint32_t m = 0u - ((ux >> (sab & 255u)) & (ux >> (sab >> 8)) & 1u);
+              u0 += m & q0;
+              if (g < 4) u1 += m & q1;
+            }
+            a0[g] = s0 + u0;
+            if (g < 4) a1[g] = s1 + u1;
+          }
+          // slot with all register bits 0: bit rho takes the frame's X on
+          // its qubit; the factor for a set register bit is the phase
+          // difference of the two values, negated under that X
+          uint32_t tb = a0[4];
+          uint32_t td[4];
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            const bool xr = ((fx >> ((rqw >> (8 * g)) & 255u)) & 1u) != 0u;
+            tb += xr ? a1[g] : a0[g];
+            td[g] = xr ? a0[g] - a1[g] : a1[g] - a0[g];
+          }
+          auto phase = [](uint32_t t) { return phase_turns(t); };
+          const cx<T> pb = phase(tb);
+          const uint32_t used = (hdr >> 1) & 15u;
+          if (used == 0u) {
+#pragma unroll
+            for (int r = 0; r < (1 << R); ++r) w[r] = cmul(pb, v[r]);
+          } else if ((used & (used - 1u)) == 0u) {
+            const int g = __builtin_ctz(used);
+            const cx<T> p1 = cmul(phase(td[g]), pb);
+            switch (g) {
+              case 0: diag_bit<0, R>(v, w, pb, p1); break;
+              case 1: if constexpr (R > 1) diag_bit<1, R>(v, w, pb, p1); break;
+              case 2: if constexpr (R > 2) diag_bit<2, R>(v, w, pb, p1); break;
+              default: if constexpr (R > 3) diag_bit<3, R>(v, w, pb, p1); break;
+            }
+          } else {
+            cx<T> rt[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) rt[g] = ((used >> g) & 1u) ? phase(td[g]) : cx<T>{T(1), T(0)};
+            cx<T> ph[1 << R];
+#pragma unroll
+            for (int r = 0; r < (1 << R); ++r) {
+              ph[r] = r == 0 ? pb : cmul(rt[__builtin_ctz((unsigned)r)], ph[r & (r - 1)]);
+              w[r] = cmul(ph[r], v[r]);
+            }
+          }
+          return;
+        }
+      }
       cx<T> base{T(1), T(0)}, rt0{T(1), T(0)}, rt1{T(1), T(0)}, rt2{T(1), T(0)}, rt3{T(1), T(0)};
       auto load = [&](uint32_t k) {
         const NT_CONST DfRec<T> &q = cptr(recs)[k];

@@ -73,6 +73,29 @@ struct DfRec {
   T p[8];
 };
 
+// The same run as phase angles in fixed point (turns x 2^32, sums mod 2^32
+// are exact mod 2 pi), complex64 only, stored after the run's DfRecs.  Every
+// gate's phase is split into a constant and terms "add q when bits sa and sb
+// of the global index (XOR the frame's X) are both 1".  Group rho < 4 holds
+// the gates whose register qubit sits on register bit rho, with a pair of
+// angles for that bit's two values; group 4 the gates with no register
+// qubit.  Valid only when no error falls inside the run (the frame is then
+// constant over it).
+struct DfFast {
+  uint32_t hdr;        // bit 0: form present; bit 1 + rho: group rho used
+  uint32_t nlane;      // per group (6 bits each): terms whose bits vary per lane
+  uint32_t nuni;       // per group: terms whose bits are uniform over the work-group
+  uint32_t rq;         // qubit on register bit rho (8 bits each)
+  uint32_t c0[5], c1[4];
+  uint32_t pad[3];
+};
+struct DfTerm {
+  uint32_t sab;        // sa | sb << 8
+  uint32_t q0, q1, pad;
+};
+static_assert(sizeof(DfFast) == 64 && sizeof(DfTerm) == 16, "fixed-point run layout");
+constexpr int DF_MAX_TERMS = 63;
+
 
 // Event words: (op << EV_OP_SHIFT) | (stage << 8) | (qubit << 2) | pauli.
 // stage: for an error inside a fused block, the block gate it follows (the

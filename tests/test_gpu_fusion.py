@@ -172,3 +172,71 @@ def test_plan_autotuner(P, ctx, orc):
     np.testing.assert_array_equal(a.view(np.uint64), b.view(np.uint64))
     assert np.abs(a - want).max() <= 2e-5
     P.nt_circuit_free(h)
+
+
+def _diag_circuit(n, layers, seed):
+    # one-qubit layers, then long stretches of diagonal gates (one- and
+    # two-qubit, phases of every kind) on random qubits: runs whose qubits sit
+    # in the registers, in the tile, and outside it, with one or several
+    # register qubits per run
+    rng = np.random.default_rng(seed)
+    gates = []
+    for _ in range(layers):
+        for q in range(n):
+            if rng.integers(2):
+                gates.append(W.Gate("H", (q,)))
+            else:
+                gates.append(W.Gate("RX", (q,), (float(rng.uniform(0, 2 * math.pi)),)))
+        for _ in range(3 * n):
+            nm = ["RZ", "T", "S", "Z", "CP", "CZ", "RZZ"][int(rng.integers(7))]
+            if nm in ("RZ", "T", "S", "Z"):
+                q = int(rng.integers(n))
+                par = (float(rng.uniform(-4 * math.pi, 4 * math.pi)),) if nm == "RZ" else ()
+                gates.append(W.Gate(nm, (q,), par))
+            else:
+                a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+                par = (float(rng.uniform(-4 * math.pi, 4 * math.pi)),) if nm in ("CP", "RZZ") else ()
+                gates.append(W.Gate(nm, (a, b), par))
+    return W.Circuit(n, gates, f"diag{n}")
+
+
+DIAG_CIRCUITS = [
+    ("ghzqft16", lambda: W.config1(n=16, layers=0)),
+    ("diag17", lambda: _diag_circuit(17, 3, 91)),
+    ("qaoa16", lambda: W.config4(n=16, rounds=2)),
+]
+
+
+@pytest.mark.parametrize("name,make", DIAG_CIRCUITS)
+def test_diagonal_runs(P, ctx, orc, name, make):
+    """Diagonal runs at complex64 over 2^12-amplitude tiles (several passes,
+    qubits outside the tile): a run with no error inside it is one phase per
+    amplitude from fixed-point angle sums, one with an error inside it is
+    applied gate by gate.  Error-free states take the first form for every
+    run; the error models put errors inside and outside runs."""
+    c = make()
+    pr = P.NT_C64
+    P.nt_set_precision(ctx, pr)
+    for width in (4, 2):
+        h = P.nt_circuit_load(None, c)
+        P.nt_circuit_set_id(h, 7)
+        P.nt_circuit_set_tile(h, pr, 12)
+        P.nt_circuit_set_fusion(h, pr, width)
+        n_ops, n_fused = P.nt_plan_ops(h, pr)
+        _say(f"{name} G={c.G} fusion {width}: {n_ops} ops, {n_fused} fused")
+        assert n_fused > 0
+        for model in [(0.0, 0.0, 0.0), (0.004, 0.004, 0.004), (0.1, 0.0, 0.0), (1 / 3, 1 / 3, 1 / 3)]:
+            P.nt_set_error_model(ctx, *model)
+            for t in range(3):
+                g = P.nt_final_state(ctx, h, 21, t, pr)
+                o = orc.final_state(c, *model, 21, t, cid=7)
+                err = _l2(g, o)
+                assert err <= 1e-5, (model, t, err)
+        p = 0.01
+        P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+        N = 64
+        fid = np.zeros(N)
+        P.nt_run(ctx, h, 21, 0, N, TAU, fid)
+        f_o, _ = orc.run(c, p / 3, p / 3, p / 3, 21, 0, N, TAU, cid=7)
+        assert np.abs(fid - f_o).max() <= 2e-5
+        P.nt_circuit_free(h)
