@@ -1127,11 +1127,15 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
     double ovr = 0.0, ovi = 0.0, nrm = 0.0, mass = 0.0;
     const uint32_t tgt = a.target ^ fx;   // psi[target] = +-s[target ^ x]
     const bool want_t = a.crit == CRIT_TARGET, want_h = a.crit == CRIT_HEAVY;
+    // all reference loads in flight before the first use
+    cx<T> rv[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) rv[k] = refp[(tilebase | dlo | dk[k]) ^ fx];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       const uint32_t g = tilebase | dlo | dk[k];
       const cx<T> s = lds_k(k);
-      const cx<T> r = refp[g ^ fx];
+      const cx<T> r = rv[k];
       double sr = (double)s.x, si = (double)s.y;
       if (__popc(fz & g) & 1u) {
         sr = -sr;
