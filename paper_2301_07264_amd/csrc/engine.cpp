@@ -19,7 +19,8 @@
 
 namespace nt {
 
-static_assert(SITE_OP_SHIFT == ntk::EV_OP_SHIFT && SITE_STAGE_END == ntk::EV_STAGE_END,
+static_assert(SITE_OP_SHIFT == ntk::EV_OP_SHIFT && SITE_STAGE_SHIFT == ntk::EV_STAGE_SHIFT &&
+                  SITE_STAGE_END == ntk::EV_STAGE_END,
               "event word layout of the planner and the gate kernel");
 
 void check_hip(hipError_t e, const char *what) {
@@ -378,7 +379,7 @@ static void upload_ops(const Circuit &c, DevPlan &dp, const std::vector<int32_t>
       // matrix sets are addressed in units of 256 entries
       while (aux.size() % 256) aux.push_back(ntk::cx<T>{0, 0});
       const size_t first = aux.size() / 256;
-      if (first + h.sub.size() + 1 >= ((size_t)1 << 24) || h.sub.size() > 15)
+      if (first + h.sub.size() + 1 >= ((size_t)1 << 24) || h.sub.size() > (size_t)MAX_BLOCK_GATES)
         throw Error(NT_ERR_UNSUPPORTED, "internal: fused-block table too large");
       push_variants<T>(h.m, swap_ab[o] != 0, aux);
       for (int g : h.sub) {
@@ -396,7 +397,7 @@ static void upload_ops(const Circuit &c, DevPlan &dp, const std::vector<int32_t>
     if (h.cls == OPC_DF) {
       while ((aux.size() * sizeof(ntk::cx<T>)) % 16) aux.push_back(ntk::cx<T>{0, 0});
       const size_t first = aux.size() * sizeof(ntk::cx<T>) / 16;
-      if (first >= ((size_t)1 << 24) || h.sub.size() > 15)
+      if (first >= ((size_t)1 << 24) || h.sub.size() > (size_t)MAX_BLOCK_GATES)
         throw Error(NT_ERR_UNSUPPORTED, "internal: diagonal-run table too large");
       const std::vector<int> &rb = reg_of_op[o];   // register bit per qubit id (-1: none)
       for (int g : h.sub) {

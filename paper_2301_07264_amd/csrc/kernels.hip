@@ -1033,7 +1033,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WPE))
   };
   // A fused block's interior errors come first among its events, in stage
   // order: whether op o has any, and those that follow its stage k.
-  auto stage_of = [&]() { return (next_e >> 8) & 15u; };
+  auto stage_of = [&]() { return (next_e >> EV_STAGE_SHIFT) & 31u; };
   auto has_interior = [&](int o) { return next_op == (uint32_t)o && stage_of() != EV_STAGE_END; };
   auto take_stage = [&](int o, uint32_t k) {
     while (next_op == (uint32_t)o && stage_of() == k) advance();

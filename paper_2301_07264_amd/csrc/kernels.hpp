@@ -97,12 +97,14 @@ static_assert(sizeof(DfFast) == 64 && sizeof(DfTerm) == 16, "fixed-point run lay
 constexpr int DF_MAX_TERMS = 63;
 
 
-// Event words: (op << EV_OP_SHIFT) | (stage << 8) | (qubit << 2) | pauli.
+// Event words: (op << EV_OP_SHIFT) | (stage << EV_STAGE_SHIFT) | (qubit << 2) | pauli
+// (qubit < 32).
 // stage: for an error inside a fused block, the block gate it follows (the
 // next gate of the block on its qubit comes after it); EV_STAGE_END for an
 // error that acts after the whole op.
 constexpr int EV_OP_SHIFT = 12;
-constexpr uint32_t EV_STAGE_END = 15u;
+constexpr int EV_STAGE_SHIFT = 7;
+constexpr uint32_t EV_STAGE_END = 31u;
 constexpr int D2RR_PAIRS[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
 
 // One register segment: which local bits / global qubits the thread's

@@ -94,9 +94,10 @@ struct Pass {
 // gates), else with SITE_STAGE_END (the error commutes with the rest of the
 // block and acts after it).  Sites of an op are listed interior first, in
 // stage order, then the others.
-constexpr int SITE_OP_SHIFT = 12;       // tag = (op << 12) | (stage << 8) | (qubit << 2)
-constexpr uint32_t SITE_STAGE_END = 15u;
-constexpr int MAX_BLOCK_GATES = 15;     // stages 0..14
+constexpr int SITE_OP_SHIFT = 12;       // tag = (op << 12) | (stage << 7) | (qubit << 2)
+constexpr int SITE_STAGE_SHIFT = 7;
+constexpr uint32_t SITE_STAGE_END = 31u;
+constexpr int MAX_BLOCK_GATES = 31;     // stages 0..30
 struct Plan {
   int n = 0;
   int L = 0;          // tile qubits (<= n)
@@ -107,7 +108,7 @@ struct Plan {
   std::vector<Segment> segs;
   // sites in application order: Philox site index and kernel tag
   std::vector<int32_t> app_site;
-  std::vector<uint32_t> app_tag;        // (op << 12) | (stage << 8) | (qubit << 2)
+  std::vector<uint32_t> app_tag;        // (op << 12) | (stage << 7) | (qubit << 2)
   std::vector<int> op_of_gate;          // gate -> application position
   int n_fused = 0;                      // fused blocks
   int n_diag = 0;                       // fused diagonal runs

@@ -633,7 +633,7 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix, int fuse) {
     for (auto *v : {&in, &end})
       for (const auto &t : *v) {
         P.app_site.push_back((int32_t)std::get<2>(t));
-        P.app_tag.push_back(((uint32_t)o << SITE_OP_SHIFT) | (std::get<0>(t) << 8) | ((uint32_t)std::get<1>(t) << 2));
+        P.app_tag.push_back(((uint32_t)o << SITE_OP_SHIFT) | (std::get<0>(t) << SITE_STAGE_SHIFT) | ((uint32_t)std::get<1>(t) << 2));
       }
   }
   return P;
