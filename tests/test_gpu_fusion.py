@@ -70,6 +70,32 @@ def _mixed_circuit(n, layers, seed):
     return W.Circuit(n, gates, f"mixed{n}")
 
 
+def _diag_circuit(n, layers, seed):
+    # one-qubit layers, then long stretches of diagonal gates (one- and
+    # two-qubit, phases of every kind) on random qubits: runs whose qubits sit
+    # in the registers, in the tile, and outside it, with one or several
+    # register qubits per run
+    rng = np.random.default_rng(seed)
+    gates = []
+    for _ in range(layers):
+        for q in range(n):
+            if rng.integers(2):
+                gates.append(W.Gate("H", (q,)))
+            else:
+                gates.append(W.Gate("RX", (q,), (float(rng.uniform(0, 2 * math.pi)),)))
+        for _ in range(3 * n):
+            nm = ["RZ", "T", "S", "Z", "CP", "CZ", "RZZ"][int(rng.integers(7))]
+            if nm in ("RZ", "T", "S", "Z"):
+                q = int(rng.integers(n))
+                par = (float(rng.uniform(-4 * math.pi, 4 * math.pi)),) if nm == "RZ" else ()
+                gates.append(W.Gate(nm, (q,), par))
+            else:
+                a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+                par = (float(rng.uniform(-4 * math.pi, 4 * math.pi)),) if nm in ("CP", "RZZ") else ()
+                gates.append(W.Gate(nm, (a, b), par))
+    return W.Circuit(n, gates, f"diag{n}")
+
+
 CIRCUITS = [
     ("layers8", lambda: W.random_layers(8, 6, np.random.default_rng(81))),
     ("layers15", lambda: W.random_layers(15, 3, np.random.default_rng(82))),   # several passes
@@ -79,6 +105,8 @@ CIRCUITS = [
     ("ghzqft12", lambda: W.config1(n=12, layers=3)),
     # rounds of RZZ on a 3-regular graph and RX (diagonal runs)
     ("qaoa12", lambda: W.config4(n=12, rounds=2)),
+    # long diagonal runs (up to 31 gates, errors at every stage inside them)
+    ("diag12", lambda: _diag_circuit(12, 2, 92)),
 ]
 
 
@@ -172,32 +200,6 @@ def test_plan_autotuner(P, ctx, orc):
     np.testing.assert_array_equal(a.view(np.uint64), b.view(np.uint64))
     assert np.abs(a - want).max() <= 2e-5
     P.nt_circuit_free(h)
-
-
-def _diag_circuit(n, layers, seed):
-    # one-qubit layers, then long stretches of diagonal gates (one- and
-    # two-qubit, phases of every kind) on random qubits: runs whose qubits sit
-    # in the registers, in the tile, and outside it, with one or several
-    # register qubits per run
-    rng = np.random.default_rng(seed)
-    gates = []
-    for _ in range(layers):
-        for q in range(n):
-            if rng.integers(2):
-                gates.append(W.Gate("H", (q,)))
-            else:
-                gates.append(W.Gate("RX", (q,), (float(rng.uniform(0, 2 * math.pi)),)))
-        for _ in range(3 * n):
-            nm = ["RZ", "T", "S", "Z", "CP", "CZ", "RZZ"][int(rng.integers(7))]
-            if nm in ("RZ", "T", "S", "Z"):
-                q = int(rng.integers(n))
-                par = (float(rng.uniform(-4 * math.pi, 4 * math.pi)),) if nm == "RZ" else ()
-                gates.append(W.Gate(nm, (q,), par))
-            else:
-                a, b = (int(x) for x in rng.choice(n, 2, replace=False))
-                par = (float(rng.uniform(-4 * math.pi, 4 * math.pi)),) if nm in ("CP", "RZZ") else ()
-                gates.append(W.Gate(nm, (a, b), par))
-    return W.Circuit(n, gates, f"diag{n}")
 
 
 DIAG_CIRCUITS = [
