@@ -254,6 +254,10 @@ std::vector<HostOp> classify(const Circuit &c) {
       op.m[0] = 0; op.m[1] = 1; op.m[2] = 1; op.m[3] = 0;
       continue;
     }
+    if (hg.kind == NT_SWAP) {
+      op.cls = OPC_SW;
+      continue;
+    }
     op.cls = OPC_G2;
     for (int i = 0; i < 16; ++i) op.m[i] = hg.m[i];
   }
@@ -292,7 +296,7 @@ double gate_flops(const HostGate &g) {
 uint32_t HostOp::need_mask() const {
   switch (cls) {
     case OPC_G1: case OPC_C1: return 1u << qa;
-    case OPC_G2: case OPC_G4: return (1u << qa) | (1u << qb);
+    case OPC_G2: case OPC_G4: case OPC_SW: return (1u << qa) | (1u << qb);
     default: return 0u;
   }
 }

@@ -503,6 +503,19 @@ void Ctx::upload_plan(const Circuit &c, DevPlan &dp) {
           code[o] = ntk::OPK_G4 * 4 + (lo >> 1);
         } else if (h.cls == OPC_NOP) {
           code[o] = ntk::OPK_NOP * 4;
+        } else if (h.cls == OPC_SW) {
+          // register permutation of the bit pair holding qa and qb
+          auto rbit = [&](int q) {
+            auto it = std::find(sg.reg_q.begin(), sg.reg_q.end(), q);
+            if (it == sg.reg_q.end()) throw Error(NT_ERR_UNSUPPORTED, "internal: SWAP outside the registers");
+            return (int)(it - sg.reg_q.begin());
+          };
+          const int ba = rbit(h.qa), bb = rbit(h.qb);
+          const int lo = std::min(ba, bb), hi = std::max(ba, bb);
+          int k = 0;
+          while (k < 6 && !(ntk::D2RR_PAIRS[k][0] == lo && ntk::D2RR_PAIRS[k][1] == hi)) ++k;
+          if (k == 6 || lo == hi) throw Error(NT_ERR_UNSUPPORTED, "internal: register-bit pair out of range");
+          code[o] = ntk::OPK_SW * 4 + k;
         } else if (h.cls == OPC_DF) {
           if ((o - sg.op_begin) & 1) throw Error(NT_ERR_UNSUPPORTED, "internal: diagonal run at an odd segment offset");
           code[o] = ntk::OPK_DF * 4;

@@ -458,6 +458,26 @@ DEV void diag2(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R], cx<T> p0, cx<T> p1,
   }
 }
 
+// Register permutation of a SWAP on register bits A and B: slot r takes the
+// slot with those two bits exchanged.
+template <int A, int B, int R, typename T>
+DEV void swap_perm(const cx<T> (&v)[1 << R], cx<T> (&w)[1 << R]) {
+#pragma unroll
+  for (int r = 0; r < (1 << R); ++r) {
+    const int ba = (r >> A) & 1, bb = (r >> B) & 1;
+    w[r] = v[ba == bb ? r : (r ^ (1 << A) ^ (1 << B))];
+  }
+}
+
+// Frame after a SWAP of qubits a and b: the X and Z bits of the two qubits
+// trade places (the phase is unchanged).
+DEV void swap_frame(uint32_t a, uint32_t b, uint32_t &fx, uint32_t &fz) {
+  const uint32_t m = (1u << a) | (1u << b);
+  const uint32_t dx = ((fx >> a) ^ (fx >> b)) & 1u, dz = ((fz >> a) ^ (fz >> b)) & 1u;
+  fx = __builtin_amdgcn_readfirstlane(fx ^ (dx ? m : 0u));
+  fz = __builtin_amdgcn_readfirstlane(fz ^ (dz ? m : 0u));
+}
+
 // Frame update of a CNOT (control qc, target qt).  Conjugated by the frame,
 // the CNOT becomes (+-Z_c)^{z_t} CX_cv: the frame's X on the control sets the
 // control value cv, its Z on the target turns X into -X = (+-Z_c) X (sign +
@@ -719,6 +739,28 @@ DEV void apply_reg_op(const OpLite<T, NM> &op, const cx<T> *aux, cx<T> (&v)[1 <<
   // Diagonal on two register qubits (qa on the lower register bit, the host
   // orders them): the phase of slot group (b_qa, b_qb) is D[(b_qa, b_qb) ^
   // (x_qa, x_qb)] under the frame.
+  // SWAP of two register qubits: the slots trade along the bit pair, and
+  // SWAP F SWAP^dag is F with the two qubits' frame bits exchanged
+  const uint32_t swk = (uint32_t)(code - OPK_SW * 4);
+  if (swk < 6u) {
+    switch (swk) {
+#define NT_SW(k)                                                                \
+  case k:                                                                       \
+    if constexpr (D2RR_PAIRS[k][1] < R) swap_perm<D2RR_PAIRS[k][0], D2RR_PAIRS[k][1], R>(v, w); \
+    break;
+      NT_SW(0)
+      NT_SW(1)
+      NT_SW(2)
+      NT_SW(3)
+      NT_SW(4)
+      default:
+        if constexpr (D2RR_PAIRS[5][1] < R) swap_perm<D2RR_PAIRS[5][0], D2RR_PAIRS[5][1], R>(v, w);
+        break;
+#undef NT_SW
+    }
+    swap_frame(qa, qc, fx, fz);
+    return;
+  }
   const uint32_t d2k = (uint32_t)(code - OPK_D2RR * 4);
   if (d2k < 6u) {
     cx<T> e0, e1, e2, e3;

@@ -59,6 +59,9 @@ enum : int32_t {
   // Fused run of diagonal gates: rsel = byte offset / 16 of its first record
   // (DfRec) in the aux table | (gates << 24).
   OPK_DF = 14,
+  // SWAP of two register qubits: code OPK_SW * 4 + k, the pair
+  // D2RR_PAIRS[k] of register bits (codes up to OPK_SW * 4 + 5)
+  OPK_SW = 15,
 };
 
 // One gate of a fused diagonal run.  kind 0 (no qubit in the registers):

@@ -42,6 +42,9 @@ enum OpClass : int32_t {
   // one qubit in the segment's registers: one multiply per amplitude by the
   // product of their phases.
   OPC_DF = 7,
+  // SWAP with both qubits in the registers: a register permutation, the
+  // frame's bits on the two qubits trade places.
+  OPC_SW = 8,
 };
 
 struct HostGate {

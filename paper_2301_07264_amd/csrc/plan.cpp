@@ -207,7 +207,7 @@ double op_cost(const HostOp &h) {
       break;
     }
     case OPC_D1: case OPC_D2: v = 64.0 * CYC; break;
-    case OPC_C1: v = 32.0 * CYC; break;
+    case OPC_C1: case OPC_SW: v = 32.0 * CYC; break;
     case OPC_G2: v = 256.0 * CYC + 2.0 * FLOOR; break;   // and an LDS round trip of its own
     case OPC_G4: v = 288.0 * CYC; break;                 // 256 FMA, 32 moves of matrix entries
     default: break;
