@@ -44,13 +44,13 @@ ALU_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}
 MEASURED_TRAFFIC = {
     ("ghz_qft_layers24", "c64", 32): {
         "bytes_per_launch": 8.416e9,
-        "passes": 43, "tile_qubits": 12, "ops": 985,
-        "kernel_sha256": "267f9a3b132e2aabfb6ea0dc0925d619f87170cc4005ebd91cd2f2b862dc8c70",
+        "passes": 43, "tile_qubits": 12, "ops": 984,
+        "kernel_sha256": "d7599aafc5bb43ac2b1988e2afac374ac82b459e27aedb9bdcee73b4c5efcf18",
     },
     ("qaoa3reg30", "c64", 4): {
         "bytes_per_launch": 6.560e10,
         "passes": 11, "tile_qubits": 12, "ops": 261,
-        "kernel_sha256": "267f9a3b132e2aabfb6ea0dc0925d619f87170cc4005ebd91cd2f2b862dc8c70",
+        "kernel_sha256": "d7599aafc5bb43ac2b1988e2afac374ac82b459e27aedb9bdcee73b4c5efcf18",
     },
 }
 
