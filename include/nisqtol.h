@@ -156,7 +156,9 @@ nt_status nt_circuit_set_tile(nt_circuit *c, int prec, int tile_qubits);
 
 /* Gate fusion of the circuit's plan at precision `prec`: 0 = automatic
  * (currently 2), 1 = none (one op per gate), 2 = two-qubit blocks and
- * diagonal runs, 3 = two-qubit blocks only, 4 = diagonal runs only.  Within
+ * diagonal runs, 3 = two-qubit blocks only, 4 = diagonal runs only; at
+ * complex64 the widths with blocks also join four RX-type one-qubit gates,
+ * one on each register qubit, into one op.  Within
  * a pass, a two-qubit gate takes the runs of
  * one-qubit gates right before it on its qubits (not already taken) and,
  * when it took any, the runs right after it, and the block is applied as one
@@ -206,8 +208,8 @@ nt_status nt_plan_export(const nt_circuit *c, int prec, int32_t *op_gate, int32_
 
 /* Host-only: ops the plan runs per trajectory (a fused op counts once;
  * no-op pads that keep fused ops at even positions of their segments
- * included) and the number of fused ops (two-qubit blocks and diagonal
- * runs). */
+ * included) and the number of fused ops (two-qubit blocks, diagonal runs
+ * and one-qubit layers). */
 nt_status nt_plan_ops(const nt_circuit *c, int prec, int64_t *n_ops, int64_t *n_fused);
 
 /* ---- success criterion (Sec. II, Sec. V) ----------------------------------- */

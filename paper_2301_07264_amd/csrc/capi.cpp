@@ -261,7 +261,7 @@ nt_status nt_plan_ops(const nt_circuit *c, int prec, int64_t *n_ops, int64_t *n_
   return guard([&] {
     nt::Plan P = nt::choose_plan(*c->impl, prec);
     if (n_ops) *n_ops = (int64_t)P.ops.size();
-    if (n_fused) *n_fused = P.n_fused + P.n_diag;
+    if (n_fused) *n_fused = P.n_fused + P.n_diag + P.n_layer;
   });
 }
 

@@ -375,6 +375,14 @@ static void upload_ops(const Circuit &c, DevPlan &dp, const std::vector<int32_t>
       d.m[2 * i] = (T)h.m[i].real();
       d.m[2 * i + 1] = (T)h.m[i].imag();
     }
+    if (h.cls == OPC_L4) {
+      // c and Im m01 of each RX-type gate, register bit 0 first
+      for (int b = 0; b < 4; ++b) {
+        d.m[2 * b] = (T)h.m[4 * b].real();
+        d.m[2 * b + 1] = (T)h.m[4 * b + 1].imag();
+      }
+      continue;
+    }
     if (h.cls == OPC_G4) {
       // matrix sets are addressed in units of 256 entries
       while (aux.size() % 256) aux.push_back(ntk::cx<T>{0, 0});
@@ -503,6 +511,17 @@ void Ctx::upload_plan(const Circuit &c, DevPlan &dp) {
           code[o] = ntk::OPK_G4 * 4 + (lo >> 1);
         } else if (h.cls == OPC_NOP) {
           code[o] = ntk::OPK_NOP * 4;
+        } else if (h.cls == OPC_L4) {
+          if ((o - sg.op_begin) & 1) throw Error(NT_ERR_UNSUPPORTED, "internal: one-qubit layer at an odd segment offset");
+          if (pr != NT_C64 || R != 4) throw Error(NT_ERR_UNSUPPORTED, "internal: one-qubit layer outside a complex64 plan");
+          uint32_t qw = 0;
+          for (int b = 0; b < 4; ++b) {
+            const HostGate &hg = c.gates[(size_t)h.sub[(size_t)b]];
+            if (hg.q[0] != sg.reg_q[(size_t)b]) throw Error(NT_ERR_UNSUPPORTED, "internal: one-qubit layer off its register bits");
+            qw |= (uint32_t)hg.q[0] << (8 * b);
+          }
+          rsel[o] = (int32_t)qw;
+          code[o] = ntk::OPK_L4 * 4;
         } else if (h.cls == OPC_SW) {
           // register permutation of the bit pair holding qa and qb
           auto rbit = [&](int q) {
@@ -707,7 +726,7 @@ void Ctx::timing_flush() {
 
 // Gate-kernel instance a plan needs (the fused ops it holds).
 static int plan_features(const Plan &P) {
-  return (P.n_fused > 0 ? ntk::FEAT_G4 : 0) | (P.n_diag > 0 ? ntk::FEAT_DF : 0);
+  return (P.n_fused > 0 ? ntk::FEAT_G4 : 0) | (P.n_diag > 0 ? ntk::FEAT_DF : 0) | (P.n_layer > 0 ? ntk::FEAT_L4 : 0);
 }
 
 // One launch of every pass of the plan over a batch.  With `start`, batch

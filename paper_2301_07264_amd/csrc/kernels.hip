@@ -574,6 +574,24 @@ DEV void apply_reg_op(const OpLite<T, NM> &op, const cx<T> *aux, cx<T> (&v)[1 <<
       }
       return;
     }
+    if constexpr ((FEAT & FEAT_L4) && SLOT == 1 && R == 4 && sizeof(T) == 4) {
+      if (code == OPK_L4 * 4) {
+        // four RX-type gates, one per register bit; a Z of the frame on a
+        // gate's qubit flips its w, an X leaves it (the gates act on
+        // different qubits, so the frame is the op's own for all four)
+        const uint32_t qw = (uint32_t)op.rsel;
+        auto wz = [&](int i) {
+          const T w0 = op.m[2 * i + 1];
+          return ((fz >> ((qw >> (8 * i)) & 255u)) & 1u) ? -w0 : w0;
+        };
+        cx<T> t[1 << R], u[1 << R];
+        g1x_apply<0, R>(v, t, vpin(op.m[0]), vpin(wz(0)));
+        g1x_apply<1, R>(t, u, vpin(op.m[2]), vpin(wz(1)));
+        g1x_apply<2, R>(u, t, vpin(op.m[4]), vpin(wz(2)));
+        g1x_apply<3, R>(t, w, vpin(op.m[6]), vpin(wz(3)));
+        return;
+      }
+    }
     if ((FEAT & FEAT_DF) && SLOT == 1 && code == OPK_DF * 4) {
       // Run of diagonal gates: each gate's phase is taken under the frame as
       // the errors before it left it (F^dag D F = D(j ^ x)), per lane for
@@ -1270,8 +1288,19 @@ hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, int feat, hipS
     case FEAT_G4: return launch_pass_k<T, FEAT_G4>(a, R, nthreads, s);
     case FEAT_DF: return launch_pass_k<T, FEAT_DF>(a, R, nthreads, s);
     case FEAT_G4 | FEAT_DF: return launch_pass_k<T, FEAT_G4 | FEAT_DF>(a, R, nthreads, s);
-    default: return hipErrorInvalidValue;
+    default: break;
   }
+  // one-qubit layers: complex64 plans only
+  if constexpr (sizeof(T) == 4) {
+    switch (feat) {
+      case FEAT_L4: return launch_pass_k<T, FEAT_L4>(a, R, nthreads, s);
+      case FEAT_L4 | FEAT_G4: return launch_pass_k<T, FEAT_L4 | FEAT_G4>(a, R, nthreads, s);
+      case FEAT_L4 | FEAT_DF: return launch_pass_k<T, FEAT_L4 | FEAT_DF>(a, R, nthreads, s);
+      case FEAT_L4 | FEAT_G4 | FEAT_DF: return launch_pass_k<T, FEAT_L4 | FEAT_G4 | FEAT_DF>(a, R, nthreads, s);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 template hipError_t launch_pass<float>(const PassArgs<float> &, int, int, int, hipStream_t);

@@ -62,6 +62,10 @@ enum : int32_t {
   // SWAP of two register qubits: code OPK_SW * 4 + k, the pair
   // D2RR_PAIRS[k] of register bits (codes up to OPK_SW * 4 + 5)
   OPK_SW = 15,
+  // Four RX-type one-qubit gates, one per register bit (complex64, R = 4):
+  // m[2i] = c, m[2i + 1] = Im m01 of the gate on register bit i, rsel = the
+  // four qubits (8 bits each, bit 0 first).  Code OPK_L4 * 4.
+  OPK_L4 = 17,
 };
 
 // One gate of a fused diagonal run.  kind 0 (no qubit in the registers):
@@ -255,7 +259,7 @@ hipError_t launch_zero_words(uint32_t *p, uint64_t n, hipStream_t s);
 // Launch wrappers (kernels.hip).
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
 // Fused ops a plan holds; the gate kernel has an instance per combination.
-enum : int { FEAT_G4 = 1, FEAT_DF = 2 };
+enum : int { FEAT_G4 = 1, FEAT_DF = 2, FEAT_L4 = 4 };
 template <typename T>
 hipError_t launch_pass(const PassArgs<T> &a, int R, int nthreads, int feat, hipStream_t s);
 // nref: reference norm (end == NULL) or per-pass reference norms indexed by

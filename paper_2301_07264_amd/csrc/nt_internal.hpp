@@ -45,6 +45,10 @@ enum OpClass : int32_t {
   // SWAP with both qubits in the registers: a register permutation, the
   // frame's bits on the two qubits trade places.
   OPC_SW = 8,
+  // Four one-qubit gates of RX type, one on each register qubit
+  // (HostOp::sub in register-bit order, m: their 2x2s), applied in one op
+  // (complex64, four register qubits).
+  OPC_L4 = 9,
 };
 
 struct HostGate {
@@ -115,6 +119,7 @@ struct Plan {
   std::vector<int> op_of_gate;          // gate -> application position
   int n_fused = 0;                      // fused blocks
   int n_diag = 0;                       // fused diagonal runs
+  int n_layer = 0;                      // fused one-qubit layers (OPC_L4)
 };
 
 struct Circuit {
@@ -141,8 +146,9 @@ double gate_flops(const HostGate &g);   // algorithmic flops per amplitude
 // plan.cpp
 // 4x4 matrix (local index b_qa + 2 b_qb) of gate g, which acts within {qa, qb}.
 void embed_gate(const HostGate &g, int qa, int qb, cd *e);
-// Fusion of a plan: two-qubit blocks, diagonal runs (bit set).
-enum : int { FUSE_BLOCKS = 1, FUSE_DIAG = 2 };
+// Fusion of a plan: two-qubit blocks, diagonal runs, one-qubit layers (bit
+// set; layers at complex64 only).
+enum : int { FUSE_BLOCKS = 1, FUSE_DIAG = 2, FUSE_LAYERS = 4 };
 int fusion_mode(int width);   // nt_circuit_set_fusion width -> FUSE_* bits
 Plan make_plan(const Circuit &c, int max_tile_qubits, int max_reg, int cfix, int fuse = FUSE_BLOCKS | FUSE_DIAG);
 void plan_for_precision(const Circuit &c, int prec, int *L, int *R, int *cfix);

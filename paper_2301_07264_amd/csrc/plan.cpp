@@ -380,6 +380,83 @@ std::vector<int> fuse_diagonals(const Circuit &c, std::vector<HostOp> &pu, const
   return out;
 }
 
+// Shape of a one-qubit gate's body in the gate kernel: general, real, or
+// [[c, -i s], [-i s, c]].
+int g1_shape(const HostOp &h) {
+  auto real = [](cd v) { return v.imag() == 0.0; };
+  auto imag = [](cd v) { return v.real() == 0.0; };
+  if (real(h.m[0]) && real(h.m[1]) && real(h.m[2]) && real(h.m[3])) return 1;
+  if (h.m[0] == h.m[3] && real(h.m[0]) && h.m[1] == h.m[2] && imag(h.m[1])) return 2;
+  return 0;
+}
+
+// One-qubit layers.  In a segment with four register qubits, one-qubit ops
+// of RX type ([[c, -i s], [-i s, c]]) on all four register qubits become
+// one op when the later ones can move back to the first past everything in
+// between (ops on other qubits).  The four gates act on different qubits, so their order is free
+// and an error after any of them commutes with the others: the errors all
+// act after the op.
+std::vector<int> fuse_layers(const Circuit &c, std::vector<HostOp> &pu, const std::vector<int> &sched,
+                             const std::vector<int> &reg_q, int *n_layer) {
+  if (reg_q.size() != 4) return sched;
+  auto rbit = [&](int q) {
+    for (int b = 0; b < 4; ++b)
+      if (reg_q[(size_t)b] == q) return b;
+    return -1;
+  };
+  const size_t L = sched.size();
+  std::vector<char> used(L, 0);
+  std::vector<int> out;
+  for (size_t i = 0; i < L; ++i) {
+    if (used[i]) continue;
+    const HostOp &h = pu[(size_t)sched[i]];
+    if (h.cls != OPC_G1 || rbit(h.qa) < 0) {
+      out.push_back(sched[i]);
+      continue;
+    }
+    const int shape = g1_shape(h);
+    if (shape != 2) {
+      out.push_back(sched[i]);
+      continue;
+    }
+    std::vector<size_t> grp = {i};
+    int have = 1 << rbit(h.qa);
+    for (size_t j = i + 1; j < L && grp.size() < 4; ++j) {
+      if (used[j]) continue;
+      const HostOp &g = pu[(size_t)sched[j]];
+      const int b = g.cls == OPC_G1 ? rbit(g.qa) : -1;
+      if (b < 0 || (have >> b) & 1 || g1_shape(g) != shape) continue;
+      bool ok = true;
+      for (size_t k = i + 1; k < j && ok; ++k)
+        if (!used[k] && std::find(grp.begin(), grp.end(), k) == grp.end()) ok = commute(c, g, pu[(size_t)sched[k]]);
+      if (!ok) continue;
+      grp.push_back(j);
+      have |= 1 << b;
+    }
+    if (grp.size() < 4) {
+      out.push_back(sched[i]);
+      continue;
+    }
+    HostOp l;
+    l.cls = OPC_L4;
+    l.qa = reg_q[0];
+    l.qb = -1;
+    l.gate = h.gate;
+    l.sub.assign(4, -1);
+    for (size_t k : grp) {
+      const HostOp &g = pu[(size_t)sched[k]];
+      const int b = rbit(g.qa);
+      l.sub[(size_t)b] = g.gate;
+      for (int e = 0; e < 4; ++e) l.m[4 * b + e] = g.m[e];
+      used[k] = 1;
+    }
+    pu.push_back(l);
+    out.push_back((int)pu.size() - 1);
+    ++*n_layer;
+  }
+  return out;
+}
+
 }  // namespace
 
 int fusion_mode(int width) {
@@ -419,7 +496,10 @@ Plan choose_plan(const Circuit &c, int prec) {
   int L, R, cfix;
   plan_for_precision(c, prec, &L, &R, &cfix);
   const int ov = c.tile_override[prec == NT_C64 ? 1 : 2];
-  const int fuse = fusion_mode(c.fuse_width[prec == NT_C64 ? 1 : 2]);
+  int fuse = fusion_mode(c.fuse_width[prec == NT_C64 ? 1 : 2]);
+  // one-qubit layers go with the blocks, at complex64 (their descriptor
+  // points at single-precision matrices)
+  if (prec == NT_C64 && (fuse & FUSE_BLOCKS)) fuse |= FUSE_LAYERS;
   if (ov > 0) {
     const int Lo = std::min(ov, L);
     const int Ro = std::max(2, std::min(4, Lo - 6));
@@ -531,6 +611,7 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix, int fuse) {
           sg.reg_q.push_back(q);
       if ((int)sg.reg_q.size() != R) throw Error(NT_ERR_UNSUPPORTED, "internal: register set size");
       if (fuse & FUSE_DIAG) sched = fuse_diagonals(c, pu, sched, sg.reg_q, &P.n_diag);
+      if (fuse & FUSE_LAYERS) sched = fuse_layers(c, pu, sched, sg.reg_q, &P.n_layer);
       // Offsets in the segment: the gate kernel applies ops in pairs and
       // holds the block body for register bits (0, 1) and the diagonal-run
       // body in the first slot of a pair, the block body for bits (2, 3) in
@@ -540,6 +621,7 @@ Plan make_plan(const Circuit &c, int L, int R, int cfix, int fuse) {
       auto align = [&](const std::vector<int> &rq) {
         auto parity = [&](int i) -> int {
           if (pu[i].cls == OPC_DF) return 0;
+          if (pu[i].cls == OPC_L4) return 0;
           if (pu[i].cls != OPC_G4) return -1;
           return (int)(std::find(rq.begin(), rq.end(), pu[i].qa) - rq.begin()) / 2;
         };
