@@ -156,7 +156,7 @@ def _check_plan(P, c, prec):
         need = _needs(c.gates[g])
         pm = int(ex["pass_local_mask"][ex["op_pass"][o]])
         sm = int(ex["segment_reg_mask"][ex["op_segment"][o]])
-        dense2 = c.gates[g].name in ("SWAP", "U2Q")       # applied in LDS, not registers
+        dense2 = c.gates[g].name == "U2Q"                 # applied in LDS, not registers
         for q in need:
             assert (pm >> q) & 1
             assert dense2 or (sm >> q) & 1
@@ -173,6 +173,34 @@ def test_plan_invariants(P, which):
         npass, _ = _check_plan(P, c, prec)
         if c.n <= 12:
             assert npass == 1
+
+
+@pytest.mark.parametrize("width", [1, 2, 3, 4])
+def test_plan_invariants_every_fusion_width(P, width):
+    """Every fusion width (blocks, diagonal runs, one-qubit layers, none)
+    keeps each gate once, the order of the gates on every qubit, and the
+    locality and register needs of every gate."""
+    for c in (W.config1(n=15, layers=4), W.config4(n=16, rounds=2), W.config1(n=13, layers=2)):
+        for prec in (P.NT_C64, P.NT_C128):
+            h = P.nt_circuit_load(None, c)
+            P.nt_circuit_set_fusion(h, prec, width)
+            n_ops, n_fused = P.nt_plan_ops(h, prec)
+            if width == 1:
+                assert n_fused == 0 and n_ops == c.G
+            npass, nseg, L = P.nt_plan_info(h, prec)
+            ex = P.nt_plan_export(h, prec)
+            og = ex["op_gate"].tolist()
+            assert sorted(og) == list(range(c.G))
+            last = {}
+            for o, g in enumerate(og):
+                for q in c.gates[g].qubits:
+                    assert last.get(q, -1) < g
+                    last[q] = g
+                pm = int(ex["pass_local_mask"][ex["op_pass"][o]])
+                sm = int(ex["segment_reg_mask"][ex["op_segment"][o]])
+                for q in _needs(c.gates[g]):
+                    assert (pm >> q) & 1 and (sm >> q) & 1
+            P.nt_circuit_free(h)
 
 
 def test_plan_order_is_same_unitary(P, orc):
