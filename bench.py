@@ -45,12 +45,12 @@ MEASURED_TRAFFIC = {
     ("ghz_qft_layers24", "c64", 32): {
         "bytes_per_launch": 8.416e9,
         "passes": 43, "tile_qubits": 12, "ops": 984,
-        "kernel_sha256": "d7599aafc5bb43ac2b1988e2afac374ac82b459e27aedb9bdcee73b4c5efcf18",
+        "kernel_sha256": "1b7fccad597628a0698696c8efcee173ef29e1ce4d28f31bc485044d7e684b7e",
     },
     ("qaoa3reg30", "c64", 4): {
         "bytes_per_launch": 6.560e10,
-        "passes": 11, "tile_qubits": 12, "ops": 261,
-        "kernel_sha256": "d7599aafc5bb43ac2b1988e2afac374ac82b459e27aedb9bdcee73b4c5efcf18",
+        "passes": 11, "tile_qubits": 12, "ops": 216,
+        "kernel_sha256": "1b7fccad597628a0698696c8efcee173ef29e1ce4d28f31bc485044d7e684b7e",
     },
 }
 
