@@ -107,3 +107,30 @@ def test_config1_fidelities_all_rates(P, gold):
     finally:
         P.nt_circuit_free(h)
         P.nt_destroy(ctx)
+
+
+@pytest.mark.parametrize("width", [1, 3, 4])
+def test_config1_fidelities_other_fusion_widths(P, gold, width):
+    """The same 208 stored values in complex64 under the other fusion widths
+    (none; blocks and layers only; diagonal runs only): every fused-op path
+    at the headline size, errors inside fused ops included."""
+    c = W.config1()
+    ctx = P.nt_create(0)
+    h = P.nt_circuit_load(ctx, c)
+    try:
+        P.nt_set_precision(ctx, P.NT_C64)
+        P.nt_circuit_set_fusion(h, P.NT_C64, width)
+        n = gold["n_state_traj"]
+        worst = 0.0
+        for rec in gold["rates"]:
+            p = rec["p"]
+            P.nt_set_error_model(ctx, p / 3, p / 3, p / 3)
+            f = np.zeros(n)
+            P.nt_run(ctx, h, 0, 0, n, TAU, f)
+            d = np.abs(f - np.asarray(rec["F"]))
+            worst = max(worst, float(d.max()))
+            assert d.max() <= 2e-5, (width, rec["j"], float(d.max()))
+        _say(f"config1 fidelities c64, fusion width {width}: max |F - F_oracle| = {worst:.2e}")
+    finally:
+        P.nt_circuit_free(h)
+        P.nt_destroy(ctx)
