@@ -265,7 +265,9 @@ std::vector<HostOp> fuse_blocks(const Circuit &c, const std::vector<HostOp> &ops
         post.push_back(j);
       }
     }
-    if (pre.empty() || (int)pre.size() + 1 > MAX_BLOCK_GATES) continue;
+    // a dense two-qubit gate forms a block even alone: as a block it runs
+    // on two register qubits instead of an LDS pass of its own
+    if ((pre.empty() && op.cls != OPC_G2) || (int)pre.size() + 1 > MAX_BLOCK_GATES) continue;
     std::vector<int> mem = pre;
     mem.push_back(k);
     // the runs after the gate only when the block still has room for them
