@@ -107,6 +107,9 @@ CIRCUITS = [
     ("qaoa12", lambda: W.config4(n=12, rounds=2)),
     # long diagonal runs (up to 31 gates, errors at every stage inside them)
     ("diag12", lambda: _diag_circuit(12, 2, 92)),
+    # Haar-random two-qubit gates, each a block of its own on two register
+    # qubits (errors before a block pick its frame variant)
+    ("qv10", lambda: W.quantum_volume(10, 6, np.random.default_rng(93))),
 ]
 
 
