@@ -55,6 +55,33 @@ MEASURED_TRAFFIC = {
 }
 
 
+_COPY_GBS = None
+
+
+def device_copy_gbs(nbytes: int = 4 << 30) -> float:
+    """Practical HBM rate of this machine: a device-to-device copy of nbytes
+    (read + write bytes over the best of five, HIP events), measured once per
+    process after the timed region."""
+    global _COPY_GBS
+    if _COPY_GBS is None:
+        import torch
+        x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = float("inf")
+        for _ in range(5):
+            e0.record()
+            y.copy_(x)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        del x, y
+        torch.cuda.empty_cache()
+        _COPY_GBS = 2.0 * nbytes / (best / 1e3) / 1e9
+    return _COPY_GBS
+
+
 def kernel_sha256():
     import hashlib
     path = os.path.join(ROOT, "paper_2301_07264_amd", "csrc", "kernels.hip")
@@ -346,8 +373,10 @@ def bench_single(args, P, W, workload, sub):
     hbm_frac = achieved / HBM_PEAK_GBS
     alu_peak = ALU_PEAK_TFLOPS[args.prec]
     alu_frac = achieved_tf / alu_peak
+    copy_gbs = device_copy_gbs()
     hbm_view = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": hbm_frac, "traffic": traffic}
+                "frac": hbm_frac, "traffic": traffic,
+                "device_copy_GBps": copy_gbs, "frac_of_device_copy": achieved / copy_gbs}
     alu_view = {"bound": "alu", "achieved": achieved_tf, "peak": alu_peak, "unit": "TFLOP/s",
                 "frac": alu_frac, "traffic": traffic}
     # the binding roofline is the one the kernel is closest to
@@ -556,8 +585,10 @@ def bench_batch(args, P, W, sub=False):
     alu_peak = ALU_PEAK_TFLOPS[args.prec]
     alu_view = {"bound": "alu", "achieved": achieved_tf, "peak": alu_peak, "unit": "TFLOP/s",
                 "frac": achieved_tf / alu_peak, "traffic": None}
+    copy_gbs = device_copy_gbs()
     hbm_view = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None}
+                "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                "device_copy_GBps": copy_gbs, "frac_of_device_copy": achieved_gbs / copy_gbs}
     roofline = dict(alu_view if alu_view["frac"] >= hbm_view["frac"] else hbm_view)
     roofline.update({"kernel": "k_pass (all launch shapes, time-weighted)", "launches": launches,
                      "avg_launch_ms": pass_ms / max(launches, 1),
