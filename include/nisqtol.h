@@ -164,7 +164,7 @@ nt_status nt_circuit_set_tile(nt_circuit *c, int prec, int tile_qubits);
  * when it took any, the runs right after it, and the block is applied as one
  * dense 4x4 (both qubits then sit in registers) when a cost model prices it
  * below its gates; a dense two-qubit gate (U2Q) forms such a block even
- * alone, and a SWAP of two register qubits is a register permutation.  Within a register segment, runs of at least three
+ * alone (at every width a SWAP is a permutation of two register qubits).  Within a register segment, runs of at least three
  * diagonal gates (each with at most one qubit in the registers) multiply
  * every amplitude once by the product of their phases.  An error inside a
  * block or run still acts right after its gate (Sec. IV-B): a trajectory
